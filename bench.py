@@ -1,0 +1,184 @@
+#!/usr/bin/env python3
+"""Throughput of batched offline RMQ on one MI355X.
+
+Workload (the paper's scale, Section 4): A = 1e8 int32 values uniform in
+[0, 2^31); query batches of q in {1e3, 1e4, 1e5, 1e6, 1e7} with both
+endpoints uniform over [0, n) and swapped so l <= r.  A step answers every
+batch of the sweep with both methods -- the block Sparse Table over A
+(Section 3.2) and the contracted one (Section 3.1) -- through the C ABI,
+each call doing the whole offline job (build + answers).  Inputs are resident
+in HBM before timing starts.
+
+value  = queries answered per second over the timed steps (all batches, both
+         methods), timed with events on the stream the library runs on.
+roofline = the full-array block-minima pass (the dominant kernel of the
+         plain method): algorithmic bytes 4n + 8 ceil(n/k) over its average
+         duration, measured with the library's per-stage events.
+cpu_baseline = the CPU oracle (Sparse Table over 32-element blocks, build +
+         answers for every batch of the sweep) on this host's cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = ("queries/s and HBM GB/s (% of peak) at n=1e8, q=1e3..1e7; "
+          "p50/p99 latency served")
+HBM_PEAK_GBS = 8000.0
+
+
+def parse_qs(s: str):
+    return [int(float(x)) for x in s.split(",") if x]
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=10 ** 8)
+    ap.add_argument("--qs", default="1e3,1e4,1e5,1e6,1e7")
+    ap.add_argument("--paths", default="full,contracted")
+    ap.add_argument("--k-full", type=int, default=0, help="0 = planner's choice")
+    ap.add_argument("--k-con", type=int, default=512)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--verify", action="store_true",
+                    help="check every answer of the first step against the oracle")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}, world size {world}); "
+              "the multi-GPU form of this method is a design note only", file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_1706_06940_amd as rmq
+    import workloads as W
+
+    d = torch.device("cuda:0")
+    n = args.n
+    qs = parse_qs(args.qs)
+    paths = [p for p in args.paths.split(",") if p]
+    seed = W.BASE_SEED + 1
+    t0 = time.time()
+    A_h = W.uniform_int31(n, seed)
+    batches_h = [W.uniform_queries(n, q, seed, 100 + 2 * j) for j, q in enumerate(qs)]
+    print(f"[bench] generated n={n} and {len(qs)} batches in {time.time() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    A = torch.from_numpy(A_h).to(d)
+    batches = [(torch.from_numpy(L).to(d), torch.from_numpy(R).to(d)) for L, R in batches_h]
+    outs = [torch.empty(q, dtype=torch.int32, device=d) for q in qs]
+    k_full = args.k_full or rmq.plan(n, max(qs))[0]
+    ks = {"full": k_full, "contracted": args.k_con}
+    torch.cuda.synchronize()
+
+    def step(timers=None):
+        for p in paths:
+            for j, q in enumerate(qs):
+                L, R = batches[j]
+                rmq.query_batch(A, L, R, path=p, block_size=ks[p], out=outs[j],
+                                timer=timers[(p, j)] if timers else None)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    if args.verify:
+        import oracle
+
+        orc = oracle.Oracle()
+        for p in paths:
+            for j, q in enumerate(qs):
+                L, R = batches[j]
+                got = rmq.query_batch(A, L, R, path=p, block_size=ks[p]).cpu().numpy()
+                exp = orc.rmq_sparse_table(A_h, batches_h[j][0], batches_h[j][1], 32)
+                if not np.array_equal(got, exp):
+                    print(f"[bench] MISMATCH path={p} q={q}", file=sys.stderr, flush=True)
+                    return 1
+        print("[bench] verified all batches against the oracle", file=sys.stderr, flush=True)
+
+    # ---- timed region ----
+    timers = [{(p, j): rmq.Timer() for p in paths for j in range(len(qs))}
+              for _ in range(args.steps)]
+    stream = torch.cuda.current_stream(d)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for s in range(args.steps):
+        step(timers[s])
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = ev0.elapsed_time(ev1)
+    ms_per_step = total_ms / args.steps
+    answered = sum(qs) * len(paths)
+    value = answered / (ms_per_step / 1e3)
+
+    # per-call and per-stage figures from the library's stage events
+    breakdown = {}
+    blockmin_ms = []
+    for p in paths:
+        for j, q in enumerate(qs):
+            per = [timers[s][(p, j)].read() for s in range(args.steps)]
+            tot = statistics.median(t for _, t in per)
+            stages = [statistics.median(st[i] for st, _ in per) for i in range(4)]
+            breakdown[f"{p}/q={q}"] = {
+                "ms": round(tot, 4), "queries_per_s": round(q / (tot / 1e3), 1),
+                "stage_ms": {name: round(v, 4) for name, v in zip(rmq.STAGE_NAMES, stages)}}
+            if p == "full":
+                blockmin_ms += [st[1] for st, _ in per]
+    roofline = None
+    if blockmin_ms:
+        avg = sum(blockmin_ms) / len(blockmin_ms)
+        nb = -(-n // k_full)
+        algo_bytes = 4 * n + 8 * nb
+        achieved = algo_bytes / (avg / 1e3) / 1e9
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "kernel": "k_blockmin_i32", "avg_ms": round(avg, 5),
+                    "algorithmic_bytes": algo_bytes}
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+
+        orc = oracle.Oracle()
+        t = time.perf_counter()
+        for j, q in enumerate(qs):
+            orc.rmq_sparse_table(A_h, batches_h[j][0], batches_h[j][1], 32)
+        dt = time.perf_counter() - t
+        cpu = {"value": round(sum(qs) / dt, 1), "unit": "queries/s",
+               "cores": orc.num_threads(), "kind": "oracle",
+               "sample": (f"oracle Sparse Table over 32-element blocks, build + answers for "
+                          f"each batch of the sweep q={qs} on the same n={n} array "
+                          f"({dt:.2f}s on the host)")}
+
+    line = {
+        "metric": METRIC, "value": round(value, 1), "unit": "queries/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": (f"batched RMQ, n={n} int32 uniform in [0,2^31), batches "
+                                f"q={qs} uniform swapped queries, each answered by "
+                                f"{' and '.join(paths)} method(s)"),
+                   "n": n, "q": qs, "paths": paths, "block_size": ks,
+                   "parallelism": "single GPU"},
+        "roofline": roofline, "cpu_baseline": cpu, "breakdown": breakdown,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

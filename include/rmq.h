@@ -1,0 +1,220 @@
+/*
+ * rmq.h -- C ABI of an MI355X (gfx950) library for batched, offline range
+ * minimum queries, after Grabowski & Kowalski, "Faster batched range minimum
+ * queries" (arXiv 1706.06940).
+ *
+ * Problem (Section 1, definition of RMQ; Section 1, offline setting): given
+ * an int32 array A[0..n-1] and a batch of q queries [L[i], R[i]] known
+ * beforehand, return for each query the position of the minimum of
+ * A[L[i]..R[i]].  This library fixes the tie-break the paper leaves open:
+ * the LEFTMOST position holding the minimum value.  Positions are 0-based and
+ * ranges inclusive (the paper is 1-based).
+ *
+ * Two methods compute the same answers:
+ *   RMQ_PATH_FULL        Section 3.2 (BbST, no contraction): block minima over
+ *                        all of A, a Sparse Table over the blocks, and each
+ *                        query from two overlapping power-of-two block spans
+ *                        plus speculative reads of its two end blocks.
+ *   RMQ_PATH_CONTRACTED  Section 3.1 (BbST_CON): sort the 2q endpoints,
+ *                        contract A into A_Q (2q-1 minima of the closed areas
+ *                        between consecutive endpoints), then the same block
+ *                        Sparse Table and query step on A_Q.
+ *
+ * Memory: every array argument named A, L, R, out, keys, pos, tag, st, aq,
+ * bad_count, stats or workspace is a DEVICE pointer (hipMalloc / torch CUDA
+ * tensor memory) owned by the caller.  The library never copies A or the
+ * queries (extra space is counted apart from A and Q, as in Section 4).  It
+ * owns rmq_index objects and, when no workspace is passed, the per-call
+ * scratch, which it takes from the device's stream-ordered pool
+ * (hipMallocAsync) and returns on the same stream.
+ *
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = the null
+ * stream).  Every call only enqueues work on it and returns; results are
+ * valid once the stream has been synchronised.  Calls on one stream run in
+ * order.  An rmq_index is immutable after rmq_build and may be queried from
+ * several streams at once.
+ *
+ * Errors: host-checkable problems return a status synchronously and enqueue
+ * nothing.  A query with L > R, L < 0 or R >= n is not a host error: it gets
+ * out[i] = -1 and, when opt->bad_count is given, adds one to *bad_count on
+ * the device; other queries are unaffected.  q = 0 is a no-op returning
+ * RMQ_OK.  No C++ exception crosses this interface.
+ *
+ * Value encoding used by the key-valued outputs (block minima, Sparse Table
+ * entries, A_Q): key(p) = ((uint32(A[p]) XOR 0x80000000) << 32) | p, a
+ * uint64.  Comparing keys as unsigned integers compares (A[p], p)
+ * lexicographically, so the smallest key is the leftmost minimum and every
+ * min over keys is exact and order-independent.
+ */
+#ifndef RMQ_H
+#define RMQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum rmq_status {
+    RMQ_OK = 0,
+    RMQ_ERR_INVALID_ARG = 1,      /* bad pointer, size, block size or option */
+    RMQ_ERR_OUT_OF_MEMORY = 2,    /* device allocation failed                */
+    RMQ_ERR_DEVICE = 3,           /* a HIP runtime call failed               */
+    RMQ_ERR_WORKSPACE_SMALL = 4,  /* caller workspace below the needed size  */
+    RMQ_ERR_MISALIGNED = 5        /* a device pointer is not 4/8-byte aligned */
+} rmq_status;
+
+typedef enum rmq_path {
+    RMQ_PATH_AUTO = 0,        /* planner picks FULL or CONTRACTED            */
+    RMQ_PATH_FULL = 1,        /* Section 3.2                                 */
+    RMQ_PATH_CONTRACTED = 2   /* Section 3.1                                 */
+} rmq_path;
+
+/* Block sizes k are powers of two in [RMQ_MIN_BLOCK, RMQ_MAX_BLOCK]. */
+#define RMQ_MIN_BLOCK 16
+#define RMQ_MAX_BLOCK (1 << 24)
+/* Largest n (positions must fit in the int32 outputs) and largest q. */
+#define RMQ_MAX_N 2147483647LL
+#define RMQ_MAX_Q (1LL << 30)
+
+/* Number of per-stage timings an rmq_timer can hold.  The stages mirror the
+ * four steps of Section 3.1 (Table 1 reports their cumulative shares):
+ *   0 sort + remap (CONTRACTED only), 1 contraction or block minima,
+ *   2 block Sparse Table, 3 queries. */
+#define RMQ_NUM_STAGES 4
+
+typedef struct rmq_timer_s rmq_timer;
+typedef struct rmq_index_s *rmq_index;
+
+typedef struct rmq_options {
+    int32_t block_size;      /* k; 0 = chosen by the planner                    */
+    int32_t path;            /* rmq_path                                         */
+    int64_t *bad_count;      /* device int64, optional: += invalid queries       */
+    uint64_t *stats;         /* device uint64[2], optional: += scans performed,
+                                += elements scanned by partial-block scans       */
+    void *workspace;         /* device scratch, optional (see rmq_workspace_bytes) */
+    size_t workspace_bytes;
+    rmq_timer *timer;        /* optional: records per-stage events on the stream */
+} rmq_options;
+
+/* A human-readable name for a status code (static storage). */
+const char *rmq_status_string(rmq_status s);
+
+/* Library version string (static storage). */
+const char *rmq_version(void);
+
+/* ----------------------------------------------------------------------------
+ * One offline batch (Section 1, offline setting): build whatever the chosen
+ * method needs from A and answer all q queries.  out[i] receives the leftmost
+ * argmin of A[L[i]..R[i]] (int32), or -1 for an invalid query.
+ *   A    int32[n], 1 <= n <= RMQ_MAX_N
+ *   L, R int32[q], 0 <= q <= RMQ_MAX_Q
+ *   out  int32[q]; may not alias A, L or R
+ * rmq_query_batch uses the planner with default options. */
+rmq_status rmq_query_batch(const int32_t *A, int64_t n, const int32_t *L, const int32_t *R,
+                           int64_t q, int32_t *out, void *stream);
+
+/* As rmq_query_batch, with options (opt may be NULL). */
+rmq_status rmq_query_batch_ex(const int32_t *A, int64_t n, const int32_t *L, const int32_t *R,
+                              int64_t q, int32_t *out, void *stream, const rmq_options *opt);
+
+/* Device scratch bytes rmq_query_batch_ex needs for (n, q, opt->block_size,
+ * opt->path) after planning; 0 on invalid arguments.  A caller-provided
+ * workspace must be at least this large and 256-byte aligned. */
+size_t rmq_workspace_bytes(int64_t n, int64_t q, const rmq_options *opt);
+
+/* The planner's choice of block size and path for (n, q) -- the automated
+ * selection of k that Section 5 leaves as future work.  Either output
+ * pointer may be NULL. */
+rmq_status rmq_plan(int64_t n, int64_t q, int32_t *block_size, int32_t *path);
+
+/* ----------------------------------------------------------------------------
+ * Resident index (Section 3.2): block minima and the block Sparse Table of A
+ * with block size k, kept in device memory for any number of later query
+ * batches.  A must stay alive and unmodified while the index is used, since
+ * partial-block scans read it.  opt->block_size 0 picks k ~ sqrt(n)
+ * (Section 3.2 sets k = Theta(sqrt(n))); opt->path is ignored.  *idx is set
+ * only on success.  The build is enqueued on `stream`. */
+rmq_status rmq_build(const int32_t *A, int64_t n, const rmq_options *opt, void *stream,
+                     rmq_index *idx);
+
+/* Answer a batch on a resident index (Section 3.1 step 4 on A's blocks). */
+rmq_status rmq_query_index(rmq_index idx, const int32_t *L, const int32_t *R, int64_t q,
+                           int32_t *out, void *stream);
+
+/* As rmq_query_index with options; only bad_count and stats are used. */
+rmq_status rmq_query_index_ex(rmq_index idx, const int32_t *L, const int32_t *R, int64_t q,
+                              int32_t *out, void *stream, const rmq_options *opt);
+
+/* Free an index.  The caller must make sure no enqueued work still uses it. */
+rmq_status rmq_index_free(rmq_index idx);
+
+/* Facts about an index (any output pointer may be NULL). */
+rmq_status rmq_index_info(rmq_index idx, int64_t *n, int32_t *block_size, int64_t *num_blocks,
+                          int32_t *levels, size_t *bytes);
+
+/* Copy of the index's Sparse Table (level-major, levels x num_blocks uint64
+ * keys; level 0 = block minima) into device memory `st`, on `stream`. */
+rmq_status rmq_index_copy_table(rmq_index idx, uint64_t *st, void *stream);
+
+/* Device bytes of a resident index for (n, k): 8 * nb * levels with
+ * nb = ceil(n / k) and levels = floor(log2(max(nb - 2, 1))) + 1 -- the spans
+ * of 2^j blocks that a query strictly inside A can use (Table 2 reports this
+ * footprint as a share of the 4n bytes of A).  0 on invalid arguments. */
+size_t rmq_index_bytes(int64_t n, int32_t block_size);
+
+/* Number of Sparse Table levels for nb blocks (see rmq_index_bytes). */
+int32_t rmq_table_levels(int64_t num_blocks);
+
+/* ----------------------------------------------------------------------------
+ * The steps of the two methods, one call each, for callers that want a
+ * single stage (and for checking each stage on its own).  All enqueue on
+ * `stream` and return at once.
+ *
+ * Section 3.2 / Section 3.1 step 3, first half: keys[j] = min key over block
+ * j = A[j*k .. min((j+1)*k, n) - 1], j < ceil(n/k).  keys: uint64[ceil(n/k)]. */
+rmq_status rmq_block_minima(const int32_t *A, int64_t n, int32_t block_size, uint64_t *keys,
+                            void *stream);
+
+/* Same over a key array (the contracted array A_Q of the CONTRACTED path):
+ * keys[j] = min of src[j*k .. min((j+1)*k, m) - 1]. */
+rmq_status rmq_block_minima_keys(const uint64_t *src, int64_t m, int32_t block_size,
+                                 uint64_t *keys, void *stream);
+
+/* Section 3.1 step 3 (Section 2's doubling on blocks): given level 0 in
+ * st[0 .. nb-1], fill levels 1 .. levels-1 of the level-major table
+ * st[levels][nb], where st[j][b] = min(st[0][b .. min(b + 2^j, nb) - 1]). */
+rmq_status rmq_sparse_table_build(uint64_t *st, int64_t num_blocks, int32_t levels,
+                                  void *stream);
+
+/* Section 3.1 step 1: the 2q endpoints (L[i], tag 2i) and (R[i], tag 2i+1)
+ * sorted by (position, tag) with a device LSD radix sort.  pos, tag:
+ * int32[2q].  Endpoint positions must lie in [0, n); an invalid query's
+ * endpoints are sorted as position 0.  Needs rmq_sort_workspace_bytes(q). */
+rmq_status rmq_sort_endpoints(const int32_t *L, const int32_t *R, int64_t q, int64_t n,
+                              int32_t *pos, int32_t *tag, void *workspace,
+                              size_t workspace_bytes, void *stream);
+size_t rmq_sort_workspace_bytes(int64_t q);
+
+/* Section 3.1 steps 1-2 after the sort: remap each query onto contracted
+ * indices (Lc[i] = slot of its left end, Rc[i] = slot of its right end - 1)
+ * and build A_Q: aq[s] = min key over the CLOSED area A[pos[s] .. pos[s+1]],
+ * s = 0 .. 2q-2.  Lc, Rc: int32[q]; aq: uint64[2q-1]. */
+rmq_status rmq_contract(const int32_t *A, int64_t n, const int32_t *pos, const int32_t *tag,
+                        int64_t q, int32_t *Lc, int32_t *Rc, uint64_t *aq, void *stream);
+
+/* ----------------------------------------------------------------------------
+ * Per-stage timing (Table 1's stages).  A timer collects HIP events that
+ * rmq_query_batch_ex records on its stream; rmq_timer_read waits for them and
+ * returns the milliseconds of each stage of the last call that used the
+ * timer (0 for stages that did not run) and the total. */
+rmq_status rmq_timer_create(rmq_timer **t);
+rmq_status rmq_timer_read(rmq_timer *t, float *stage_ms, float *total_ms);
+rmq_status rmq_timer_destroy(rmq_timer *t);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RMQ_H */

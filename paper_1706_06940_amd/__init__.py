@@ -1,0 +1,321 @@
+"""Python binding of librmq: batched offline range minimum queries on MI355X.
+
+Argument marshalling only -- every step of both methods runs in the HIP
+kernels of librmq.so (see include/rmq.h for the C ABI this mirrors).  Tensors
+are torch CUDA (HIP) tensors; calls enqueue on the current stream of the
+tensor's device and return without synchronising.
+
+Methods (Grabowski & Kowalski, "Faster batched range minimum queries"):
+  path="full"        Section 3.2, block Sparse Table over all of A (BbST)
+  path="contracted"  Section 3.1, contraction of A to A_Q first (BbST_CON)
+  path="auto"        the library's planner
+Answers are the LEFTMOST position of the minimum of A[L[i]..R[i]] (0-based,
+inclusive), -1 for an invalid query.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librmq.so")
+
+OK = 0
+STATUS = {0: "ok", 1: "invalid argument", 2: "out of device memory", 3: "HIP runtime error",
+          4: "workspace too small", 5: "misaligned device pointer"}
+PATHS = {"auto": 0, "full": 1, "contracted": 2}
+MIN_BLOCK = 16
+MAX_BLOCK = 1 << 24
+NUM_STAGES = 4
+STAGE_NAMES = ("sort", "contract_or_blockmin", "sparse_table", "query")
+
+
+class RMQError(RuntimeError):
+    def __init__(self, fn: str, status: int):
+        super().__init__(f"{fn}: {STATUS.get(status, status)} (status {status})")
+        self.status = status
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [
+        ("block_size", ctypes.c_int32),
+        ("path", ctypes.c_int32),
+        ("bad_count", ctypes.c_void_p),
+        ("stats", ctypes.c_void_p),
+        ("workspace", ctypes.c_void_p),
+        ("workspace_bytes", ctypes.c_size_t),
+        ("timer", ctypes.c_void_p),
+    ]
+
+
+_LIB = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded librmq.so.  Raises if it has not been built: there is no
+    fallback implementation."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_1706_06940_amd.build` (no CPU fallback exists)")
+    L = ctypes.CDLL(LIB_PATH)
+    v, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    opt = ctypes.POINTER(_Options)
+    sigs = {
+        "rmq_status_string": ([i32], ctypes.c_char_p),
+        "rmq_version": ([], ctypes.c_char_p),
+        "rmq_query_batch": ([v, i64, v, v, i64, v, v], i32),
+        "rmq_query_batch_ex": ([v, i64, v, v, i64, v, v, opt], i32),
+        "rmq_workspace_bytes": ([i64, i64, opt], sz),
+        "rmq_plan": ([i64, i64, ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
+        "rmq_build": ([v, i64, opt, v, ctypes.POINTER(v)], i32),
+        "rmq_query_index": ([v, v, v, i64, v, v], i32),
+        "rmq_query_index_ex": ([v, v, v, i64, v, v, opt], i32),
+        "rmq_index_free": ([v], i32),
+        "rmq_index_info": ([v, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i64),
+                            ctypes.POINTER(i32), ctypes.POINTER(sz)], i32),
+        "rmq_index_copy_table": ([v, v, v], i32),
+        "rmq_index_bytes": ([i64, i32], sz),
+        "rmq_table_levels": ([i64], i32),
+        "rmq_block_minima": ([v, i64, i32, v, v], i32),
+        "rmq_block_minima_keys": ([v, i64, i32, v, v], i32),
+        "rmq_sparse_table_build": ([v, i64, i32, v], i32),
+        "rmq_sort_endpoints": ([v, v, i64, i64, v, v, v, sz, v], i32),
+        "rmq_sort_workspace_bytes": ([i64], sz),
+        "rmq_contract": ([v, i64, v, v, i64, v, v, v, v], i32),
+        "rmq_timer_create": ([ctypes.POINTER(v)], i32),
+        "rmq_timer_read": ([v, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)], i32),
+        "rmq_timer_destroy": ([v], i32),
+    }
+    for name, (args, res) in sigs.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _LIB = L
+    return L
+
+
+def _check(fn: str, status: int) -> None:
+    if status != OK:
+        raise RMQError(fn, status)
+
+
+def _dev_i32(t: torch.Tensor, name: str) -> int:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != torch.int32 or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous int32 tensor")
+    return t.data_ptr()
+
+
+def _dev_u64(t: torch.Tensor, name: str) -> int:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype not in (torch.int64, torch.uint64) or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous 64-bit tensor")
+    return t.data_ptr()
+
+
+def _stream(device: torch.device, stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    return int(s.cuda_stream)
+
+
+class Timer:
+    """Per-stage timing of one batch (Table 1's four stages)."""
+
+    def __init__(self):
+        h = ctypes.c_void_p()
+        _check("rmq_timer_create", lib().rmq_timer_create(ctypes.byref(h)))
+        self.handle = h
+
+    def read(self):
+        """Wait for the last timed call; returns (stage_ms[4], total_ms)."""
+        st = (ctypes.c_float * NUM_STAGES)()
+        tot = ctypes.c_float()
+        _check("rmq_timer_read", lib().rmq_timer_read(self.handle, st, ctypes.byref(tot)))
+        return list(st), tot.value
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _LIB is not None:
+            _LIB.rmq_timer_destroy(self.handle)
+            self.handle = None
+
+
+def _options(block_size=0, path="auto", bad_count=None, stats=None, workspace=None,
+             timer: Optional[Timer] = None) -> _Options:
+    o = _Options()
+    o.block_size = int(block_size)
+    o.path = PATHS[path] if isinstance(path, str) else int(path)
+    o.bad_count = _dev_u64(bad_count, "bad_count") if bad_count is not None else None
+    o.stats = _dev_u64(stats, "stats") if stats is not None else None
+    if workspace is not None:
+        if not workspace.is_cuda or not workspace.is_contiguous():
+            raise TypeError("workspace must be a contiguous CUDA tensor")
+        o.workspace = workspace.data_ptr()
+        o.workspace_bytes = workspace.numel() * workspace.element_size()
+    o.timer = timer.handle if timer is not None else None
+    return o
+
+
+def version() -> str:
+    return lib().rmq_version().decode()
+
+
+def plan(n: int, q: int):
+    """(block_size, path name) the planner picks for (n, q)."""
+    k, p = ctypes.c_int32(), ctypes.c_int32()
+    _check("rmq_plan", lib().rmq_plan(n, q, ctypes.byref(k), ctypes.byref(p)))
+    return k.value, {v: k_ for k_, v in PATHS.items()}[p.value]
+
+
+def workspace_bytes(n: int, q: int, path="auto", block_size: int = 0) -> int:
+    o = _options(block_size, path)
+    return int(lib().rmq_workspace_bytes(n, q, ctypes.byref(o)))
+
+
+def index_bytes(n: int, block_size: int) -> int:
+    return int(lib().rmq_index_bytes(n, block_size))
+
+
+def table_levels(num_blocks: int) -> int:
+    return int(lib().rmq_table_levels(num_blocks))
+
+
+def query_batch(A: torch.Tensor, L: torch.Tensor, R: torch.Tensor, *, path="auto",
+                block_size: int = 0, out: Optional[torch.Tensor] = None, bad_count=None,
+                stats=None, workspace=None, timer: Optional[Timer] = None,
+                stream=None) -> torch.Tensor:
+    """Answer all queries of one offline batch (Section 1); returns int32 out."""
+    n, q = A.numel(), L.numel()
+    if R.numel() != q:
+        raise ValueError("L and R differ in length")
+    if out is None:
+        out = torch.empty(q, dtype=torch.int32, device=A.device)
+    o = _options(block_size, path, bad_count, stats, workspace, timer)
+    st = lib().rmq_query_batch_ex(_dev_i32(A, "A"), n, _dev_i32(L, "L") if q else None,
+                                  _dev_i32(R, "R") if q else None, q,
+                                  _dev_i32(out, "out") if q else None,
+                                  _stream(A.device, stream), ctypes.byref(o))
+    _check("rmq_query_batch_ex", st)
+    return out
+
+
+class Index:
+    """Resident block Sparse Table of A (Section 3.2) for repeated batches.
+    Keeps a reference to A, which partial-block scans read."""
+
+    def __init__(self, A: torch.Tensor, block_size: int = 0, stream=None):
+        h = ctypes.c_void_p()
+        o = _options(block_size, "full")
+        _check("rmq_build", lib().rmq_build(_dev_i32(A, "A"), A.numel(), ctypes.byref(o),
+                                            _stream(A.device, stream), ctypes.byref(h)))
+        self.handle = h
+        self.A = A
+        n, k, nb, lv, by = (ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64(),
+                            ctypes.c_int32(), ctypes.c_size_t())
+        _check("rmq_index_info", lib().rmq_index_info(h, ctypes.byref(n), ctypes.byref(k),
+                                                      ctypes.byref(nb), ctypes.byref(lv),
+                                                      ctypes.byref(by)))
+        self.n, self.block_size, self.num_blocks = n.value, k.value, nb.value
+        self.levels, self.bytes = lv.value, by.value
+
+    def query(self, L: torch.Tensor, R: torch.Tensor, out: Optional[torch.Tensor] = None,
+              bad_count=None, stats=None, stream=None) -> torch.Tensor:
+        q = L.numel()
+        if out is None:
+            out = torch.empty(q, dtype=torch.int32, device=self.A.device)
+        o = _options(0, "full", bad_count, stats)
+        _check("rmq_query_index_ex", lib().rmq_query_index_ex(
+            self.handle, _dev_i32(L, "L") if q else None, _dev_i32(R, "R") if q else None, q,
+            _dev_i32(out, "out") if q else None, _stream(self.A.device, stream), ctypes.byref(o)))
+        return out
+
+    def table(self, stream=None) -> torch.Tensor:
+        """The Sparse Table as a (levels, num_blocks) int64 tensor of keys."""
+        st = torch.empty(self.levels * self.num_blocks, dtype=torch.int64, device=self.A.device)
+        _check("rmq_index_copy_table", lib().rmq_index_copy_table(
+            self.handle, st.data_ptr(), _stream(self.A.device, stream)))
+        return st.view(self.levels, self.num_blocks)
+
+    def free(self) -> None:
+        if getattr(self, "handle", None):
+            torch.cuda.synchronize(self.A.device)
+            _check("rmq_index_free", lib().rmq_index_free(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+# ---- single stages ----------------------------------------------------------
+def block_minima(A: torch.Tensor, block_size: int, stream=None) -> torch.Tensor:
+    nb = (A.numel() + block_size - 1) // block_size
+    keys = torch.empty(nb, dtype=torch.int64, device=A.device)
+    _check("rmq_block_minima", lib().rmq_block_minima(_dev_i32(A, "A"), A.numel(), block_size,
+                                                      keys.data_ptr(), _stream(A.device, stream)))
+    return keys
+
+
+def block_minima_keys(S: torch.Tensor, block_size: int, stream=None) -> torch.Tensor:
+    nb = (S.numel() + block_size - 1) // block_size
+    keys = torch.empty(nb, dtype=torch.int64, device=S.device)
+    _check("rmq_block_minima_keys", lib().rmq_block_minima_keys(
+        _dev_u64(S, "src"), S.numel(), block_size, keys.data_ptr(), _stream(S.device, stream)))
+    return keys
+
+
+def sparse_table(level0: torch.Tensor, levels: Optional[int] = None, stream=None) -> torch.Tensor:
+    """(levels, nb) table built on the device from its level 0."""
+    nb = level0.numel()
+    levels = table_levels(nb) if levels is None else levels
+    st = torch.empty(levels * nb, dtype=torch.int64, device=level0.device)
+    st[:nb].copy_(level0)
+    _check("rmq_sparse_table_build", lib().rmq_sparse_table_build(
+        st.data_ptr(), nb, levels, _stream(level0.device, stream)))
+    return st.view(levels, nb)
+
+
+def sort_endpoints(L: torch.Tensor, R: torch.Tensor, n: int, stream=None):
+    """Sorted (position, tag) endpoint list of Section 3.1 step 1."""
+    q = L.numel()
+    pos = torch.empty(2 * q, dtype=torch.int32, device=L.device)
+    tag = torch.empty(2 * q, dtype=torch.int32, device=L.device)
+    wsb = int(lib().rmq_sort_workspace_bytes(q))
+    ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=L.device)
+    _check("rmq_sort_endpoints", lib().rmq_sort_endpoints(
+        _dev_i32(L, "L"), _dev_i32(R, "R"), q, n, _dev_i32(pos, "pos"), _dev_i32(tag, "tag"),
+        ws.data_ptr(), wsb, _stream(L.device, stream)))
+    return pos, tag
+
+
+def contract(A: torch.Tensor, pos: torch.Tensor, tag: torch.Tensor, stream=None):
+    """Remapped ranges (Lc, Rc) and A_Q keys of Section 3.1 steps 1-2."""
+    q = pos.numel() // 2
+    Lc = torch.empty(q, dtype=torch.int32, device=A.device)
+    Rc = torch.empty(q, dtype=torch.int32, device=A.device)
+    aq = torch.empty(max(2 * q - 1, 0), dtype=torch.int64, device=A.device)
+    _check("rmq_contract", lib().rmq_contract(
+        _dev_i32(A, "A"), A.numel(), _dev_i32(pos, "pos"), _dev_i32(tag, "tag"), q,
+        _dev_i32(Lc, "Lc"), _dev_i32(Rc, "Rc"), aq.data_ptr() if q else None,
+        _stream(A.device, stream)))
+    return Lc, Rc, aq
+
+
+def key_positions(keys: torch.Tensor) -> torch.Tensor:
+    """Low 32 bits of keys (the positions in A)."""
+    return (keys & 0xFFFFFFFF).to(torch.int32)
+
+
+def key_values(keys: torch.Tensor) -> torch.Tensor:
+    """High 32 bits of keys mapped back to the int32 values."""
+    u = ((keys >> 32) & 0xFFFFFFFF) ^ 0x80000000
+    return torch.where(u >= 2 ** 31, u - 2 ** 32, u).to(torch.int32)

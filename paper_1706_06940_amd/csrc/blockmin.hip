@@ -1,0 +1,220 @@
+// Block minima (Section 3.2, first stage; Section 3.1 step 3 on A_Q):
+// keys[j] = min key over block j of k consecutive elements.
+//
+// One streaming pass over the input with 16-byte loads.  A workgroup of 4
+// waves owns a chunk of C elements -- one whole block when k > 4 wave loads,
+// else 16 wave loads -- and wave w owns the w-th quarter of it.  Inside a wave:
+//   * k >= one wave load  -> each lane keeps a running (value, position)
+//     minimum over the iterations of the block, then a full-wave DPP min;
+//   * k <  one wave load  -> a block is k/V lanes of one load and is reduced
+//     with a DPP group min right after the load;
+//   * k >  4 wave loads   -> the four waves hold quarters of one block and
+//     combine their minima through LDS.
+#include "device.h"
+#include "kernels.h"
+
+namespace rmq {
+
+namespace {
+
+constexpr int WG = 256;
+
+// ---------------------------------------------------------------- int32 input
+// Per-lane running minimum over 4 consecutive int32 at positions p..p+3.
+// Elements are met in increasing position, so a strict < keeps the leftmost.
+struct LaneMin {
+  int32_t v;
+  int64_t p;
+};
+
+__device__ __forceinline__ void lane_update(LaneMin& m, v4i32 x, int64_t p) {
+  if (x.x < m.v) { m.v = x.x; m.p = p; }
+  if (x.y < m.v) { m.v = x.y; m.p = p + 1; }
+  if (x.z < m.v) { m.v = x.z; m.p = p + 2; }
+  if (x.w < m.v) { m.v = x.w; m.p = p + 3; }
+}
+
+template <bool ALIGNED>
+__device__ __forceinline__ v4i32 load4_i32(const int32_t* __restrict__ A, int64_t p, int64_t n) {
+  if (ALIGNED && p + 3 < n) return load_stream(A + p);
+  v4i32 x;
+  x.x = p + 0 < n ? A[p + 0] : INT32_MAX;
+  x.y = p + 1 < n ? A[p + 1] : INT32_MAX;
+  x.z = p + 2 < n ? A[p + 2] : INT32_MAX;
+  x.w = p + 3 < n ? A[p + 3] : INT32_MAX;
+  return x;
+}
+
+// Key of a lane's running minimum.  The minimum starts as (INT32_MAX, first
+// position of the lane): correct even when that element is INT32_MAX, since
+// a strict < never replaces an equal value.  A lane whose first position is
+// past n contributes nothing.
+__device__ __forceinline__ uint64_t lane_key(const LaneMin& m, int64_t first, int64_t n) {
+  return first < n ? make_key(m.v, (uint32_t)m.p) : KEY_NONE;
+}
+
+template <bool ALIGNED>
+__global__ __launch_bounds__(WG) void k_blockmin_i32(const int32_t* __restrict__ A, int64_t n,
+                                                     int kshift, uint64_t* __restrict__ keys) {
+  constexpr int V = 4, WL = 64 * V;  // elements per lane load / per wave load
+  const int lane = lane_id(), wave = threadIdx.x >> 6;
+  const int64_t k = 1ll << kshift;
+  const int64_t C = k > 4 * WL ? k : 16 * WL;
+  const int64_t WS = C / 4;  // elements per wave, >= 4 * WL
+  const int64_t w0 = (int64_t)blockIdx.x * C + wave * WS;
+  __shared__ uint64_t part[4];
+
+  if (k >= WL) {
+    // one block spans >= 1 wave loads; this wave holds WS / min(k, WS) block slices
+    const int64_t span = k < WS ? k : WS;
+    for (int64_t s0 = w0; s0 < w0 + WS; s0 += span) {
+      const int64_t first = s0 + lane * V;
+      LaneMin m{INT32_MAX, first};
+      int64_t it = 0;
+      for (; it + 4 * WL <= span; it += 4 * WL) {
+        v4i32 x0 = load4_i32<ALIGNED>(A, first + it, n);
+        v4i32 x1 = load4_i32<ALIGNED>(A, first + it + WL, n);
+        v4i32 x2 = load4_i32<ALIGNED>(A, first + it + 2 * WL, n);
+        v4i32 x3 = load4_i32<ALIGNED>(A, first + it + 3 * WL, n);
+        lane_update(m, x0, first + it);
+        lane_update(m, x1, first + it + WL);
+        lane_update(m, x2, first + it + 2 * WL);
+        lane_update(m, x3, first + it + 3 * WL);
+      }
+      for (; it < span; it += WL) lane_update(m, load4_i32<ALIGNED>(A, first + it, n), first + it);
+      uint64_t key = group_min_u64<64>(lane_key(m, first, n));
+      if (k > WS) {
+        if (lane == 63) part[wave] = key;
+      } else if (lane == 63 && s0 < n) {
+        keys[s0 >> kshift] = key;
+      }
+    }
+    if (k > WS) {
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        uint64_t b = umin64(umin64(part[0], part[1]), umin64(part[2], part[3]));
+        if ((int64_t)blockIdx.x * C < n) keys[blockIdx.x] = b;
+      }
+    }
+  } else {
+    // several blocks per wave load: groups of g = k / V lanes
+    const int g = (int)(k / V);
+    for (int64_t it = 0; it < WS; it += WL) {
+      const int64_t first = w0 + it + lane * V;
+      LaneMin m{INT32_MAX, first};
+      lane_update(m, load4_i32<ALIGNED>(A, first, n), first);
+      uint64_t key = group_min_u64_rt(lane_key(m, first, n), g);
+      const int64_t blk_start = first - (int64_t)(lane % g) * V;
+      if ((lane % g) == g - 1 && blk_start < n) keys[blk_start >> kshift] = key;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- uint64 keys
+template <bool ALIGNED>
+__device__ __forceinline__ void load2_key(const uint64_t* __restrict__ S, int64_t p, int64_t m,
+                                          uint64_t& a, uint64_t& b) {
+  if (ALIGNED && p + 1 < m) {
+    v2u64 x = load_stream(S + p);
+    a = x.x;
+    b = x.y;
+    return;
+  }
+  a = p < m ? S[p] : KEY_NONE;
+  b = p + 1 < m ? S[p + 1] : KEY_NONE;
+}
+
+template <bool ALIGNED>
+__global__ __launch_bounds__(WG) void k_blockmin_keys(const uint64_t* __restrict__ S, int64_t m,
+                                                      int kshift, uint64_t* __restrict__ keys) {
+  constexpr int V = 2, WL = 64 * V;
+  const int lane = lane_id(), wave = threadIdx.x >> 6;
+  const int64_t k = 1ll << kshift;
+  const int64_t C = k > 4 * WL ? k : 16 * WL;
+  const int64_t WS = C / 4;
+  const int64_t w0 = (int64_t)blockIdx.x * C + wave * WS;
+  __shared__ uint64_t part[4];
+
+  if (k >= WL) {
+    const int64_t span = k < WS ? k : WS;
+    for (int64_t s0 = w0; s0 < w0 + WS; s0 += span) {
+      const int64_t first = s0 + lane * V;
+      uint64_t best = KEY_NONE;
+      int64_t it = 0;
+      for (; it + 4 * WL <= span; it += 4 * WL) {
+        uint64_t a0, b0, a1, b1, a2, b2, a3, b3;
+        load2_key<ALIGNED>(S, first + it, m, a0, b0);
+        load2_key<ALIGNED>(S, first + it + WL, m, a1, b1);
+        load2_key<ALIGNED>(S, first + it + 2 * WL, m, a2, b2);
+        load2_key<ALIGNED>(S, first + it + 3 * WL, m, a3, b3);
+        best = umin64(best, umin64(umin64(a0, b0), umin64(a1, b1)));
+        best = umin64(best, umin64(umin64(a2, b2), umin64(a3, b3)));
+      }
+      for (; it < span; it += WL) {
+        uint64_t a, b;
+        load2_key<ALIGNED>(S, first + it, m, a, b);
+        best = umin64(best, umin64(a, b));
+      }
+      uint64_t key = group_min_u64<64>(best);
+      if (k > WS) {
+        if (lane == 63) part[wave] = key;
+      } else if (lane == 63 && s0 < m) {
+        keys[s0 >> kshift] = key;
+      }
+    }
+    if (k > WS) {
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        uint64_t b = umin64(umin64(part[0], part[1]), umin64(part[2], part[3]));
+        if ((int64_t)blockIdx.x * C < m) keys[blockIdx.x] = b;
+      }
+    }
+  } else {
+    const int g = (int)(k / V);
+    for (int64_t it = 0; it < WS; it += WL) {
+      const int64_t first = w0 + it + lane * V;
+      uint64_t a, b;
+      load2_key<ALIGNED>(S, first, m, a, b);
+      uint64_t key = group_min_u64_rt(umin64(a, b), g);
+      const int64_t blk_start = first - (int64_t)(lane % g) * V;
+      if ((lane % g) == g - 1 && blk_start < m) keys[blk_start >> kshift] = key;
+    }
+  }
+}
+
+}  // namespace
+
+int64_t blockmin_grid(int64_t n, int kshift, int elems_per_lane_load) {
+  const int64_t k = 1ll << kshift;
+  const int64_t WL = 64ll * elems_per_lane_load;
+  const int64_t C = k > 4 * WL ? k : 16 * WL;
+  return (n + C - 1) / C;
+}
+
+hipError_t launch_blockmin_i32(const int32_t* A, int64_t n, int kshift, uint64_t* keys,
+                               hipStream_t stream) {
+  const int64_t grid = blockmin_grid(n, kshift, 4);
+  if (grid <= 0) return hipSuccess;
+  if (((uintptr_t)A & 15) == 0)
+    hipLaunchKernelGGL(k_blockmin_i32<true>, dim3((unsigned)grid), dim3(WG), 0, stream, A, n,
+                       kshift, keys);
+  else
+    hipLaunchKernelGGL(k_blockmin_i32<false>, dim3((unsigned)grid), dim3(WG), 0, stream, A, n,
+                       kshift, keys);
+  return hipGetLastError();
+}
+
+hipError_t launch_blockmin_keys(const uint64_t* S, int64_t m, int kshift, uint64_t* keys,
+                                hipStream_t stream) {
+  const int64_t grid = blockmin_grid(m, kshift, 2);
+  if (grid <= 0) return hipSuccess;
+  if (((uintptr_t)S & 15) == 0)
+    hipLaunchKernelGGL(k_blockmin_keys<true>, dim3((unsigned)grid), dim3(WG), 0, stream, S, m,
+                       kshift, keys);
+  else
+    hipLaunchKernelGGL(k_blockmin_keys<false>, dim3((unsigned)grid), dim3(WG), 0, stream, S, m,
+                       kshift, keys);
+  return hipGetLastError();
+}
+
+}  // namespace rmq

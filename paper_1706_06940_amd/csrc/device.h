@@ -1,0 +1,102 @@
+// Device-side building blocks shared by the kernels: the (value, position)
+// key encoding, wave64 min reductions over DPP, and vector loads.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rmq {
+
+constexpr uint64_t KEY_NONE = ~0ull;  // identity of min over keys
+
+// key(p) = ((uint32(v) ^ 0x80000000) << 32) | p: unsigned order of keys is the
+// lexicographic order of (v, p), so min over keys = leftmost minimum.
+__device__ __forceinline__ uint64_t make_key(int32_t v, uint32_t p) {
+  return ((uint64_t)((uint32_t)v ^ 0x80000000u) << 32) | (uint64_t)p;
+}
+__device__ __forceinline__ uint32_t key_pos(uint64_t k) { return (uint32_t)k; }
+
+__device__ __forceinline__ uint64_t umin64(uint64_t a, uint64_t b) { return a < b ? a : b; }
+
+// ---- DPP moves of a 64-bit value (gfx9 DPP control codes) ------------------
+enum : int {
+  DPP_QUAD_XOR1 = 0xB1,        // quad_perm [1,0,3,2]
+  DPP_QUAD_XOR2 = 0x4E,        // quad_perm [2,3,0,1]
+  DPP_ROW_HALF_MIRROR = 0x141,  // lane i <-> 7-i within 8
+  DPP_ROW_MIRROR = 0x140,       // lane i <-> 15-i within 16
+  DPP_ROW_BCAST15 = 0x142,      // lane 15 of each row -> next row
+  DPP_ROW_BCAST31 = 0x143,      // lane 31 -> rows 2 and 3
+};
+
+// Lanes whose DPP source is disabled keep their own value (old = src), so a
+// following min() is a no-op for them.
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t v) {
+  int lo = (int)(uint32_t)v, hi = (int)(uint32_t)(v >> 32);
+  lo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROW_MASK, 0xF, false);
+  hi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROW_MASK, 0xF, false);
+  return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+// Min over aligned groups of G lanes (G = 1..64, power of two).  Afterwards
+// the LAST lane of each group (lane % G == G-1) holds the group's minimum
+// (for G <= 16 every lane of the group does).
+template <int G>
+__device__ __forceinline__ uint64_t group_min_u64(uint64_t v) {
+  if constexpr (G >= 2) v = umin64(v, dpp_u64<DPP_QUAD_XOR1>(v));
+  if constexpr (G >= 4) v = umin64(v, dpp_u64<DPP_QUAD_XOR2>(v));
+  if constexpr (G >= 8) v = umin64(v, dpp_u64<DPP_ROW_HALF_MIRROR>(v));
+  if constexpr (G >= 16) v = umin64(v, dpp_u64<DPP_ROW_MIRROR>(v));
+  if constexpr (G >= 32) v = umin64(v, dpp_u64<DPP_ROW_BCAST15, 0xA>(v));
+  if constexpr (G >= 64) v = umin64(v, dpp_u64<DPP_ROW_BCAST31, 0xC>(v));
+  return v;
+}
+
+// Runtime group size dispatch (uniform across the wave).
+__device__ __forceinline__ uint64_t group_min_u64_rt(uint64_t v, int g) {
+  switch (g) {
+    case 1: return v;
+    case 2: return group_min_u64<2>(v);
+    case 4: return group_min_u64<4>(v);
+    case 8: return group_min_u64<8>(v);
+    case 16: return group_min_u64<16>(v);
+    case 32: return group_min_u64<32>(v);
+    default: return group_min_u64<64>(v);
+  }
+}
+
+// Full-wave minimum, broadcast to every lane.
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
+  v = group_min_u64<64>(v);
+  uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)v, 63);
+  uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+// Wave-uniform broadcast of a 64-bit register from lane `src` (src uniform).
+__device__ __forceinline__ int64_t readlane64(int64_t v, int src) {
+  uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)(uint64_t)v, src);
+  uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), src);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+typedef int32_t v4i32 __attribute__((ext_vector_type(4)));
+typedef uint64_t v2u64 __attribute__((ext_vector_type(2)));
+
+// Streaming 16-byte loads with the non-temporal hint (each byte of the input
+// is read once per pass).
+__device__ __forceinline__ v4i32 load_stream(const int32_t* p) {
+  return __builtin_nontemporal_load(reinterpret_cast<const v4i32*>(p));
+}
+__device__ __forceinline__ v2u64 load_stream(const uint64_t* p) {
+  return __builtin_nontemporal_load(reinterpret_cast<const v2u64*>(p));
+}
+
+// Floor log2 for x >= 1.
+__device__ __forceinline__ int ilog2_u64(uint64_t x) { return 63 - __clzll(x); }
+
+}  // namespace rmq

@@ -1,0 +1,104 @@
+"""The C ABI on the host (CPU only): symbols, status codes, sizes, planner.
+
+None of these calls touches a device: invalid arguments are rejected before
+any HIP call, and the size/plan functions are pure host logic."""
+import ctypes
+import json
+import math
+import os
+import re
+
+import pytest
+
+import paper_1706_06940_amd as rmq
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rmq.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rmq_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    L = rmq.lib()
+    names = declared_functions()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_status_strings():
+    L = rmq.lib()
+    for code in range(6):
+        assert L.rmq_status_string(code).decode() == rmq.STATUS[code]
+
+
+def test_index_bytes_reproduces_table2():
+    """Section 4, Table 2: the BbST footprint 8 * nb * levels bytes."""
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "table2_memory.json")))
+    for n in (10 ** 8, 10 ** 9):
+        got = [round(100 * rmq.index_bytes(n, k) / (4 * n), 2) for k in g["bbst"]["k"]]
+        assert got == g["bbst"][f"n={n}"], (n, got)
+
+
+def test_con_footprint_reading_matches_table2():
+    """Reading of the paper's BbST_CON footprint: 40 bytes per query plus the
+    block Sparse Table over 2q/512 blocks reproduces all six cells."""
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "table2_memory.json")))
+    for n in (10 ** 8, 10 ** 9):
+        row = g["bbst_con"][f"n={n}"]
+        for q, pct in zip(row["q"], row["pct"]):
+            nb = math.ceil(2 * q / 512)
+            b = 40 * q + 8 * nb * math.ceil(math.log2(nb))
+            assert round(100 * b / (4 * n), 2) == pct
+
+
+def test_table_levels():
+    # levels = floor(log2(nb - 2)) + 1: the widest span strictly inside A
+    assert [rmq.table_levels(nb) for nb in (1, 2, 3, 4, 5, 6, 10, 1024, 1026)] == \
+        [1, 1, 1, 2, 2, 3, 4, 10, 11]
+
+
+def test_invalid_arguments_rejected_on_host():
+    L = rmq.lib()
+    fake = ctypes.c_void_p(256)  # never dereferenced: rejected before any device work
+    out = ctypes.c_void_p(512)
+    assert L.rmq_query_batch(fake, 0, fake, fake, 1, out, None) == 1        # n < 1
+    assert L.rmq_query_batch(fake, 10, fake, fake, -1, out, None) == 1      # q < 0
+    assert L.rmq_query_batch(None, 10, fake, fake, 1, out, None) == 1       # A null
+    assert L.rmq_query_batch(fake, 10, None, fake, 1, out, None) == 1       # L null
+    assert L.rmq_query_batch(fake, 2 ** 31, fake, fake, 1, out, None) == 1  # n too big
+    assert L.rmq_query_batch(ctypes.c_void_p(258), 10, fake, fake, 1, out, None) == 5
+    o = rmq._Options()
+    o.block_size = 1000  # not a power of two
+    assert L.rmq_query_batch_ex(fake, 10, fake, fake, 1, out, None, ctypes.byref(o)) == 1
+    o.block_size = 8     # below the minimum
+    assert L.rmq_query_batch_ex(fake, 10, fake, fake, 1, out, None, ctypes.byref(o)) == 1
+    o.block_size = 0
+    o.path = 7
+    assert L.rmq_query_batch_ex(fake, 10, fake, fake, 1, out, None, ctypes.byref(o)) == 1
+    assert L.rmq_index_bytes(0, 1024) == 0 and L.rmq_index_bytes(100, 1000) == 0
+    assert L.rmq_workspace_bytes(10, -1, None) == 0
+
+
+def test_workspace_sizes():
+    n, q = 10 ** 8, 10 ** 7
+    full = rmq.workspace_bytes(n, q, "full", 1024)
+    nb = -(-n // 1024)
+    assert full >= 8 * nb * rmq.table_levels(nb)
+    con = rmq.workspace_bytes(n, q, "contracted", 512)
+    m = 2 * q - 1
+    nbq = -(-m // 512)
+    # endpoint list, sort scratch, remapped ranges, A_Q and its table
+    assert con >= 8 * 2 * q + 8 * 2 * q + 8 * q + 8 * m + 8 * nbq * rmq.table_levels(nbq)
+    assert con < 60 * q + n // 256 + 8 * nbq * rmq.table_levels(nbq) + (1 << 20)
+
+
+def test_plan():
+    k, p = rmq.plan(10 ** 8, 10 ** 6)
+    assert p in ("full", "contracted") and k >= 16 and (k & (k - 1)) == 0
+    with pytest.raises(rmq.RMQError):
+        rmq.plan(0, 5)
