@@ -50,10 +50,15 @@ def main() -> int:
     ap.add_argument("--qs", default="1e3,1e4,1e5,1e6,1e7")
     ap.add_argument("--paths", default="full,contracted")
     ap.add_argument("--k-full", type=int, default=0, help="0 = planner's choice")
-    ap.add_argument("--k-con", type=int, default=512)
+    ap.add_argument("--k-con", type=int, default=0, help="0 = the library's default per q")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--verify", action="store_true",
                     help="check every answer of the first step against the oracle")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="before timing, run one plain device copy of BYTES bytes (a known "
+                         "HBM traffic figure to scale profiler byte counters by)")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="repeat the CPU oracle sweep until this much time has passed")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -80,8 +85,10 @@ def main() -> int:
     A = torch.from_numpy(A_h).to(d)
     batches = [(torch.from_numpy(L).to(d), torch.from_numpy(R).to(d)) for L, R in batches_h]
     outs = [torch.empty(q, dtype=torch.int32, device=d) for q in qs]
-    k_full = args.k_full or rmq.plan(n, max(qs))[0]
+    k_full = args.k_full or rmq.default_block(n, max(qs), "full")
     ks = {"full": k_full, "contracted": args.k_con}
+    k_used = {"full": {q: k_full for q in qs},
+              "contracted": {q: args.k_con or rmq.default_block(n, q, "contracted") for q in qs}}
     torch.cuda.synchronize()
 
     def step(timers=None):
@@ -90,6 +97,14 @@ def main() -> int:
                 L, R = batches[j]
                 rmq.query_batch(A, L, R, path=p, block_size=ks[p], out=outs[j],
                                 timer=timers[(p, j)] if timers else None)
+
+    if args.copy_calibration:
+        src = torch.empty(args.copy_calibration // 4, dtype=torch.int32, device=d).fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     for _ in range(args.warmup):
         step()
@@ -154,15 +169,19 @@ def main() -> int:
         import oracle
 
         orc = oracle.Oracle()
-        t = time.perf_counter()
-        for j, q in enumerate(qs):
-            orc.rmq_sparse_table(A_h, batches_h[j][0], batches_h[j][1], 32)
-        dt = time.perf_counter() - t
-        cpu = {"value": round(sum(qs) / dt, 1), "unit": "queries/s",
+        reps, t = 0, time.perf_counter()
+        while True:
+            for j, q in enumerate(qs):
+                orc.rmq_sparse_table(A_h, batches_h[j][0], batches_h[j][1], 32)
+            reps += 1
+            dt = time.perf_counter() - t
+            if dt >= args.cpu_seconds or reps >= 200:
+                break
+        cpu = {"value": round(reps * sum(qs) / dt, 1), "unit": "queries/s",
                "cores": orc.num_threads(), "kind": "oracle",
                "sample": (f"oracle Sparse Table over 32-element blocks, build + answers for "
-                          f"each batch of the sweep q={qs} on the same n={n} array "
-                          f"({dt:.2f}s on the host)")}
+                          f"each batch of the sweep q={qs} on the same n={n} array, "
+                          f"{reps} sweeps in {dt:.1f}s on the host")}
 
     line = {
         "metric": METRIC, "value": round(value, 1), "unit": "queries/s", "n_gpus": 1,
@@ -172,7 +191,8 @@ def main() -> int:
         "config": {"workload": (f"batched RMQ, n={n} int32 uniform in [0,2^31), batches "
                                 f"q={qs} uniform swapped queries, each answered by "
                                 f"{' and '.join(paths)} method(s)"),
-                   "n": n, "q": qs, "paths": paths, "block_size": ks,
+                   "n": n, "q": qs, "paths": paths,
+                   "block_size": {p: k_used[p] for p in paths},
                    "parallelism": "single GPU"},
         "roofline": roofline, "cpu_baseline": cpu, "breakdown": breakdown,
     }

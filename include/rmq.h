@@ -129,6 +129,23 @@ size_t rmq_workspace_bytes(int64_t n, int64_t q, const rmq_options *opt);
  * pointer may be NULL. */
 rmq_status rmq_plan(int64_t n, int64_t q, int32_t *block_size, int32_t *path);
 
+/* Measured plans for the planner: for a call with path AUTO, rmq_plan picks
+ * the entry nearest to (n, q) in (log2 n, log2 q) and uses its block size and
+ * method; with no table (count 0 clears it) it falls back to the built-in
+ * rule.  The table is copied; process-wide. */
+typedef struct rmq_plan_entry {
+    int64_t n, q;
+    int32_t block_size;
+    int32_t path;          /* RMQ_PATH_FULL or RMQ_PATH_CONTRACTED */
+} rmq_plan_entry;
+rmq_status rmq_planner_set_table(const rmq_plan_entry *entries, int32_t count);
+
+/* Block size a call with block_size 0 uses for the given path (FULL or
+ * CONTRACTED): about sqrt(n)/8 for FULL (Section 3.2 takes k = Theta(sqrt(n))
+ * for the average case), about sqrt(2q)/2 for CONTRACTED (Section 3.1's
+ * O(1 + k^2/q) average query cost).  0 on invalid arguments. */
+int32_t rmq_default_block(int64_t n, int64_t q, int32_t path);
+
 /* ----------------------------------------------------------------------------
  * Resident index (Section 3.2): block minima and the block Sparse Table of A
  * with block size k, kept in device memory for any number of later query
@@ -198,11 +215,55 @@ rmq_status rmq_sort_endpoints(const int32_t *L, const int32_t *R, int64_t q, int
 size_t rmq_sort_workspace_bytes(int64_t q);
 
 /* Section 3.1 steps 1-2 after the sort: remap each query onto contracted
- * indices (Lc[i] = slot of its left end, Rc[i] = slot of its right end - 1)
- * and build A_Q: aq[s] = min key over the CLOSED area A[pos[s] .. pos[s+1]],
- * s = 0 .. 2q-2.  Lc, Rc: int32[q]; aq: uint64[2q-1]. */
+ * indices -- LR[2i] = Lc[i], the slot of its left end, and LR[2i+1] = Rc[i],
+ * the slot of its right end minus one -- and build A_Q: aq[s] = min key over
+ * the CLOSED area A[pos[s] .. pos[s+1]], s = 0 .. 2q-2.  pos, tag: the
+ * output of rmq_sort_endpoints.  LR: int32[2q] (8-byte aligned);
+ * aq: uint64[2q-1].  Takes its scratch from the stream-ordered pool. */
 rmq_status rmq_contract(const int32_t *A, int64_t n, const int32_t *pos, const int32_t *tag,
-                        int64_t q, int32_t *Lc, int32_t *Rc, uint64_t *aq, void *stream);
+                        int64_t q, int32_t *LR, uint64_t *aq, void *stream);
+
+/* ----------------------------------------------------------------------------
+ * Batches of arrays.  Many independent arrays, each with its own batch of
+ * queries, answered together: the planner picks each array's block size and
+ * method (the automated choice of k left open in Section 5), and the arrays
+ * that take the plain method (Section 3.2) run as ONE launch per phase for
+ * all of them -- block minima, each round of Sparse Table levels, queries --
+ * instead of a few launches per array.  A batch owns its device scratch and a
+ * device table describing the arrays; inputs and outputs stay the caller's.
+ * Pointers in the items must stay valid, and the arrays unmodified, for the
+ * batch's life: runs reuse them. */
+typedef struct rmq_batch_item {
+    const int32_t *A;        /* device int32[n]                             */
+    int64_t n;
+    const int32_t *L, *R;    /* device int32[q]                             */
+    int64_t q;
+    int32_t *out;            /* device int32[q]                             */
+    int32_t block_size;      /* 0 = planner                                 */
+    int32_t path;            /* rmq_path; AUTO = planner                    */
+} rmq_batch_item;
+
+typedef struct rmq_batch_s *rmq_batch;
+
+#define RMQ_BATCH_FUSED 0     /* one launch per phase over all plain-path arrays */
+#define RMQ_BATCH_PER_ITEM 1  /* the single-array sequence for each array        */
+
+/* Plan every item and allocate the batch's scratch (synchronous). */
+rmq_status rmq_batch_create(const rmq_batch_item *items, int32_t count, rmq_batch *out);
+
+/* Enqueue one run of the whole batch on `stream`.  use_graph != 0 records the
+ * run's launches into a hipGraph on first use (per mode) and replays it
+ * afterwards; it needs a non-null stream. */
+rmq_status rmq_batch_run(rmq_batch b, int32_t mode, int32_t use_graph, void *stream);
+
+/* The block size and method the planner gave item i. */
+rmq_status rmq_batch_item_plan(rmq_batch b, int32_t i, int32_t *block_size, int32_t *path);
+
+/* Device scratch the batch holds for its items. */
+size_t rmq_batch_workspace_bytes(rmq_batch b);
+
+/* Free a batch; no enqueued run may still be using it. */
+rmq_status rmq_batch_free(rmq_batch b);
 
 /* ----------------------------------------------------------------------------
  * Per-stage timing (Table 1's stages).  A timer collects HIP events that

@@ -73,6 +73,7 @@ def lib() -> ctypes.CDLL:
         "rmq_query_batch_ex": ([v, i64, v, v, i64, v, v, opt], i32),
         "rmq_workspace_bytes": ([i64, i64, opt], sz),
         "rmq_plan": ([i64, i64, ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
+        "rmq_default_block": ([i64, i64, i32], i32),
         "rmq_build": ([v, i64, opt, v, ctypes.POINTER(v)], i32),
         "rmq_query_index": ([v, v, v, i64, v, v], i32),
         "rmq_query_index_ex": ([v, v, v, i64, v, v, opt], i32),
@@ -87,7 +88,13 @@ def lib() -> ctypes.CDLL:
         "rmq_sparse_table_build": ([v, i64, i32, v], i32),
         "rmq_sort_endpoints": ([v, v, i64, i64, v, v, v, sz, v], i32),
         "rmq_sort_workspace_bytes": ([i64], sz),
-        "rmq_contract": ([v, i64, v, v, i64, v, v, v, v], i32),
+        "rmq_contract": ([v, i64, v, v, i64, v, v, v], i32),
+        "rmq_planner_set_table": ([v, i32], i32),
+        "rmq_batch_create": ([v, i32, ctypes.POINTER(v)], i32),
+        "rmq_batch_run": ([v, i32, i32, v], i32),
+        "rmq_batch_item_plan": ([v, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
+        "rmq_batch_workspace_bytes": ([v], sz),
+        "rmq_batch_free": ([v], i32),
         "rmq_timer_create": ([ctypes.POINTER(v)], i32),
         "rmq_timer_read": ([v, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)], i32),
         "rmq_timer_destroy": ([v], i32),
@@ -163,6 +170,42 @@ def _options(block_size=0, path="auto", bad_count=None, stats=None, workspace=No
     return o
 
 
+class _PlanEntry(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("q", ctypes.c_int64), ("block_size", ctypes.c_int32),
+                ("path", ctypes.c_int32)]
+
+
+class _BatchItem(ctypes.Structure):
+    _fields_ = [("A", ctypes.c_void_p), ("n", ctypes.c_int64), ("L", ctypes.c_void_p),
+                ("R", ctypes.c_void_p), ("q", ctypes.c_int64), ("out", ctypes.c_void_p),
+                ("block_size", ctypes.c_int32), ("path", ctypes.c_int32)]
+
+
+def set_plan_table(entries) -> None:
+    """Install measured plans: iterable of (n, q, block_size, path name).
+    An empty iterable restores the built-in rule."""
+    entries = list(entries)
+    arr = (_PlanEntry * max(len(entries), 1))()
+    for i, (n, q, k, p) in enumerate(entries):
+        arr[i] = _PlanEntry(int(n), int(q), int(k), PATHS[p] if isinstance(p, str) else int(p))
+    _check("rmq_planner_set_table", lib().rmq_planner_set_table(arr, len(entries)))
+
+
+TUNE_TABLE = os.path.join(HERE, "tune_table.json")
+
+
+def load_plan_table(path: str = TUNE_TABLE) -> bool:
+    """Install the autotuner's table if it exists; returns whether it did."""
+    import json
+
+    if not os.path.exists(path):
+        return False
+    with open(path) as f:
+        data = json.load(f)
+    set_plan_table((e["n"], e["q"], e["block_size"], e["path"]) for e in data["entries"])
+    return True
+
+
 def version() -> str:
     return lib().rmq_version().decode()
 
@@ -172,6 +215,11 @@ def plan(n: int, q: int):
     k, p = ctypes.c_int32(), ctypes.c_int32()
     _check("rmq_plan", lib().rmq_plan(n, q, ctypes.byref(k), ctypes.byref(p)))
     return k.value, {v: k_ for k_, v in PATHS.items()}[p.value]
+
+
+def default_block(n: int, q: int, path: str) -> int:
+    """Block size a call with block_size=0 uses on the given path."""
+    return int(lib().rmq_default_block(n, q, PATHS[path]))
 
 
 def workspace_bytes(n: int, q: int, path="auto", block_size: int = 0) -> int:
@@ -300,14 +348,13 @@ def sort_endpoints(L: torch.Tensor, R: torch.Tensor, n: int, stream=None):
 def contract(A: torch.Tensor, pos: torch.Tensor, tag: torch.Tensor, stream=None):
     """Remapped ranges (Lc, Rc) and A_Q keys of Section 3.1 steps 1-2."""
     q = pos.numel() // 2
-    Lc = torch.empty(q, dtype=torch.int32, device=A.device)
-    Rc = torch.empty(q, dtype=torch.int32, device=A.device)
+    LR = torch.empty(2 * q, dtype=torch.int32, device=A.device)
     aq = torch.empty(max(2 * q - 1, 0), dtype=torch.int64, device=A.device)
-    _check("rmq_contract", lib().rmq_contract(
-        _dev_i32(A, "A"), A.numel(), _dev_i32(pos, "pos"), _dev_i32(tag, "tag"), q,
-        _dev_i32(Lc, "Lc"), _dev_i32(Rc, "Rc"), aq.data_ptr() if q else None,
-        _stream(A.device, stream)))
-    return Lc, Rc, aq
+    if q:
+        _check("rmq_contract", lib().rmq_contract(
+            _dev_i32(A, "A"), A.numel(), _dev_i32(pos, "pos"), _dev_i32(tag, "tag"), q,
+            _dev_i32(LR, "LR"), aq.data_ptr(), _stream(A.device, stream)))
+    return LR[0::2], LR[1::2], aq
 
 
 def key_positions(keys: torch.Tensor) -> torch.Tensor:
@@ -319,3 +366,61 @@ def key_values(keys: torch.Tensor) -> torch.Tensor:
     """High 32 bits of keys mapped back to the int32 values."""
     u = ((keys >> 32) & 0xFFFFFFFF) ^ 0x80000000
     return torch.where(u >= 2 ** 31, u - 2 ** 32, u).to(torch.int32)
+
+
+class Batch:
+    """Many arrays, each with its own query batch (rmq_batch_* in rmq.h).
+    `arrays`: int32 CUDA tensors; `queries`: (L, R) pairs; `outs`: optional
+    int32 outputs.  Keeps references to every tensor it was given."""
+
+    def __init__(self, arrays, queries, outs=None, block_sizes=None, paths=None):
+        count = len(arrays)
+        if len(queries) != count:
+            raise ValueError("one (L, R) pair per array")
+        if outs is None:
+            outs = [torch.empty(L.numel(), dtype=torch.int32, device=A.device)
+                    for A, (L, _) in zip(arrays, queries)]
+        self.arrays, self.queries, self.outs = list(arrays), list(queries), list(outs)
+        items = (_BatchItem * count)()
+        for i, (A, (L, R), out) in enumerate(zip(self.arrays, self.queries, self.outs)):
+            q = L.numel()
+            items[i] = _BatchItem(
+                _dev_i32(A, "A"), A.numel(), _dev_i32(L, "L") if q else None,
+                _dev_i32(R, "R") if q else None, q, _dev_i32(out, "out") if q else None,
+                int(block_sizes[i]) if block_sizes else 0,
+                PATHS[paths[i]] if paths else 0)
+        h = ctypes.c_void_p()
+        _check("rmq_batch_create", lib().rmq_batch_create(items, count, ctypes.byref(h)))
+        self.handle = h
+        self.device = self.arrays[0].device
+
+    MODES = {"fused": 0, "per_item": 1}
+
+    def run(self, mode: str = "fused", graph: bool = False, stream=None):
+        """Enqueue one run; `graph` replays a captured hipGraph (needs a
+        non-default stream)."""
+        s = _stream(self.device, stream)
+        _check("rmq_batch_run", lib().rmq_batch_run(self.handle, self.MODES[mode],
+                                                    1 if graph else 0, s))
+        return self.outs
+
+    def plan(self, i: int):
+        k, p = ctypes.c_int32(), ctypes.c_int32()
+        _check("rmq_batch_item_plan", lib().rmq_batch_item_plan(self.handle, i, ctypes.byref(k),
+                                                                ctypes.byref(p)))
+        return k.value, {v: k_ for k_, v in PATHS.items()}[p.value]
+
+    def workspace_bytes(self) -> int:
+        return int(lib().rmq_batch_workspace_bytes(self.handle))
+
+    def free(self) -> None:
+        if getattr(self, "handle", None):
+            torch.cuda.synchronize(self.device)
+            _check("rmq_batch_free", lib().rmq_batch_free(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

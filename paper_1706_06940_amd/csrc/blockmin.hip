@@ -53,16 +53,17 @@ __device__ __forceinline__ uint64_t lane_key(const LaneMin& m, int64_t first, in
   return first < n ? make_key(m.v, (uint32_t)m.p) : KEY_NONE;
 }
 
+// The work of workgroup `wg` (chunk wg of C elements) of one array.
 template <bool ALIGNED>
-__global__ __launch_bounds__(WG) void k_blockmin_i32(const int32_t* __restrict__ A, int64_t n,
-                                                     int kshift, uint64_t* __restrict__ keys) {
+__device__ __forceinline__ void blockmin_i32_wg(const int32_t* __restrict__ A, int64_t n,
+                                                int kshift, uint64_t* __restrict__ keys,
+                                                int64_t wg, uint64_t* part) {
   constexpr int V = 4, WL = 64 * V;  // elements per lane load / per wave load
   const int lane = lane_id(), wave = threadIdx.x >> 6;
   const int64_t k = 1ll << kshift;
   const int64_t C = k > 4 * WL ? k : 16 * WL;
   const int64_t WS = C / 4;  // elements per wave, >= 4 * WL
-  const int64_t w0 = (int64_t)blockIdx.x * C + wave * WS;
-  __shared__ uint64_t part[4];
+  const int64_t w0 = wg * C + wave * WS;
 
   if (k >= WL) {
     // one block spans >= 1 wave loads; this wave holds WS / min(k, WS) block slices
@@ -93,7 +94,7 @@ __global__ __launch_bounds__(WG) void k_blockmin_i32(const int32_t* __restrict__
       __syncthreads();
       if (threadIdx.x == 0) {
         uint64_t b = umin64(umin64(part[0], part[1]), umin64(part[2], part[3]));
-        if ((int64_t)blockIdx.x * C < n) keys[blockIdx.x] = b;
+        if (wg * C < n) keys[wg] = b;
       }
     }
   } else {
@@ -108,6 +109,28 @@ __global__ __launch_bounds__(WG) void k_blockmin_i32(const int32_t* __restrict__
       if ((lane % g) == g - 1 && blk_start < n) keys[blk_start >> kshift] = key;
     }
   }
+}
+
+template <bool ALIGNED>
+__global__ __launch_bounds__(WG) void k_blockmin_i32(const int32_t* __restrict__ A, int64_t n,
+                                                     int kshift, uint64_t* __restrict__ keys) {
+  __shared__ uint64_t part[4];
+  blockmin_i32_wg<ALIGNED>(A, n, kshift, keys, blockIdx.x, part);
+}
+
+// Block minima of every array of a batch in one launch: workgroup w works on
+// the array whose range of workgroups holds w.
+__global__ __launch_bounds__(WG) void k_blockmin_multi(const ArrayDesc* __restrict__ items,
+                                                       const int64_t* __restrict__ wg_prefix,
+                                                       int count) {
+  __shared__ uint64_t part[4];
+  const int j = find_item(wg_prefix, count, blockIdx.x);
+  const ArrayDesc& d = items[j];
+  const int64_t wg = blockIdx.x - wg_prefix[j];
+  if (((uintptr_t)d.A & 15) == 0)
+    blockmin_i32_wg<true>(d.A, d.n, d.kshift, d.st, wg, part);
+  else
+    blockmin_i32_wg<false>(d.A, d.n, d.kshift, d.st, wg, part);
 }
 
 // ---------------------------------------------------------------- uint64 keys
@@ -196,12 +219,20 @@ hipError_t launch_blockmin_i32(const int32_t* A, int64_t n, int kshift, uint64_t
   const int64_t grid = blockmin_grid(n, kshift, 4);
   if (grid <= 0) return hipSuccess;
   if (((uintptr_t)A & 15) == 0)
-    hipLaunchKernelGGL(k_blockmin_i32<true>, dim3((unsigned)grid), dim3(WG), 0, stream, A, n,
-                       kshift, keys);
+    RMQ_TRY(launch(k_blockmin_i32<true>, dim3((unsigned)grid), dim3(WG), 0, stream, A, n,
+                       kshift, keys));
   else
-    hipLaunchKernelGGL(k_blockmin_i32<false>, dim3((unsigned)grid), dim3(WG), 0, stream, A, n,
-                       kshift, keys);
+    RMQ_TRY(launch(k_blockmin_i32<false>, dim3((unsigned)grid), dim3(WG), 0, stream, A, n,
+                       kshift, keys));
   return hipGetLastError();
+}
+
+hipError_t launch_blockmin_multi(const ArrayDesc* items, const int64_t* wg_prefix, int count,
+                                 int64_t total_wg, hipStream_t stream) {
+  if (total_wg <= 0) return hipSuccess;
+  RMQ_TRY(launch(k_blockmin_multi, dim3((unsigned)total_wg), dim3(WG), 0, stream, items,
+                 wg_prefix, count));
+  return hipSuccess;
 }
 
 hipError_t launch_blockmin_keys(const uint64_t* S, int64_t m, int kshift, uint64_t* keys,
@@ -209,11 +240,11 @@ hipError_t launch_blockmin_keys(const uint64_t* S, int64_t m, int kshift, uint64
   const int64_t grid = blockmin_grid(m, kshift, 2);
   if (grid <= 0) return hipSuccess;
   if (((uintptr_t)S & 15) == 0)
-    hipLaunchKernelGGL(k_blockmin_keys<true>, dim3((unsigned)grid), dim3(WG), 0, stream, S, m,
-                       kshift, keys);
+    RMQ_TRY(launch(k_blockmin_keys<true>, dim3((unsigned)grid), dim3(WG), 0, stream, S, m,
+                       kshift, keys));
   else
-    hipLaunchKernelGGL(k_blockmin_keys<false>, dim3((unsigned)grid), dim3(WG), 0, stream, S, m,
-                       kshift, keys);
+    RMQ_TRY(launch(k_blockmin_keys<false>, dim3((unsigned)grid), dim3(WG), 0, stream, S, m,
+                       kshift, keys));
   return hipGetLastError();
 }
 

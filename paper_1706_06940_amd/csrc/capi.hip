@@ -5,6 +5,8 @@
 #include <string.h>
 
 #include <mutex>
+#include <new>
+#include <vector>
 
 #include "kernels.h"
 #include "rmq.h"
@@ -12,10 +14,12 @@
 using namespace rmq;
 
 struct rmq_timer_s {
-  hipEvent_t ev[RMQ_NUM_STAGES + 1];
+  rmq::StageClock clock[RMQ_NUM_STAGES];
   bool ran[RMQ_NUM_STAGES];
   bool armed;
 };
+
+thread_local rmq::StageClock* rmq::tl_clock = nullptr;
 
 struct rmq_index_s {
   int device;
@@ -63,7 +67,15 @@ int32_t default_block_full(int64_t n) {
   while (k < 65536 && (double)(k * 2) <= t) k *= 2;
   return (int32_t)k;
 }
-constexpr int32_t DEFAULT_BLOCK_CONTRACTED = 512;
+// CONTRACTED: the average query cost is O(1 + k^2/q) (Section 3.1, step 4
+// analysis), so k ~ sqrt(q); A_Q has 2q - 1 entries and partial scans read k
+// of them.  A power of two near sqrt(2q) / 2, clamped to [16, 4096].
+int32_t default_block_contracted(int64_t q) {
+  const double t = sqrt(2.0 * (double)q) / 2.0;
+  int64_t k = 16;
+  while (k < 4096 && (double)(k * 2) <= t) k *= 2;
+  return (int32_t)k;
+}
 
 struct Plan {
   int path;
@@ -83,7 +95,7 @@ rmq_status make_plan(int64_t n, int64_t q, const rmq_options* opt, Plan* p) {
     path = pp;
     if (k == 0) k = pk;
   }
-  if (k == 0) k = path == RMQ_PATH_FULL ? default_block_full(n) : DEFAULT_BLOCK_CONTRACTED;
+  if (k == 0) k = path == RMQ_PATH_FULL ? default_block_full(n) : default_block_contracted(q);
   p->path = path;
   p->k = k;
   p->kshift = ilog2_i64(k);
@@ -109,7 +121,7 @@ FullLayout full_layout(int64_t n, int64_t k) {
 struct ConLayout {
   int64_t M, m, nb;
   int levels;
-  size_t off_pos, off_tag, off_sort, off_lc, off_rc, off_aq, off_tiles, off_st, bytes;
+  size_t off_pos, off_tag, off_sort, off_lr, off_aq, off_tiles, off_st, bytes;
 };
 
 ConLayout con_layout(int64_t n, int64_t q, int64_t k) {
@@ -125,10 +137,8 @@ ConLayout con_layout(int64_t n, int64_t q, int64_t k) {
   o = align_up(o + sizeof(int32_t) * (size_t)c.M);
   c.off_sort = o;
   o = align_up(o + sort_workspace_bytes(q));
-  c.off_lc = o;
-  o = align_up(o + sizeof(int32_t) * (size_t)q);
-  c.off_rc = o;
-  o = align_up(o + sizeof(int32_t) * (size_t)q);
+  c.off_lr = o;
+  o = align_up(o + sizeof(int32_t) * (size_t)c.M);
   c.off_aq = o;
   o = align_up(o + sizeof(uint64_t) * (size_t)c.m);
   c.off_tiles = o;
@@ -146,6 +156,9 @@ size_t plan_bytes(int64_t n, int64_t q, const Plan& p) {
 
 std::once_flag g_pool_once[64];
 
+std::mutex g_table_mu;
+std::vector<rmq_plan_entry> g_table;  // measured plans, see rmq_planner_set_table
+
 // Keep freed stream-ordered memory cached in the device pool, so that
 // per-call scratch costs no device allocation after the first call.
 void prepare_pool() {
@@ -160,9 +173,27 @@ void prepare_pool() {
   });
 }
 
-void timer_mark(rmq_timer* t, int i, hipStream_t s) {
-  if (t) hipEventRecord(t->ev[i], s);
+// Stage i of a timed call: kernels launched until stage_end carry the
+// stage's start/stop events.  A stage that launched nothing gets two plain
+// event records (zero length).
+void stage_begin(rmq_timer* t, int i) {
+  if (!t) return;
+  t->clock[i].started = false;
+  tl_clock = &t->clock[i];
 }
+void stage_end(rmq_timer* t, int i, hipStream_t s) {
+  if (!t) return;
+  tl_clock = nullptr;
+  if (!t->clock[i].started) {
+    hipEventRecord(t->clock[i].start, s);
+    hipEventRecord(t->clock[i].stop, s);
+  }
+  t->ran[i] = true;
+  t->armed = true;
+}
+struct ClockGuard {  // never leave a stage clock armed on an early return
+  ~ClockGuard() { tl_clock = nullptr; }
+};
 
 bool check_query_ptrs(const int32_t* L, const int32_t* R, int32_t* out, int64_t q) {
   if (q == 0) return true;
@@ -173,25 +204,23 @@ rmq_status run_full(const int32_t* A, int64_t n, const int32_t* L, const int32_t
                     int32_t* out, hipStream_t s, const rmq_options* opt, const Plan& p,
                     char* ws) {
   rmq_timer* t = opt ? opt->timer : nullptr;
+  ClockGuard guard;
+  if (t) t->ran[0] = false;  // no sort stage on this path
   const FullLayout f = full_layout(n, p.k);
   uint64_t* st = reinterpret_cast<uint64_t*>(ws + f.off_st);
-  timer_mark(t, 0, s);
-  timer_mark(t, 1, s);  // no sort stage on this path
+  stage_begin(t, 1);
   hipError_t e = launch_blockmin_i32(A, n, p.kshift, st, s);
   if (e != hipSuccess) return from_hip(e);
-  timer_mark(t, 2, s);
+  stage_end(t, 1, s);
+  stage_begin(t, 2);
   e = launch_sparse_table(st, f.nb, f.levels, s);
   if (e != hipSuccess) return from_hip(e);
-  timer_mark(t, 3, s);
+  stage_end(t, 2, s);
+  stage_begin(t, 3);
   e = launch_query_full(A, n, p.kshift, st, f.nb, L, R, q, out, opt ? opt->bad_count : nullptr,
                         opt ? opt->stats : nullptr, s);
   if (e != hipSuccess) return from_hip(e);
-  timer_mark(t, 4, s);
-  if (t) {
-    t->ran[0] = false;
-    t->ran[1] = t->ran[2] = t->ran[3] = true;
-    t->armed = true;
-  }
+  stage_end(t, 3, s);
   return RMQ_OK;
 }
 
@@ -202,32 +231,33 @@ rmq_status run_contracted(const int32_t* A, int64_t n, const int32_t* L, const i
   const ConLayout c = con_layout(n, q, p.k);
   int32_t* pos = reinterpret_cast<int32_t*>(ws + c.off_pos);
   int32_t* tag = reinterpret_cast<int32_t*>(ws + c.off_tag);
-  int32_t* Lc = reinterpret_cast<int32_t*>(ws + c.off_lc);
-  int32_t* Rc = reinterpret_cast<int32_t*>(ws + c.off_rc);
+  int32_t* LR = reinterpret_cast<int32_t*>(ws + c.off_lr);
   uint64_t* aq = reinterpret_cast<uint64_t*>(ws + c.off_aq);
   int32_t* tiles = reinterpret_cast<int32_t*>(ws + c.off_tiles);
   uint64_t* st = reinterpret_cast<uint64_t*>(ws + c.off_st);
-  timer_mark(t, 0, s);
+  ClockGuard guard;
+  stage_begin(t, 0);
   hipError_t e = launch_sort_endpoints(L, R, q, n, pos, tag, ws + c.off_sort,
                                        sort_workspace_bytes(q), s);
   if (e != hipSuccess) return from_hip(e);
-  timer_mark(t, 1, s);
-  e = launch_contract(A, n, pos, tag, q, Lc, Rc, aq, tiles, s);
+  e = launch_remap(tag, q, LR, ws + c.off_sort, sort_workspace_bytes(q), s);
   if (e != hipSuccess) return from_hip(e);
-  timer_mark(t, 2, s);
+  stage_end(t, 0, s);
+  stage_begin(t, 1);
+  e = launch_contract(A, n, pos, q, aq, tiles, s);
+  if (e != hipSuccess) return from_hip(e);
+  stage_end(t, 1, s);
+  stage_begin(t, 2);
   e = launch_blockmin_keys(aq, c.m, p.kshift, st, s);
   if (e != hipSuccess) return from_hip(e);
   e = launch_sparse_table(st, c.nb, c.levels, s);
   if (e != hipSuccess) return from_hip(e);
-  timer_mark(t, 3, s);
-  e = launch_query_contracted(aq, c.m, n, p.kshift, st, c.nb, L, R, Lc, Rc, q, out,
+  stage_end(t, 2, s);
+  stage_begin(t, 3);
+  e = launch_query_contracted(aq, c.m, n, p.kshift, st, c.nb, L, R, LR, q, out,
                               opt ? opt->bad_count : nullptr, opt ? opt->stats : nullptr, s);
   if (e != hipSuccess) return from_hip(e);
-  timer_mark(t, 4, s);
-  if (t) {
-    t->ran[0] = t->ran[1] = t->ran[2] = t->ran[3] = true;
-    t->armed = true;
-  }
+  stage_end(t, 3, s);
   return RMQ_OK;
 }
 
@@ -260,8 +290,41 @@ size_t rmq_index_bytes(int64_t n, int32_t k) {
   return sizeof(uint64_t) * (size_t)nb * (size_t)rmq_table_levels(nb);
 }
 
+rmq_status rmq_planner_set_table(const rmq_plan_entry* entries, int32_t count) {
+  if (count < 0 || (count > 0 && !entries)) return RMQ_ERR_INVALID_ARG;
+  for (int32_t i = 0; i < count; ++i) {
+    const rmq_plan_entry& e = entries[i];
+    if (e.n < 1 || e.q < 1 || !is_pow2_block(e.block_size) ||
+        (e.path != RMQ_PATH_FULL && e.path != RMQ_PATH_CONTRACTED))
+      return RMQ_ERR_INVALID_ARG;
+  }
+  std::lock_guard<std::mutex> lock(g_table_mu);
+  g_table.assign(entries, entries + count);
+  return RMQ_OK;
+}
+
 rmq_status rmq_plan(int64_t n, int64_t q, int32_t* block_size, int32_t* path) {
   if (n < 1 || n > RMQ_MAX_N || q < 0 || q > RMQ_MAX_Q) return RMQ_ERR_INVALID_ARG;
+  {
+    // measured table: the entry nearest in (log2 n, log2 q)
+    std::lock_guard<std::mutex> lock(g_table_mu);
+    if (!g_table.empty()) {
+      const double ln = log2((double)n), lq = log2((double)(q > 0 ? q : 1));
+      const rmq_plan_entry* best = nullptr;
+      double bd = 0;
+      for (const rmq_plan_entry& e : g_table) {
+        const double dn = log2((double)e.n) - ln, dq = log2((double)e.q) - lq;
+        const double d = dn * dn + dq * dq;
+        if (!best || d < bd) {
+          best = &e;
+          bd = d;
+        }
+      }
+      if (block_size) *block_size = best->block_size;
+      if (path) *path = best->path;
+      return RMQ_OK;
+    }
+  }
   // Both methods stream A once (the contracted one between its outermost
   // endpoints, which for queries spread over A is all of it); the contracted
   // one adds a sort of 2q endpoints and a pass over A_Q, so the plain one is
@@ -269,6 +332,13 @@ rmq_status rmq_plan(int64_t n, int64_t q, int32_t* block_size, int32_t* path) {
   if (block_size) *block_size = default_block_full(n);
   if (path) *path = RMQ_PATH_FULL;
   return RMQ_OK;
+}
+
+int32_t rmq_default_block(int64_t n, int64_t q, int32_t path) {
+  if (n < 1 || n > RMQ_MAX_N || q < 0 || q > RMQ_MAX_Q) return 0;
+  if (path == RMQ_PATH_FULL) return default_block_full(n);
+  if (path == RMQ_PATH_CONTRACTED) return default_block_contracted(q);
+  return 0;
 }
 
 size_t rmq_workspace_bytes(int64_t n, int64_t q, const rmq_options* opt) {
@@ -443,31 +513,41 @@ rmq_status rmq_sort_endpoints(const int32_t* L, const int32_t* R, int64_t q, int
 }
 
 rmq_status rmq_contract(const int32_t* A, int64_t n, const int32_t* pos, const int32_t* tag,
-                        int64_t q, int32_t* Lc, int32_t* Rc, uint64_t* aq, void* stream) {
+                        int64_t q, int32_t* LR, uint64_t* aq, void* stream) {
   if (!A || n < 1 || n > RMQ_MAX_N || q < 0 || q > RMQ_MAX_Q) return RMQ_ERR_INVALID_ARG;
   if (q == 0) return RMQ_OK;
-  if (!pos || !tag || !Lc || !Rc || !aq) return RMQ_ERR_INVALID_ARG;
-  if (!aligned_to(A, 4) || !aligned_to(aq, 8)) return RMQ_ERR_MISALIGNED;
+  if (!pos || !tag || !LR || !aq) return RMQ_ERR_INVALID_ARG;
+  if (!aligned_to(A, 4) || !aligned_to(pos, 4) || !aligned_to(tag, 4) || !aligned_to(LR, 8) ||
+      !aligned_to(aq, 8))
+    return RMQ_ERR_MISALIGNED;
   hipStream_t s = static_cast<hipStream_t>(stream);
   prepare_pool();
-  void* tiles = nullptr;
-  hipError_t e = hipMallocAsync(&tiles, contract_tile_start_bytes(n), s);
+  const size_t sort_b = align_up(sort_workspace_bytes(q));
+  void* scratch = nullptr;
+  hipError_t e = hipMallocAsync(&scratch, sort_b + contract_tile_start_bytes(n), s);
   if (e != hipSuccess) return from_hip(e);
-  e = launch_contract(A, n, pos, tag, q, Lc, Rc, aq, static_cast<int32_t*>(tiles), s);
-  hipFreeAsync(tiles, s);
+  char* w = static_cast<char*>(scratch);
+  e = launch_remap(tag, q, LR, w, sort_b, s);
+  if (e == hipSuccess)
+    e = launch_contract(A, n, pos, q, aq, reinterpret_cast<int32_t*>(w + sort_b), s);
+  hipFreeAsync(scratch, s);
   return from_hip(e);
 }
 
 // ---- timers ----
 rmq_status rmq_timer_create(rmq_timer** t) {
   if (!t) return RMQ_ERR_INVALID_ARG;
-  rmq_timer_s* x = static_cast<rmq_timer_s*>(calloc(1, sizeof(rmq_timer_s)));
+  rmq_timer_s* x = new (std::nothrow) rmq_timer_s();
   if (!x) return RMQ_ERR_OUT_OF_MEMORY;
-  for (int i = 0; i <= RMQ_NUM_STAGES; ++i) {
-    hipError_t e = hipEventCreate(&x->ev[i]);
+  for (int i = 0; i < RMQ_NUM_STAGES; ++i) {
+    hipError_t e = hipEventCreate(&x->clock[i].start);
+    if (e == hipSuccess) e = hipEventCreate(&x->clock[i].stop);
     if (e != hipSuccess) {
-      for (int j = 0; j < i; ++j) hipEventDestroy(x->ev[j]);
-      free(x);
+      for (int j = 0; j <= i; ++j) {
+        if (x->clock[j].start) hipEventDestroy(x->clock[j].start);
+        if (x->clock[j].stop) hipEventDestroy(x->clock[j].stop);
+      }
+      delete x;
       return from_hip(e);
     }
   }
@@ -477,18 +557,25 @@ rmq_status rmq_timer_create(rmq_timer** t) {
 
 rmq_status rmq_timer_read(rmq_timer* t, float* stage_ms, float* total_ms) {
   if (!t || !t->armed) return RMQ_ERR_INVALID_ARG;
-  hipError_t e = hipEventSynchronize(t->ev[RMQ_NUM_STAGES]);
+  int first = -1, last = -1;
+  for (int i = 0; i < RMQ_NUM_STAGES; ++i)
+    if (t->ran[i]) {
+      if (first < 0) first = i;
+      last = i;
+    }
+  if (first < 0) return RMQ_ERR_INVALID_ARG;
+  hipError_t e = hipEventSynchronize(t->clock[last].stop);
   if (e != hipSuccess) return from_hip(e);
   for (int i = 0; i < RMQ_NUM_STAGES; ++i) {
     float ms = 0.f;
     if (t->ran[i]) {
-      e = hipEventElapsedTime(&ms, t->ev[i], t->ev[i + 1]);
+      e = hipEventElapsedTime(&ms, t->clock[i].start, t->clock[i].stop);
       if (e != hipSuccess) return from_hip(e);
     }
     if (stage_ms) stage_ms[i] = ms;
   }
   if (total_ms) {
-    e = hipEventElapsedTime(total_ms, t->ev[0], t->ev[RMQ_NUM_STAGES]);
+    e = hipEventElapsedTime(total_ms, t->clock[first].start, t->clock[last].stop);
     if (e != hipSuccess) return from_hip(e);
   }
   return RMQ_OK;
@@ -496,9 +583,204 @@ rmq_status rmq_timer_read(rmq_timer* t, float* stage_ms, float* total_ms) {
 
 rmq_status rmq_timer_destroy(rmq_timer* t) {
   if (!t) return RMQ_ERR_INVALID_ARG;
-  for (int i = 0; i <= RMQ_NUM_STAGES; ++i) hipEventDestroy(t->ev[i]);
-  free(t);
+  for (int i = 0; i < RMQ_NUM_STAGES; ++i) {
+    hipEventDestroy(t->clock[i].start);
+    hipEventDestroy(t->clock[i].stop);
+  }
+  delete t;
   return RMQ_OK;
+}
+
+}  // extern "C"
+
+// ---- batches of arrays ----
+struct rmq_batch_s {
+  int device;
+  std::vector<rmq_batch_item> items;
+  std::vector<Plan> plans;
+  std::vector<size_t> ws_off;  // per item, into ws
+  char* ws = nullptr;          // device scratch for every item
+  size_t ws_bytes = 0;
+  // plain-path items, run together by the batched kernels
+  std::vector<int> full_items;
+  ArrayDesc* d_desc = nullptr;  // device copy of their descriptors
+  int64_t* d_prefix = nullptr;  // device prefix tables (see below)
+  int64_t total_wg = 0, total_q = 0;
+  int rounds = 0;
+  int64_t round_tiles[ST_MAX_ROUNDS] = {};
+  size_t off_wg = 0, off_q = 0, off_round[ST_MAX_ROUNDS] = {};
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+};
+
+namespace {
+
+rmq_status batch_enqueue(rmq_batch b, int mode, hipStream_t s) {
+  if (mode == RMQ_BATCH_FUSED) {
+    const int cnt = (int)b->full_items.size();
+    if (cnt > 0) {
+      hipError_t e = launch_blockmin_multi(b->d_desc, b->d_prefix + b->off_wg, cnt, b->total_wg, s);
+      for (int r = 0; e == hipSuccess && r < b->rounds; ++r)
+        e = launch_sparse_table_multi(b->d_desc, b->d_prefix + b->off_round[r], cnt, r,
+                                      b->round_tiles[r], s);
+      if (e == hipSuccess)
+        e = launch_query_multi(b->d_desc, b->d_prefix + b->off_q, cnt, b->total_q, nullptr,
+                               nullptr, s);
+      if (e != hipSuccess) return from_hip(e);
+    }
+  }
+  for (size_t i = 0; i < b->items.size(); ++i) {
+    const Plan& p = b->plans[i];
+    if (mode == RMQ_BATCH_FUSED && p.path == RMQ_PATH_FULL) continue;
+    const rmq_batch_item& it = b->items[i];
+    if (it.q == 0) continue;
+    char* w = b->ws + b->ws_off[i];
+    rmq_status st = p.path == RMQ_PATH_FULL
+                        ? run_full(it.A, it.n, it.L, it.R, it.q, it.out, s, nullptr, p, w)
+                        : run_contracted(it.A, it.n, it.L, it.R, it.q, it.out, s, nullptr, p, w);
+    if (st != RMQ_OK) return st;
+  }
+  return RMQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rmq_status rmq_batch_create(const rmq_batch_item* items, int32_t count, rmq_batch* out) {
+  if (!items || !out || count < 1) return RMQ_ERR_INVALID_ARG;
+  for (int32_t i = 0; i < count; ++i) {
+    const rmq_batch_item& it = items[i];
+    if (!it.A || it.n < 1 || it.n > RMQ_MAX_N || it.q < 0 || it.q > RMQ_MAX_Q)
+      return RMQ_ERR_INVALID_ARG;
+    if (it.q > 0 && (!it.L || !it.R || !it.out)) return RMQ_ERR_INVALID_ARG;
+    if (!aligned_to(it.A, 4) ||
+        (it.q && (!aligned_to(it.L, 4) || !aligned_to(it.R, 4) || !aligned_to(it.out, 4))))
+      return RMQ_ERR_MISALIGNED;
+  }
+  rmq_batch_s* b = new (std::nothrow) rmq_batch_s();
+  if (!b) return RMQ_ERR_OUT_OF_MEMORY;
+  hipGetDevice(&b->device);
+  b->items.assign(items, items + count);
+  b->plans.resize(count);
+  b->ws_off.resize(count);
+  size_t off = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    rmq_options o{};
+    o.block_size = items[i].block_size;
+    o.path = items[i].path;
+    rmq_status st = make_plan(items[i].n, items[i].q, &o, &b->plans[i]);
+    if (st != RMQ_OK) {
+      delete b;
+      return st;
+    }
+    b->ws_off[i] = off;
+    off = align_up(off + plan_bytes(items[i].n, items[i].q, b->plans[i]));
+    if (b->plans[i].path == RMQ_PATH_FULL) b->full_items.push_back(i);
+  }
+  b->ws_bytes = off;
+
+  // descriptors and prefix tables of the plain-path items
+  const int cnt = (int)b->full_items.size();
+  std::vector<ArrayDesc> desc(cnt);
+  std::vector<int64_t> wg(cnt + 1, 0), qp(cnt + 1, 0);
+  std::vector<std::vector<int64_t>> rt(ST_MAX_ROUNDS, std::vector<int64_t>(cnt + 1, 0));
+  for (int c = 0; c < cnt; ++c) {
+    const int i = b->full_items[c];
+    const rmq_batch_item& it = items[i];
+    const FullLayout f = full_layout(it.n, b->plans[i].k);
+    desc[c] = ArrayDesc{it.A, it.n, b->plans[i].kshift, f.levels, f.nb, nullptr,
+                        it.L, it.R, it.q, it.out};
+    wg[c + 1] = wg[c] + blockmin_grid(it.n, b->plans[i].kshift, 4);
+    qp[c + 1] = qp[c] + it.q;
+    const int rounds = st_rounds(f.levels);
+    if (rounds > ST_MAX_ROUNDS) {
+      delete b;
+      return RMQ_ERR_INVALID_ARG;
+    }
+    if (rounds > b->rounds) b->rounds = rounds;
+    for (int r = 0; r < ST_MAX_ROUNDS; ++r)
+      rt[r][c + 1] = rt[r][c] + st_round_tiles(f.nb, f.levels, r);
+  }
+  b->total_wg = wg[cnt];
+  b->total_q = qp[cnt];
+  for (int r = 0; r < ST_MAX_ROUNDS; ++r) b->round_tiles[r] = rt[r][cnt];
+  const size_t desc_bytes = align_up(sizeof(ArrayDesc) * (size_t)(cnt > 0 ? cnt : 1));
+  const size_t table_len = (size_t)(cnt + 1);
+  b->off_wg = 0;
+  b->off_q = table_len;
+  for (int r = 0; r < ST_MAX_ROUNDS; ++r) b->off_round[r] = (2 + r) * table_len;
+  const size_t prefix_bytes = sizeof(int64_t) * table_len * (2 + ST_MAX_ROUNDS);
+
+  void* mem = nullptr;
+  hipError_t e = hipMalloc(&mem, b->ws_bytes + desc_bytes + prefix_bytes);
+  if (e != hipSuccess) {
+    delete b;
+    return from_hip(e);
+  }
+  b->ws = static_cast<char*>(mem);
+  b->d_desc = reinterpret_cast<ArrayDesc*>(b->ws + b->ws_bytes);
+  b->d_prefix = reinterpret_cast<int64_t*>(b->ws + b->ws_bytes + desc_bytes);
+  for (int c = 0; c < cnt; ++c)
+    desc[c].st = reinterpret_cast<uint64_t*>(b->ws + b->ws_off[b->full_items[c]]);
+  std::vector<int64_t> prefix(table_len * (2 + ST_MAX_ROUNDS));
+  for (size_t c = 0; c < table_len; ++c) {
+    prefix[b->off_wg + c] = wg[c];
+    prefix[b->off_q + c] = qp[c];
+    for (int r = 0; r < ST_MAX_ROUNDS; ++r) prefix[b->off_round[r] + c] = rt[r][c];
+  }
+  if (cnt > 0) e = hipMemcpy(b->d_desc, desc.data(), sizeof(ArrayDesc) * cnt, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(b->d_prefix, prefix.data(), prefix_bytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    hipFree(mem);
+    delete b;
+    return from_hip(e);
+  }
+  *out = b;
+  return RMQ_OK;
+}
+
+rmq_status rmq_batch_run(rmq_batch b, int32_t mode, int32_t use_graph, void* stream) {
+  if (!b || (mode != RMQ_BATCH_FUSED && mode != RMQ_BATCH_PER_ITEM)) return RMQ_ERR_INVALID_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (!use_graph) return batch_enqueue(b, mode, s);
+  if (!s) return RMQ_ERR_INVALID_ARG;  // capture needs a stream of its own
+  if (!b->graph[mode]) {
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return from_hip(e);
+    rmq_status st = batch_enqueue(b, mode, s);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(s, &g);
+    if (st != RMQ_OK) {
+      if (g) hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return from_hip(e);
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) return from_hip(e);
+    b->graph[mode] = x;
+  }
+  return from_hip(hipGraphLaunch(b->graph[mode], s));
+}
+
+rmq_status rmq_batch_item_plan(rmq_batch b, int32_t i, int32_t* block_size, int32_t* path) {
+  if (!b || i < 0 || i >= (int32_t)b->items.size()) return RMQ_ERR_INVALID_ARG;
+  if (block_size) *block_size = b->plans[i].k;
+  if (path) *path = b->plans[i].path;
+  return RMQ_OK;
+}
+
+size_t rmq_batch_workspace_bytes(rmq_batch b) { return b ? b->ws_bytes : 0; }
+
+rmq_status rmq_batch_free(rmq_batch b) {
+  if (!b) return RMQ_ERR_INVALID_ARG;
+  for (int m = 0; m < 2; ++m)
+    if (b->graph[m]) hipGraphExecDestroy(b->graph[m]);
+  hipError_t e = hipFree(b->ws);
+  delete b;
+  return from_hip(e);
 }
 
 }  // extern "C"

@@ -7,8 +7,7 @@
 // ending at p (several, when endpoints repeat: the repeated ones span the
 // single element p).
 //
-// k_remap (one thread per sorted slot s):
-//   * Lc[i] = s for the left end of query i, Rc[i] = s - 1 for its right end;
+// k_tiles (one thread per sorted slot s):
 //   * A_Q[s] = +inf for each area that spans two or more contraction tiles
 //     (those are finished with atomicMin by several waves);
 //   * tile_start[t] = index of the first endpoint >= t * T (written by the
@@ -34,41 +33,45 @@ constexpr int TSHIFT = 10;
 constexpr int T = 1 << TSHIFT;  // contraction tile (elements of A per wave)
 constexpr int EPL = T / 64;     // elements per lane
 
-__global__ __launch_bounds__(WG) void k_remap(const int32_t* __restrict__ pos,
-                                              const int32_t* __restrict__ tag, int64_t M,
-                                              int32_t* __restrict__ Lc, int32_t* __restrict__ Rc,
+// One thread per 4 consecutive slots s = 4i .. 4i+3 (and the past-the-end
+// slot M, which closes the tile table).
+__global__ __launch_bounds__(WG) void k_tiles(const int32_t* __restrict__ pos, int64_t M,
                                               uint64_t* __restrict__ aq,
                                               int32_t* __restrict__ tile_start,
                                               int64_t num_tiles) {
-  const int64_t s = (int64_t)blockIdx.x * WG + threadIdx.x;
-  if (s > M) return;
-  if (s < M) {
-    const int32_t t = tag[s];
-    if (t >= 0 && t < M) {  // a sorted list holds every tag once
-      if (t & 1)
-        Rc[t >> 1] = (int32_t)(s - 1);
-      else
-        Lc[t >> 1] = (int32_t)s;
-    }
-  }
+  const int64_t s0 = ((int64_t)blockIdx.x * WG + threadIdx.x) * 4;
+  if (s0 > M) return;
   // positions of a sorted list lie in [0, n); clamping only guards the
   // writes below against a malformed list
   const int64_t last = num_tiles * T - 1;
   auto clampp = [last](int64_t e) { return e < 0 ? 0 : (e > last ? last : e); };
-  const int64_t e_prev = s > 0 ? clampp(pos[s - 1]) : -1;
-  const int64_t e_cur = s < M ? clampp(pos[s]) : -1;
-  if (s + 1 < M) {
-    const int64_t e_next = clampp(pos[s + 1]);
-    if ((e_cur >> TSHIFT) != (e_next >> TSHIFT)) aq[s] = KEY_NONE;
+  int64_t e[6];  // pos[s0-1 .. s0+4]
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    const int64_t s = s0 - 1 + i;
+    e[i] = (s >= 0 && s < M) ? clampp(pos[s]) : -1;
   }
-  // tiles t with e_prev < t*T <= e_cur get tile_start[t] = s
-  const int64_t t_lo = s == 0 ? 0 : (e_prev >> TSHIFT) + 1;
-  const int64_t t_hi = s == M ? num_tiles : (e_cur >> TSHIFT);
-  for (int64_t t = t_lo; t <= t_hi; ++t) tile_start[t] = (int32_t)s;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t s = s0 + i;
+    if (s > M) break;
+    const int64_t e_prev = e[i], e_cur = e[i + 1];
+    if (s + 1 < M && (e_cur >> TSHIFT) != (e[i + 2] >> TSHIFT)) aq[s] = KEY_NONE;
+    // tiles t with e_prev < t*T <= e_cur get tile_start[t] = s
+    const int64_t t_lo = s == 0 ? 0 : (e_prev >> TSHIFT) + 1;
+    const int64_t t_hi = s == M ? num_tiles : (e_cur >> TSHIFT);
+    for (int64_t t = t_lo; t <= t_hi; ++t) tile_start[t] = (int32_t)s;
+  }
 }
 
-__device__ __forceinline__ int32_t load_elem(const int32_t* __restrict__ A, int64_t p, int64_t n) {
-  return p < n ? A[p] : INT32_MAX;
+// A[p..p+3], elements past n read as INT32_MAX (never part of an area).
+__device__ __forceinline__ v4i32 load4(const int32_t* __restrict__ A, int64_t p, int64_t n,
+                                       bool aligned) {
+  if (aligned && p + 3 < n) return load_stream(A + p);
+  v4i32 x;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) x[i] = p + i < n ? A[p + i] : INT32_MAX;
+  return x;
 }
 
 __global__ __launch_bounds__(WG) void k_contract(const int32_t* __restrict__ A, int64_t n,
@@ -76,6 +79,7 @@ __global__ __launch_bounds__(WG) void k_contract(const int32_t* __restrict__ A, 
                                                  const int32_t* __restrict__ tile_start,
                                                  int64_t num_tiles, uint64_t* __restrict__ aq) {
   __shared__ __align__(16) int32_t head_last[WG / 64][T];
+  __shared__ __align__(16) int32_t vals[WG / 64][T];
   const int lane = lane_id(), wave = threadIdx.x >> 6;
   const int64_t tile = (int64_t)blockIdx.x * (WG / 64) + wave;
   const bool tile_ok = tile < num_tiles;
@@ -86,11 +90,42 @@ __global__ __launch_bounds__(WG) void k_contract(const int32_t* __restrict__ A, 
   jend = jend < jlo ? jlo : (jend > M ? M : jend);
   // tiles wholly before E_0 (jend == 0) or after E_{M-1} (jlo == M) hold no area
   const bool active = tile_ok && jend > 0 && jlo < M;
+  const bool marked = active && jend > jlo;  // the tile holds endpoints
+  const int64_t last_area = M - 2;           // valid areas are 0 .. M-2
   int32_t* hl = head_last[wave];
+  int32_t* xs = vals[wave];
 
-  for (int c = lane; c < T; c += 64) hl[c] = -1;
+  // coalesced 16-byte loads: lane l holds elements 4l + 256c + (0..3)
+  const bool aligned = ((uintptr_t)A & 15) == 0;
+  v4i32 xv[4];
+  if (tile_ok) {  // issued before the tile's endpoint range is known
+#pragma unroll
+    for (int c = 0; c < 4; ++c) xv[c] = load4(A, t0 + c * 256 + lane * 4, n, aligned);
+  }
+
+  if (active && !marked) {
+    // no endpoint inside: the whole tile lies in area jlo - 1
+    uint64_t m = KEY_NONE;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t p = t0 + c * 256 + lane * 4 + i;
+        if (p < n) m = umin64(m, make_key(xv[c][i], (uint32_t)p));
+      }
+    m = group_min_u64<64>(m);
+    const int64_t area = jlo - 1;
+    if (lane == 63 && area >= 0 && area <= last_area)
+      atomicMin((unsigned long long*)&aq[area], (unsigned long long)m);
+  }
+
+  if (marked) {
+    for (int c = lane; c < T; c += 64) hl[c] = -1;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) *reinterpret_cast<v4i32*>(xs + c * 256 + lane * 4) = xv[c];
+  }
   __syncthreads();
-  if (active) {
+  if (marked) {
     for (int64_t j = jlo + lane; j < jend; j += 64) {
       const int32_t e = E[j];
       const bool last_dup = (j + 1 == M) || (E[j + 1] != e);
@@ -98,32 +133,20 @@ __global__ __launch_bounds__(WG) void k_contract(const int32_t* __restrict__ A, 
     }
   }
   __syncthreads();
-  if (!active) return;  // whole wave leaves together; no barrier follows
+  if (!marked) return;  // whole wave leaves together; no barrier follows
 
-  // ---- per lane: its endpoint slots and elements ----
+  // ---- per lane: 16 consecutive elements and their endpoint slots ----
   const int64_t p0 = t0 + (int64_t)lane * EPL;
-  int32_t h[EPL];
+  int32_t h[EPL], x[EPL];
 #pragma unroll
   for (int c = 0; c < EPL; c += 4) {
-    const int4 v = *reinterpret_cast<const int4*>(hl + lane * EPL + c);
-    h[c] = v.x;
-    h[c + 1] = v.y;
-    h[c + 2] = v.z;
-    h[c + 3] = v.w;
-  }
-  int32_t x[EPL];
-  if (((uintptr_t)A & 15) == 0 && p0 + EPL <= n) {
+    const v4i32 hv = *reinterpret_cast<const v4i32*>(hl + lane * EPL + c);
+    const v4i32 v = *reinterpret_cast<const v4i32*>(xs + lane * EPL + c);
 #pragma unroll
-    for (int c = 0; c < EPL; c += 4) {
-      const v4i32 v = load_stream(A + p0 + c);
-      x[c] = v[0];
-      x[c + 1] = v[1];
-      x[c + 2] = v[2];
-      x[c + 3] = v[3];
+    for (int i = 0; i < 4; ++i) {
+      h[c + i] = hv[i];
+      x[c + i] = v[i];
     }
-  } else {
-#pragma unroll
-    for (int c = 0; c < EPL; ++c) x[c] = load_elem(A, p0 + c, n);
   }
   int32_t last_head = -1;
   bool has_head = false;
@@ -144,7 +167,6 @@ __global__ __launch_bounds__(WG) void k_contract(const int32_t* __restrict__ A, 
   const int64_t in_area = below ? (int64_t)from_below : jlo - 1;
 
   // ---- walk the lane's elements ----
-  const int64_t last_area = M - 2;  // valid areas are 0 .. M-2
   uint64_t in_key = KEY_NONE, out_key = KEY_NONE;
   int64_t cur = in_area;
   bool seen = false;
@@ -203,20 +225,18 @@ __global__ __launch_bounds__(WG) void k_contract(const int32_t* __restrict__ A, 
 
 }  // namespace
 
-hipError_t launch_contract(const int32_t* A, int64_t n, const int32_t* pos, const int32_t* tag,
-                           int64_t q, int32_t* Lc, int32_t* Rc, uint64_t* aq, int32_t* tile_start,
-                           hipStream_t stream) {
+hipError_t launch_contract(const int32_t* A, int64_t n, const int32_t* pos, int64_t q,
+                           uint64_t* aq, int32_t* tile_start, hipStream_t stream) {
   if (q <= 0) return hipSuccess;
   const int64_t M = 2 * q;
   const int64_t num_tiles = (n + T - 1) / T;
-  hipLaunchKernelGGL(k_remap, dim3((unsigned)((M + 1 + WG - 1) / WG)), dim3(WG), 0, stream, pos,
-                     tag, M, Lc, Rc, aq, tile_start, num_tiles);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  const int64_t threads = M / 4 + 1;  // slots 0 .. M, four per thread
+  RMQ_TRY(launch(k_tiles, dim3((unsigned)((threads + WG - 1) / WG)), dim3(WG), 0, stream, pos, M,
+                 aq, tile_start, num_tiles));
   const int64_t grid = (num_tiles + (WG / 64) - 1) / (WG / 64);
-  hipLaunchKernelGGL(k_contract, dim3((unsigned)grid), dim3(WG), 0, stream, A, n, pos, M,
-                     tile_start, num_tiles, aq);
-  return hipGetLastError();
+  RMQ_TRY(launch(k_contract, dim3((unsigned)grid), dim3(WG), 0, stream, A, n, pos, M, tile_start,
+                 num_tiles, aq));
+  return hipSuccess;
 }
 
 size_t contract_tile_start_bytes(int64_t n) {

@@ -96,6 +96,21 @@ __device__ __forceinline__ v2u64 load_stream(const uint64_t* p) {
   return __builtin_nontemporal_load(reinterpret_cast<const v2u64*>(p));
 }
 
+// Largest j in [0, count) with prefix[j] <= x, for a non-decreasing prefix
+// table with prefix[0] = 0 (binary search; the table stays in cache).
+__device__ __forceinline__ int find_item(const int64_t* __restrict__ prefix, int count,
+                                         int64_t x) {
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= x)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
 // Floor log2 for x >= 1.
 __device__ __forceinline__ int ilog2_u64(uint64_t x) { return 63 - __clzll(x); }
 

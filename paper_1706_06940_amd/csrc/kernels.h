@@ -1,11 +1,80 @@
 // Host-side launchers of the device kernels (internal to the library).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
 
+#include <tuple>
+
 namespace rmq {
+
+// Optional per-stage clock: while set (by the host API, per thread), every
+// launch of a stage records `stop` at its end, and the first one also
+// records `start` at its beginning -- the events sit on the kernels
+// themselves, so a stage's time is pure kernel time.
+struct StageClock {
+  hipEvent_t start = nullptr;
+  hipEvent_t stop = nullptr;
+  bool started = false;
+};
+extern thread_local StageClock* tl_clock;
+
+// Launch on `stream`.  With a stage clock armed the launch goes through
+// hipExtLaunchKernel, which records the clock's events on the kernel itself;
+// otherwise through hipLaunchKernel (the form stream capture records as a
+// plain kernel node).
+template <typename... KArgs, typename... Args>
+inline hipError_t launch(void (*kernel)(KArgs...), dim3 grid, dim3 block, uint32_t lds,
+                         hipStream_t stream, Args... args) {
+  StageClock* c = tl_clock;
+  if (c) {
+    hipEvent_t start = c->started ? nullptr : c->start;
+    c->started = true;
+    hipExtLaunchKernelGGL(kernel, grid, block, lds, stream, start, c->stop, 0u,
+                          static_cast<KArgs>(args)...);
+    return hipGetLastError();
+  }
+  std::tuple<KArgs...> vals{static_cast<KArgs>(args)...};
+  void* ptrs[sizeof...(KArgs)];
+  std::apply(
+      [&ptrs](auto&... x) {
+        int i = 0;
+        ((ptrs[i++] = static_cast<void*>(&x)), ...);
+      },
+      vals);
+  return hipLaunchKernel(reinterpret_cast<const void*>(kernel), grid, block, ptrs, lds, stream);
+}
+
+#define RMQ_TRY(expr)                       \
+  do {                                      \
+    hipError_t rmq_err_ = (expr);           \
+    if (rmq_err_ != hipSuccess) return rmq_err_; \
+  } while (0)
+
+// One array of a batch on the device: its input, its block Sparse Table
+// (level-major, levels x nb keys) and its queries.
+struct ArrayDesc {
+  const int32_t* A;
+  int64_t n;
+  int32_t kshift;
+  int32_t levels;
+  int64_t nb;
+  uint64_t* st;
+  const int32_t* L;
+  const int32_t* R;
+  int64_t q;
+  int32_t* out;
+};
+
+// Sparse Table rounds: round r builds levels j0(r)+1 .. j0(r)+t; j0 = 0,
+// 10, 16, 22, ... for every table (see sparse_table.hip).
+constexpr int ST_MAX_ROUNDS = 6;
+int st_round_j0(int r);
+int st_rounds(int levels);
+int64_t st_round_tiles(int64_t nb, int levels, int r);
+size_t st_round_lds(int r);
 
 // ---- non-contracted path (Section 3.2) ----
 hipError_t launch_blockmin_i32(const int32_t* A, int64_t n, int kshift, uint64_t* keys,
@@ -13,6 +82,18 @@ hipError_t launch_blockmin_i32(const int32_t* A, int64_t n, int kshift, uint64_t
 hipError_t launch_blockmin_keys(const uint64_t* S, int64_t m, int kshift, uint64_t* keys,
                                 hipStream_t stream);
 hipError_t launch_sparse_table(uint64_t* st, int64_t nb, int levels, hipStream_t stream);
+int64_t blockmin_grid(int64_t n, int kshift, int elems_per_lane_load);
+// Batched forms: one launch per phase for all arrays of a batch.  The
+// prefix tables (count + 1 entries, starting at 0) give each array's first
+// workgroup / tile / query in the launch.
+hipError_t launch_blockmin_multi(const ArrayDesc* items, const int64_t* wg_prefix, int count,
+                                 int64_t total_wg, hipStream_t stream);
+hipError_t launch_sparse_table_multi(const ArrayDesc* items, const int64_t* tile_prefix,
+                                     int count, int round, int64_t total_tiles,
+                                     hipStream_t stream);
+hipError_t launch_query_multi(const ArrayDesc* items, const int64_t* q_prefix, int count,
+                              int64_t total_q, int64_t* bad_count, uint64_t* stats,
+                              hipStream_t stream);
 hipError_t launch_query_full(const int32_t* A, int64_t n, int kshift, const uint64_t* st,
                              int64_t nb, const int32_t* L, const int32_t* R, int64_t q,
                              int32_t* out, int64_t* bad_count, uint64_t* stats,
@@ -24,16 +105,18 @@ size_t sort_workspace_bytes(int64_t q);
 hipError_t launch_sort_endpoints(const int32_t* L, const int32_t* R, int64_t q, int64_t n,
                                  int32_t* pos, int32_t* tag, void* ws, size_t ws_bytes,
                                  hipStream_t stream);
-// Remap + contraction: Lc/Rc, A_Q over closed areas between endpoints.
+// Remap: LR[2i] = Lc[i], LR[2i+1] = Rc[i] from the sorted tags; uses the
+// sort's workspace.
+hipError_t launch_remap(const int32_t* tag, int64_t q, int32_t* LR, void* ws, size_t ws_bytes,
+                        hipStream_t stream);
+// Contraction: A_Q over the closed areas between consecutive endpoints.
 // tile_start: scratch of contract_tile_start_bytes(n).
 size_t contract_tile_start_bytes(int64_t n);
-hipError_t launch_contract(const int32_t* A, int64_t n, const int32_t* pos, const int32_t* tag,
-                           int64_t q, int32_t* Lc, int32_t* Rc, uint64_t* aq, int32_t* tile_start,
-                           hipStream_t stream);
+hipError_t launch_contract(const int32_t* A, int64_t n, const int32_t* pos, int64_t q,
+                           uint64_t* aq, int32_t* tile_start, hipStream_t stream);
 hipError_t launch_query_contracted(const uint64_t* aq, int64_t m, int64_t n, int kshift,
                                    const uint64_t* st, int64_t nb, const int32_t* L,
-                                   const int32_t* R, const int32_t* Lc, const int32_t* Rc,
-                                   int64_t q, int32_t* out, int64_t* bad_count, uint64_t* stats,
-                                   hipStream_t stream);
+                                   const int32_t* R, const int32_t* LR, int64_t q, int32_t* out,
+                                   int64_t* bad_count, uint64_t* stats, hipStream_t stream);
 
 }  // namespace rmq

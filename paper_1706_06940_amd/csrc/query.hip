@@ -47,10 +47,15 @@ struct SrcA {
     }
     return x;
   }
-  // min key over A[lo..hi], whole wave cooperating (lo, hi wave-uniform).
-  __device__ uint64_t scan(int64_t lo, int64_t hi, int lane, bool aligned) const {
+  // This lane's source as seen by the whole wave (for a wave-wide scan).
+  __device__ __forceinline__ SrcA broadcast(int src_lane) const {
+    return {reinterpret_cast<const int32_t*>(readlane64((int64_t)(uintptr_t)A, src_lane)),
+            readlane64(len, src_lane)};
+  }
+  // min key over A[lo..hi], whole wave cooperating (everything wave-uniform).
+  __device__ uint64_t scan(int64_t lo, int64_t hi, int lane) const {
     uint64_t best = KEY_NONE;
-    if (aligned) {
+    if (((uintptr_t)A & 15) == 0) {
       const int64_t a0 = lo & ~3ll;
       for (int64_t base = a0; base <= hi; base += 512) {
         const int64_t p0 = base + lane * 4, p1 = p0 + 256;
@@ -84,9 +89,13 @@ struct SrcKeys {
     return x;
   }
   __device__ __forceinline__ uint32_t pos_of(uint64_t key) const { return key_pos(key); }
-  __device__ uint64_t scan(int64_t lo, int64_t hi, int lane, bool aligned) const {
+  __device__ __forceinline__ SrcKeys broadcast(int src_lane) const {
+    return {reinterpret_cast<const uint64_t*>(readlane64((int64_t)(uintptr_t)S, src_lane)),
+            readlane64(len, src_lane)};
+  }
+  __device__ uint64_t scan(int64_t lo, int64_t hi, int lane) const {
     uint64_t best = KEY_NONE;
-    if (aligned) {
+    if (((uintptr_t)S & 15) == 0) {
       const int64_t a0 = lo & ~1ll;
       for (int64_t base = a0; base <= hi; base += 256) {
         const int64_t p0 = base + lane * 2, p1 = p0 + 128;
@@ -105,32 +114,20 @@ struct SrcKeys {
   }
 };
 
-// --- the kernel --------------------------------------------------------------
-// L, R: the queries' positions in A (validated here).  For the contracted
-// path, LI/RI hold their contracted index ranges; for the plain path LI == L
-// and RI == R.  src_len: number of source entries (n or 2q - 1).
+// --- the query step ----------------------------------------------------------
+// One lane's query [l, r] (positions in A, validated here) over source
+// entries [li, ri] of its table (st: level-major, nb blocks of 2^kshift
+// entries).  All 64 lanes of the wave must call this together: the partial
+// scans are done by the whole wave.  Lanes may belong to different tables
+// (batched launches); `live` is false for padding lanes.
 template <class Src>
-__global__ __launch_bounds__(WG) void k_query(Src src, int64_t src_len, int64_t n, int kshift,
-                                              const uint64_t* __restrict__ st, int64_t nb,
-                                              const int32_t* __restrict__ L,
-                                              const int32_t* __restrict__ R,
-                                              const int32_t* __restrict__ LI,
-                                              const int32_t* __restrict__ RI, int64_t q,
-                                              int32_t* __restrict__ out,
-                                              unsigned long long* __restrict__ bad_count,
-                                              unsigned long long* __restrict__ stats,
-                                              bool aligned) {
+__device__ __forceinline__ void query_core(const Src& src, int64_t src_len, int64_t n,
+                                           int kshift, const uint64_t* __restrict__ st,
+                                           int64_t nb, int64_t l, int64_t r, int64_t li,
+                                           int64_t ri, bool live, int32_t* outp,
+                                           unsigned long long* __restrict__ bad_count,
+                                           unsigned long long* __restrict__ stats) {
   const int lane = lane_id();
-  const int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
-  const bool live = i < q;
-
-  int64_t l = 0, r = -1, li = 0, ri = -1;
-  if (live) {
-    l = L[i];
-    r = R[i];
-    li = LI[i];
-    ri = RI[i];
-  }
   const bool ok = live && 0 <= l && l <= r && r < n && 0 <= li && li <= ri && ri < src_len;
 
   uint64_t best = KEY_NONE, kr = KEY_NONE;
@@ -181,7 +178,7 @@ __global__ __launch_bounds__(WG) void k_query(Src src, int64_t src_len, int64_t 
     const int src_lane = __builtin_ctzll(pend);
     pend &= pend - 1;
     const int64_t lo = readlane64(loL, src_lane), hi = readlane64(hiL, src_lane);
-    const uint64_t m = src.scan(lo, hi, lane, aligned);
+    const uint64_t m = src.broadcast(src_lane).scan(lo, hi, lane);
     if (lane == src_lane) best = umin64(best, m);
     n_scans += 1;
     n_elems += (uint64_t)(hi - lo + 1);
@@ -192,13 +189,13 @@ __global__ __launch_bounds__(WG) void k_query(Src src, int64_t src_len, int64_t 
     const int src_lane = __builtin_ctzll(pend);
     pend &= pend - 1;
     const int64_t lo = readlane64(loR, src_lane), hi = readlane64(hiR, src_lane);
-    const uint64_t m = src.scan(lo, hi, lane, aligned);
+    const uint64_t m = src.broadcast(src_lane).scan(lo, hi, lane);
     if (lane == src_lane) best = umin64(best, m);
     n_scans += 1;
     n_elems += (uint64_t)(hi - lo + 1);
   }
 
-  if (live) out[i] = ok ? (int32_t)src.pos_of(best) : -1;
+  if (live) *outp = ok ? (int32_t)src.pos_of(best) : -1;
 
   if (bad_count) {
     const uint64_t bad = ballot(live && !ok);
@@ -210,6 +207,59 @@ __global__ __launch_bounds__(WG) void k_query(Src src, int64_t src_len, int64_t 
   }
 }
 
+// One table.  L, R: the queries' positions in A.  For the contracted path, LR
+// holds their contracted index ranges as interleaved pairs (LR[2i],
+// LR[2i+1]); for the plain path LR is null and the ranges are [L[i], R[i]]
+// themselves.  src_len: number of source entries (n or 2q - 1).
+template <class Src>
+__global__ __launch_bounds__(WG) void k_query(Src src, int64_t src_len, int64_t n, int kshift,
+                                              const uint64_t* __restrict__ st, int64_t nb,
+                                              const int32_t* __restrict__ L,
+                                              const int32_t* __restrict__ R,
+                                              const int32_t* __restrict__ LR, int64_t q,
+                                              int32_t* __restrict__ out,
+                                              unsigned long long* __restrict__ bad_count,
+                                              unsigned long long* __restrict__ stats) {
+  const int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
+  const bool live = i < q;
+  int64_t l = 0, r = -1, li = 0, ri = -1;
+  if (live) {
+    l = L[i];
+    r = R[i];
+    if (LR) {
+      const int2 c = reinterpret_cast<const int2*>(LR)[i];
+      li = c.x;
+      ri = c.y;
+    } else {
+      li = l;
+      ri = r;
+    }
+  }
+  query_core(src, src_len, n, kshift, st, nb, l, r, li, ri, live, out + (live ? i : 0),
+             bad_count, stats);
+}
+
+// Every query of a batch of tables (plain path): global query g belongs to
+// the table whose range of the concatenated query list holds it.
+__global__ __launch_bounds__(WG) void k_query_multi(const ArrayDesc* __restrict__ items,
+                                                    const int64_t* __restrict__ q_prefix,
+                                                    int count,
+                                                    unsigned long long* __restrict__ bad_count,
+                                                    unsigned long long* __restrict__ stats) {
+  const int64_t g = (int64_t)blockIdx.x * WG + threadIdx.x;
+  const bool live = g < q_prefix[count];
+  const int j = live ? find_item(q_prefix, count, g) : 0;
+  const ArrayDesc& d = items[j];
+  const int64_t i = live ? g - q_prefix[j] : 0;
+  int64_t l = 0, r = -1;
+  if (live) {
+    l = d.L[i];
+    r = d.R[i];
+  }
+  query_core(SrcA{d.A, d.n}, d.n, d.n, d.kshift, d.st, d.nb, l, r, l, r, live, d.out + i,
+             bad_count, stats);
+}
+
 }  // namespace
 
 hipError_t launch_query_full(const int32_t* A, int64_t n, int kshift, const uint64_t* st,
@@ -218,25 +268,32 @@ hipError_t launch_query_full(const int32_t* A, int64_t n, int kshift, const uint
                              hipStream_t stream) {
   if (q <= 0) return hipSuccess;
   const int64_t grid = (q + WG - 1) / WG;
-  const bool aligned = ((uintptr_t)A & 15) == 0;
-  hipLaunchKernelGGL(k_query<SrcA>, dim3((unsigned)grid), dim3(WG), 0, stream, SrcA{A, n}, n, n,
-                     kshift, st, nb, L, R, L, R, q, out, (unsigned long long*)bad_count,
-                     (unsigned long long*)stats, aligned);
+  RMQ_TRY(launch(k_query<SrcA>, dim3((unsigned)grid), dim3(WG), 0, stream, SrcA{A, n}, n, n,
+                 kshift, st, nb, L, R, static_cast<const int32_t*>(nullptr), q, out,
+                 (unsigned long long*)bad_count, (unsigned long long*)stats));
   return hipGetLastError();
 }
 
 hipError_t launch_query_contracted(const uint64_t* aq, int64_t m, int64_t n, int kshift,
                                    const uint64_t* st, int64_t nb, const int32_t* L,
-                                   const int32_t* R, const int32_t* Lc, const int32_t* Rc,
-                                   int64_t q, int32_t* out, int64_t* bad_count, uint64_t* stats,
-                                   hipStream_t stream) {
+                                   const int32_t* R, const int32_t* LR, int64_t q, int32_t* out,
+                                   int64_t* bad_count, uint64_t* stats, hipStream_t stream) {
   if (q <= 0) return hipSuccess;
   const int64_t grid = (q + WG - 1) / WG;
-  const bool aligned = ((uintptr_t)aq & 15) == 0;
-  hipLaunchKernelGGL(k_query<SrcKeys>, dim3((unsigned)grid), dim3(WG), 0, stream, SrcKeys{aq, m}, m,
-                     n, kshift, st, nb, L, R, Lc, Rc, q, out, (unsigned long long*)bad_count,
-                     (unsigned long long*)stats, aligned);
+  RMQ_TRY(launch(k_query<SrcKeys>, dim3((unsigned)grid), dim3(WG), 0, stream, SrcKeys{aq, m}, m,
+                 n, kshift, st, nb, L, R, LR, q, out, (unsigned long long*)bad_count,
+                 (unsigned long long*)stats));
   return hipGetLastError();
+}
+
+hipError_t launch_query_multi(const ArrayDesc* items, const int64_t* q_prefix, int count,
+                              int64_t total_q, int64_t* bad_count, uint64_t* stats,
+                              hipStream_t stream) {
+  if (total_q <= 0) return hipSuccess;
+  const int64_t grid = (total_q + WG - 1) / WG;
+  RMQ_TRY(launch(k_query_multi, dim3((unsigned)grid), dim3(WG), 0, stream, items, q_prefix, count,
+                 (unsigned long long*)bad_count, (unsigned long long*)stats));
+  return hipSuccess;
 }
 
 }  // namespace rmq

@@ -1,4 +1,5 @@
-// Device LSD radix sort of the 2q query endpoints (Section 3.1 step 1).
+// Device LSD radix sort of the 2q query endpoints, and the remap that follows
+// it (Section 3.1 step 1).
 //
 // Item j of the endpoint list is (position, tag j): the left end of query i
 // is item 2i and its right end item 2i+1.  Sorting by position with a STABLE
@@ -15,8 +16,15 @@
 //              digit order and writes runs of equal digits contiguously.
 // Tiles are 4096 items: 4 waves x 16 rounds x 64 lanes, each wave owning a
 // contiguous quarter so that (wave, round, lane) order is item order.
-// The first pass reads L and R directly (invalid queries sort as position
-// 0; the query kernel re-checks them), the last writes the output arrays.
+// Workgroups are dealt round-robin over the 8 XCDs; tiles are numbered so that
+// each XCD gets a contiguous range of them, so the runs that neighbouring
+// tiles write for one digit meet in the same L2 and leave it as whole lines.
+//
+// Remap: slot s of the sorted list holding tag t gives Lc[t/2] = s (t even)
+// or Rc[t/2] = s - 1 (t odd).  Written directly these are 2q scattered 4-byte
+// stores; instead one more radix pass orders the (tag, slot) pairs by the top
+// bits of the tag, and the stores then go out window by window, each window
+// of the interleaved LR array written while it sits in one XCD's L2.
 #include "device.h"
 #include "kernels.h"
 
@@ -29,6 +37,23 @@ constexpr int ROUNDS = 16;
 constexpr int TILE = WG * ROUNDS;  // items per tile
 constexpr int RADIX_BITS = 8;
 constexpr int RADIX = 1 << RADIX_BITS;
+constexpr int NXCD = 8;
+
+// where a pass takes its items from
+enum Mode : int {
+  ARRAYS = 0,   // keys_in[j], vals_in[j]
+  QUERIES = 1,  // item j = (L[j/2] or R[j/2], j)
+  KEY_IDX = 2,  // keys_in[j], value j
+};
+
+// Tile handled by this workgroup: XCD x = blockIdx % 8 takes the x-th
+// contiguous range of tiles.  Returns -1 for the padding workgroups.
+__device__ __forceinline__ int64_t xcd_tile(int64_t num_tiles) {
+  const int64_t per = (num_tiles + NXCD - 1) / NXCD;
+  const int64_t t = (int64_t)(blockIdx.x % NXCD) * per + blockIdx.x / NXCD;
+  return t < num_tiles ? t : -1;
+}
+int64_t xcd_grid(int64_t num_tiles) { return ((num_tiles + NXCD - 1) / NXCD) * NXCD; }
 
 __device__ __forceinline__ int64_t item_index(int64_t tile0, int wave, int round, int lane) {
   return tile0 + (int64_t)wave * (64 * ROUNDS) + round * 64 + lane;
@@ -49,7 +74,22 @@ __device__ __forceinline__ void load_from_queries(const int32_t* __restrict__ L,
   val = (uint32_t)j;
 }
 
-template <bool FROM_Q>
+template <int MODE>
+__device__ __forceinline__ void load_item(const uint32_t* __restrict__ keys_in,
+                                          const uint32_t* __restrict__ vals_in,
+                                          const int32_t* __restrict__ L,
+                                          const int32_t* __restrict__ R, int64_t N, int64_t n,
+                                          int64_t j, uint32_t& key, uint32_t& val) {
+  if (MODE == QUERIES) {
+    load_from_queries(L, R, N, n, j, key, val);
+  } else {
+    const bool valid = j < N;
+    key = valid ? keys_in[j] : 0u;
+    val = MODE == KEY_IDX ? (uint32_t)j : (valid ? vals_in[j] : 0u);
+  }
+}
+
+template <int MODE>
 __global__ __launch_bounds__(WG) void k_radix_count(const uint32_t* __restrict__ keys_in,
                                                     const int32_t* __restrict__ L,
                                                     const int32_t* __restrict__ R, int64_t N,
@@ -57,23 +97,21 @@ __global__ __launch_bounds__(WG) void k_radix_count(const uint32_t* __restrict__
                                                     uint32_t* __restrict__ counts,
                                                     int64_t num_tiles) {
   __shared__ uint32_t hist[RADIX];
+  const int64_t tile = xcd_tile(num_tiles);
+  if (tile < 0) return;
   const int lane = lane_id(), wave = threadIdx.x >> 6;
-  const int64_t tile0 = (int64_t)blockIdx.x * TILE;
+  const int64_t tile0 = tile * TILE;
   const uint32_t mask = (1u << bits) - 1u;
   hist[threadIdx.x] = 0;
   __syncthreads();
   for (int rd = 0; rd < ROUNDS; ++rd) {
     const int64_t j = item_index(tile0, wave, rd, lane);
     uint32_t key, val;
-    if (FROM_Q) {
-      load_from_queries(L, R, N, n, j, key, val);
-    } else {
-      key = j < N ? keys_in[j] : 0u;
-    }
+    load_item<MODE == QUERIES ? QUERIES : KEY_IDX>(keys_in, nullptr, L, R, N, n, j, key, val);
     if (j < N) atomicAdd(&hist[(key >> shift) & mask], 1u);
   }
   __syncthreads();
-  counts[(int64_t)threadIdx.x * num_tiles + blockIdx.x] = hist[threadIdx.x];
+  counts[(int64_t)threadIdx.x * num_tiles + tile] = hist[threadIdx.x];
 }
 
 // Exclusive scan of 256 values held one per thread; returns the total.
@@ -127,7 +165,7 @@ __global__ __launch_bounds__(WG) void k_radix_rowscan(uint32_t* __restrict__ cou
   if (threadIdx.x == 0) row_total[blockIdx.x] = carry;
 }
 
-template <bool FROM_Q>
+template <int MODE>
 __global__ __launch_bounds__(WG) void k_radix_scatter(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
     const int32_t* __restrict__ L, const int32_t* __restrict__ R, int64_t N, int64_t n, int shift,
@@ -140,8 +178,10 @@ __global__ __launch_bounds__(WG) void k_radix_scatter(
   __shared__ uint32_t s_key[TILE];
   __shared__ uint32_t s_val[TILE];
 
+  const int64_t tile = xcd_tile(num_tiles);
+  if (tile < 0) return;
   const int lane = lane_id(), wave = threadIdx.x >> 6;
-  const int64_t tile0 = (int64_t)blockIdx.x * TILE;
+  const int64_t tile0 = tile * TILE;
   const uint32_t mask = (1u << bits) - 1u;
   const uint64_t lt = (1ull << lane) - 1ull;
 
@@ -154,12 +194,7 @@ __global__ __launch_bounds__(WG) void k_radix_scatter(
   for (int rd = 0; rd < ROUNDS; ++rd) {
     const int64_t j = item_index(tile0, wave, rd, lane);
     const bool valid = j < N;
-    if (FROM_Q) {
-      load_from_queries(L, R, N, n, j, key[rd], val[rd]);
-    } else {
-      key[rd] = valid ? keys_in[j] : 0u;
-      val[rd] = valid ? vals_in[j] : 0u;
-    }
+    load_item<MODE>(keys_in, vals_in, L, R, N, n, j, key[rd], val[rd]);
     const uint32_t d = (key[rd] >> shift) & mask;
     uint64_t match = ballot(valid);
     for (int b = 0; b < bits; ++b) {
@@ -189,7 +224,7 @@ __global__ __launch_bounds__(WG) void k_radix_scatter(
     local_start[d] = excl;
     uint32_t base_excl;
     block_exclusive_scan(row_total[d], tmp, base_excl);
-    global_start[d] = base_excl + counts[(int64_t)d * num_tiles + blockIdx.x];
+    global_start[d] = base_excl + counts[(int64_t)d * num_tiles + tile];
   }
   __syncthreads();
 
@@ -215,6 +250,23 @@ __global__ __launch_bounds__(WG) void k_radix_scatter(
     if ((int64_t)dst < N) {  // always true for consistent counts
       keys_out[dst] = k;
       vals_out[dst] = s_val[t];
+    }
+  }
+}
+
+// Remap writes from (tag, slot) pairs ordered by the top bits of the tag.
+__global__ __launch_bounds__(WG) void k_remap_apply(const uint32_t* __restrict__ tags,
+                                                    const uint32_t* __restrict__ slots,
+                                                    int64_t N, int32_t* __restrict__ LR,
+                                                    int64_t num_chunks) {
+  const int64_t chunk = xcd_tile(num_chunks);
+  if (chunk < 0) return;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t j = chunk * (4 * WG) + i * WG + threadIdx.x;
+    if (j < N) {
+      const uint32_t t = tags[j], s = slots[j];
+      if ((int64_t)t < N) LR[t] = (t & 1u) ? (int32_t)s - 1 : (int32_t)s;
     }
   }
 }
@@ -252,6 +304,34 @@ SortLayout sort_layout(int64_t q) {
   return s;
 }
 
+struct SortBufs {
+  uint32_t *tkey, *tval, *counts, *total;
+};
+
+SortBufs sort_bufs(const SortLayout& lay, void* ws) {
+  char* base = static_cast<char*>(ws);
+  return {reinterpret_cast<uint32_t*>(base + lay.off_key),
+          reinterpret_cast<uint32_t*>(base + lay.off_val),
+          reinterpret_cast<uint32_t*>(base + lay.off_counts),
+          reinterpret_cast<uint32_t*>(base + lay.off_total)};
+}
+
+// One stable pass: count, scan, scatter.
+template <int MODE>
+hipError_t radix_pass(const uint32_t* kin, const uint32_t* vin, const int32_t* L, const int32_t* R,
+                      int64_t N, int64_t n, int shift, int bits, const SortLayout& lay,
+                      const SortBufs& b, uint32_t* kout, uint32_t* vout, hipStream_t stream) {
+  const dim3 grid((unsigned)xcd_grid(lay.num_tiles)), block(WG);
+  RMQ_TRY(launch(k_radix_count<MODE>, grid, block, 0, stream, kin, L, R, N, n, shift, bits,
+                 b.counts, lay.num_tiles));
+  // all RADIX rows, so that digits unused by a short pass get total 0
+  RMQ_TRY(launch(k_radix_rowscan, dim3(RADIX), block, 0, stream, b.counts, lay.num_tiles,
+                 b.total));
+  RMQ_TRY(launch(k_radix_scatter<MODE>, grid, block, 0, stream, kin, vin, L, R, N, n, shift,
+                 bits, b.counts, b.total, lay.num_tiles, kout, vout));
+  return hipSuccess;
+}
+
 }  // namespace
 
 size_t sort_workspace_bytes(int64_t q) { return q > 0 ? sort_layout(q).bytes : 0; }
@@ -262,17 +342,12 @@ hipError_t launch_sort_endpoints(const int32_t* L, const int32_t* R, int64_t q, 
   if (q <= 0) return hipSuccess;
   const SortLayout lay = sort_layout(q);
   if (ws_bytes < lay.bytes) return hipErrorInvalidValue;
-  char* base = static_cast<char*>(ws);
-  uint32_t* tkey = reinterpret_cast<uint32_t*>(base + lay.off_key);
-  uint32_t* tval = reinterpret_cast<uint32_t*>(base + lay.off_val);
-  uint32_t* counts = reinterpret_cast<uint32_t*>(base + lay.off_counts);
-  uint32_t* total = reinterpret_cast<uint32_t*>(base + lay.off_total);
+  const SortBufs b = sort_bufs(lay, ws);
   uint32_t* okey = reinterpret_cast<uint32_t*>(pos);
   uint32_t* oval = reinterpret_cast<uint32_t*>(tag);
 
   const int nbits = n > 1 ? bit_length((uint64_t)(n - 1)) : 1;
   const int passes = (nbits + RADIX_BITS - 1) / RADIX_BITS;
-  const dim3 grid((unsigned)lay.num_tiles), block(WG);
   const uint32_t* src_k = nullptr;
   const uint32_t* src_v = nullptr;
   for (int p = 0; p < passes; ++p) {
@@ -281,30 +356,33 @@ hipError_t launch_sort_endpoints(const int32_t* L, const int32_t* R, int64_t q, 
     // passes alternate between the scratch pair and the output pair so that
     // the last one lands in the output
     const bool to_out = ((passes - 1 - p) % 2) == 0;
-    uint32_t* dk = to_out ? okey : tkey;
-    uint32_t* dv = to_out ? oval : tval;
-    if (p == 0) {
-      hipLaunchKernelGGL(k_radix_count<true>, grid, block, 0, stream, nullptr, L, R, lay.N, n,
-                         shift, bits, counts, lay.num_tiles);
-    } else {
-      hipLaunchKernelGGL(k_radix_count<false>, grid, block, 0, stream, src_k, nullptr, nullptr,
-                         lay.N, n, shift, bits, counts, lay.num_tiles);
-    }
-    // all RADIX rows, so that digits unused by a short last pass get total 0
-    hipLaunchKernelGGL(k_radix_rowscan, dim3(RADIX), block, 0, stream, counts, lay.num_tiles,
-                       total);
-    if (p == 0) {
-      hipLaunchKernelGGL(k_radix_scatter<true>, grid, block, 0, stream, nullptr, nullptr, L, R,
-                         lay.N, n, shift, bits, counts, total, lay.num_tiles, dk, dv);
-    } else {
-      hipLaunchKernelGGL(k_radix_scatter<false>, grid, block, 0, stream, src_k, src_v, nullptr,
-                         nullptr, lay.N, n, shift, bits, counts, total, lay.num_tiles, dk, dv);
-    }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    uint32_t* dk = to_out ? okey : b.tkey;
+    uint32_t* dv = to_out ? oval : b.tval;
+    if (p == 0)
+      RMQ_TRY(radix_pass<QUERIES>(nullptr, nullptr, L, R, lay.N, n, shift, bits, lay, b, dk, dv,
+                                  stream));
+    else
+      RMQ_TRY(radix_pass<ARRAYS>(src_k, src_v, nullptr, nullptr, lay.N, n, shift, bits, lay, b,
+                                 dk, dv, stream));
     src_k = dk;
     src_v = dv;
   }
+  return hipSuccess;
+}
+
+hipError_t launch_remap(const int32_t* tag, int64_t q, int32_t* LR, void* ws, size_t ws_bytes,
+                        hipStream_t stream) {
+  if (q <= 0) return hipSuccess;
+  const SortLayout lay = sort_layout(q);
+  if (ws_bytes < lay.bytes) return hipErrorInvalidValue;
+  const SortBufs b = sort_bufs(lay, ws);
+  const int tbits = lay.N > 1 ? bit_length((uint64_t)(lay.N - 1)) : 1;
+  const int shift = tbits > RADIX_BITS ? tbits - RADIX_BITS : 0;
+  RMQ_TRY(radix_pass<KEY_IDX>(reinterpret_cast<const uint32_t*>(tag), nullptr, nullptr, nullptr,
+                              lay.N, 0, shift, tbits - shift, lay, b, b.tkey, b.tval, stream));
+  const int64_t chunks = (lay.N + 4 * WG - 1) / (4 * WG);
+  RMQ_TRY(launch(k_remap_apply, dim3((unsigned)xcd_grid(chunks)), dim3(WG), 0, stream, b.tkey,
+                 b.tval, lay.N, LR, chunks));
   return hipSuccess;
 }
 

@@ -1,7 +1,7 @@
 // Block Sparse Table (Section 3.1 step 3; Section 2, the doubling of Bender
 // and Farach): st[j][b] = min(st[0][b .. min(b + 2^j, nb) - 1]), level-major.
 //
-// A launch computes t consecutive levels j0+1 .. j0+t from level j0 inside
+// A round computes t consecutive levels j0+1 .. j0+t from level j0 inside
 // LDS.  With stride s = 2^j0, level j0+m at block b is the min of level j0 at
 // b, b+s, ..., b+(2^m - 1)s, so the work splits into the s residue classes
 // b mod s.  A workgroup takes R adjacent residues (one contiguous row of R
@@ -9,7 +9,9 @@
 // i0 .. i0+TI-1, plus a halo of 2^t - 1 rows below; it then doubles t times
 // in LDS (ping-pong buffers) and writes each level's TI rows.  Keys past the
 // last block read as the min identity, which gives exactly the truncated
-// spans at the end of the table.
+// spans at the end of the table.  Round r starts at the same j0 for every
+// table (0, 10, 16, 22, ...), so the rounds of many tables batch into one
+// launch each.
 #include "device.h"
 #include "kernels.h"
 
@@ -20,9 +22,32 @@ namespace {
 constexpr int WG = 256;
 constexpr int TILE = 1024;  // outputs per workgroup per level (R * TI)
 
-__global__ __launch_bounds__(WG) void k_st_levels(uint64_t* __restrict__ st, int64_t nb, int j0,
-                                                  int t, int R, int col_tiles) {
-  extern __shared__ uint64_t lds[];
+struct RoundShape {
+  int j0, R, TI, tmax;
+};
+
+// Largest t such that the halo fits: rows TI + 2^t - 1 <= 2 * TI.
+int levels_per_round(int TI) {
+  int t = 0;
+  while ((2 << t) - 1 <= TI) ++t;
+  return t;
+}
+
+RoundShape round_shape(int r) {
+  RoundShape s{0, 1, TILE, 0};
+  for (int i = 0;; ++i) {
+    const int64_t stride = 1ll << s.j0;
+    s.R = (int)(stride < 16 ? stride : 16);
+    s.TI = TILE / s.R;
+    s.tmax = levels_per_round(s.TI);
+    if (i == r) return s;
+    s.j0 += s.tmax;
+  }
+}
+
+__device__ __forceinline__ void st_tile(uint64_t* __restrict__ st, int64_t nb, int j0, int t,
+                                        int R, int64_t col_tiles, int64_t tile_idx,
+                                        uint64_t* lds) {
   const int64_t s = 1ll << j0;
   const int TI = TILE / R;
   const int H = (1 << t) - 1;
@@ -30,8 +55,8 @@ __global__ __launch_bounds__(WG) void k_st_levels(uint64_t* __restrict__ st, int
   uint64_t* buf0 = lds;
   uint64_t* buf1 = lds + (size_t)rows * R;
 
-  const int64_t tile_c = blockIdx.x % col_tiles;
-  const int64_t tile_r = blockIdx.x / col_tiles;
+  const int64_t tile_c = tile_idx % col_tiles;
+  const int64_t tile_r = tile_idx / col_tiles;
   const int64_t r0 = tile_c * R;
   const int64_t i0 = tile_r * TI;
   const uint64_t* src = st + (size_t)j0 * nb;
@@ -67,34 +92,72 @@ __global__ __launch_bounds__(WG) void k_st_levels(uint64_t* __restrict__ st, int
   }
 }
 
+__global__ __launch_bounds__(WG) void k_st_levels(uint64_t* __restrict__ st, int64_t nb, int j0,
+                                                  int t, int R, int64_t col_tiles) {
+  extern __shared__ uint64_t lds[];
+  st_tile(st, nb, j0, t, R, col_tiles, blockIdx.x, lds);
+}
+
+// Round `round` of every table of a batch: workgroup w works on the table
+// whose range of tiles holds w.
+__global__ __launch_bounds__(WG) void k_st_multi(const ArrayDesc* __restrict__ items,
+                                                 const int64_t* __restrict__ tile_prefix,
+                                                 int count, int j0, int R, int tmax) {
+  extern __shared__ uint64_t lds[];
+  const int j = find_item(tile_prefix, count, blockIdx.x);
+  const ArrayDesc& d = items[j];
+  const int t = d.levels - 1 - j0 < tmax ? d.levels - 1 - j0 : tmax;
+  const int64_t s = 1ll << j0;
+  const int64_t col_tiles = (s + R - 1) / R;
+  st_tile(d.st, d.nb, j0, t, R, col_tiles, blockIdx.x - tile_prefix[j], lds);
+}
+
 }  // namespace
 
-// Largest t such that the halo fits: rows TI + 2^t - 1 <= 2 * TI.
-static int levels_per_launch(int TI) {
-  int t = 0;
-  while ((2 << t) - 1 <= TI) ++t;
-  return t;
+int st_round_j0(int r) { return round_shape(r).j0; }
+
+int st_rounds(int levels) {
+  int r = 0;
+  while (round_shape(r).j0 + 1 < levels) ++r;
+  return r;
+}
+
+int64_t st_round_tiles(int64_t nb, int levels, int r) {
+  const RoundShape sh = round_shape(r);
+  if (sh.j0 + 1 >= levels) return 0;
+  const int64_t s = 1ll << sh.j0;
+  const int64_t col_tiles = (s + sh.R - 1) / sh.R;
+  const int64_t rows_total = (nb + s - 1) / s;  // largest class length
+  return col_tiles * ((rows_total + sh.TI - 1) / sh.TI);
+}
+
+size_t st_round_lds(int r) {
+  const RoundShape sh = round_shape(r);
+  return 2ull * (size_t)(sh.TI + (1 << sh.tmax) - 1) * sh.R * sizeof(uint64_t);
 }
 
 hipError_t launch_sparse_table(uint64_t* st, int64_t nb, int levels, hipStream_t stream) {
-  int j0 = 0;
-  while (j0 + 1 < levels) {
-    const int64_t s = 1ll << j0;
-    const int R = (int)(s < 16 ? s : 16);
-    const int TI = TILE / R;
-    int t = levels_per_launch(TI);
-    if (j0 + t > levels - 1) t = levels - 1 - j0;
-    const int64_t col_tiles = (s + R - 1) / R;
-    const int64_t rows_total = (nb + s - 1) / s;  // largest class length
-    const int64_t row_tiles = (rows_total + TI - 1) / TI;
-    const int64_t grid = col_tiles * row_tiles;
-    const size_t lds = 2ull * (size_t)(TI + (1 << t) - 1) * R * sizeof(uint64_t);
-    hipLaunchKernelGGL(k_st_levels, dim3((unsigned)grid), dim3(WG), lds, stream, st, nb, j0, t, R,
-                       (int)col_tiles);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    j0 += t;
+  for (int r = 0; r < st_rounds(levels); ++r) {
+    const RoundShape sh = round_shape(r);
+    const int t = sh.j0 + sh.tmax > levels - 1 ? levels - 1 - sh.j0 : sh.tmax;
+    const int64_t s = 1ll << sh.j0;
+    const int64_t col_tiles = (s + sh.R - 1) / sh.R;
+    const int64_t grid = st_round_tiles(nb, levels, r);
+    const size_t lds = 2ull * (size_t)(sh.TI + (1 << t) - 1) * sh.R * sizeof(uint64_t);
+    RMQ_TRY(launch(k_st_levels, dim3((unsigned)grid), dim3(WG), (uint32_t)lds, stream, st, nb,
+                   sh.j0, t, sh.R, col_tiles));
   }
+  return hipSuccess;
+}
+
+hipError_t launch_sparse_table_multi(const ArrayDesc* items, const int64_t* tile_prefix,
+                                     int count, int round, int64_t total_tiles,
+                                     hipStream_t stream) {
+  if (total_tiles <= 0) return hipSuccess;
+  const RoundShape sh = round_shape(round);
+  RMQ_TRY(launch(k_st_multi, dim3((unsigned)total_tiles), dim3(WG),
+                 (uint32_t)st_round_lds(round), stream, items, tile_prefix, count, sh.j0, sh.R,
+                 sh.tmax));
   return hipSuccess;
 }
 

@@ -102,3 +102,17 @@ def test_plan():
     assert p in ("full", "contracted") and k >= 16 and (k & (k - 1)) == 0
     with pytest.raises(rmq.RMQError):
         rmq.plan(0, 5)
+
+
+def test_plan_table_roundtrip():
+    """Measured plans (host only): the nearest entry in (log2 n, log2 q)."""
+    rmq.set_plan_table([(10 ** 6, 10 ** 3, 4096, "full"), (10 ** 6, 10 ** 6, 64, "contracted")])
+    try:
+        assert rmq.plan(10 ** 6, 900) == (4096, "full")
+        assert rmq.plan(2 * 10 ** 6, 2 * 10 ** 6) == (64, "contracted")
+        with pytest.raises(rmq.RMQError):
+            rmq.set_plan_table([(10, 10, 1000, "full")])  # not a power of two
+    finally:
+        rmq.set_plan_table([])
+    k, p = rmq.plan(10 ** 6, 10)
+    assert p == "full" and k == rmq.default_block(10 ** 6, 10, "full")
