@@ -59,6 +59,9 @@ def main() -> int:
                          "HBM traffic figure to scale profiler byte counters by)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="repeat the CPU oracle sweep until this much time has passed")
+    ap.add_argument("--no-batched", action="store_true", help="skip the many-arrays measurement")
+    ap.add_argument("--no-served", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--served-requests", type=int, default=3000)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -160,9 +163,11 @@ def main() -> int:
         algo_bytes = 4 * n + 8 * nb
         achieved = algo_bytes / (avg / 1e3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": profiled_traffic(n, k_full),
                     "kernel": "k_blockmin_i32", "avg_ms": round(avg, 5),
-                    "algorithmic_bytes": algo_bytes}
+                    "algorithmic_bytes": algo_bytes,
+                    "traffic_source": os.path.relpath(TRAFFIC_PROFILE, ROOT)}
 
     cpu = None
     if not args.no_cpu:
@@ -183,6 +188,9 @@ def main() -> int:
                           f"each batch of the sweep q={qs} on the same n={n} array, "
                           f"{reps} sweeps in {dt:.1f}s on the host")}
 
+    batched = None if args.no_batched else bench_batched(d)
+    served = None if args.no_served else bench_served(d, args.served_requests)
+
     line = {
         "metric": METRIC, "value": round(value, 1), "unit": "queries/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
@@ -195,9 +203,132 @@ def main() -> int:
                    "block_size": {p: k_used[p] for p in paths},
                    "parallelism": "single GPU"},
         "roofline": roofline, "cpu_baseline": cpu, "breakdown": breakdown,
+        "batched": batched, "served": served,
     }
     print(json.dumps(line), flush=True)
     return 0
+
+
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_blockmin_i32_n1e8_traffic.md")
+
+
+def profiled_traffic(n: int, k: int):
+    """HBM bytes per launch of the block-minima kernel from the committed
+    counter profile (FETCH_SIZE / WRITE_SIZE, calibrated), when it was taken on
+    this workload and on the kernel source as it is now; else None."""
+    import hashlib
+
+    if (n, k) != (10 ** 8, 1024) or not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    text = open(TRAFFIC_PROFILE).read()
+    block = text.split("```json", 1)[1].split("```", 1)[0]
+    meta = json.loads(block)
+    src = os.path.join(ROOT, meta["source"])
+    cur = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    return meta["traffic_bytes"] if cur == meta["source_sha256"] else None
+
+
+def time_runs(fn, stream, warmup=2, reps=5):
+    import torch
+
+    for _ in range(warmup):
+        fn()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    stream.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def bench_batched(d, count=256):
+    """Many arrays of uneven length, each with its own query batch: one launch
+    per phase for all of them (eager and replayed from a hipGraph) against one
+    call per array.  n_j log-uniform in [1e4, 1e7], q_j log-uniform in
+    [10, 1e5], values uniform in [0, 2^31), uniform queries."""
+    import torch
+
+    import paper_1706_06940_amd as rmq
+    import workloads as W
+
+    seed = W.BASE_SEED + 4
+    rmq.load_plan_table()
+    ns = W.loguniform_ints(count, 1e4, 1e7, seed, 1)
+    qs = W.loguniform_ints(count, 10, 1e5, seed, 2)
+    arrays = [W.uniform_int31_torch(int(n), seed, 100 + j, device=d) for j, n in enumerate(ns)]
+    queries = [W.uniform_queries_torch(int(n), int(q), seed, 1000 + 2 * j, device=d)
+               for j, (n, q) in enumerate(zip(ns, qs))]
+    b = rmq.Batch(arrays, queries)
+    plans = [b.plan(j) for j in range(count)]
+    s = torch.cuda.Stream(device=d)
+    res = {}
+    outs = {}
+    with torch.cuda.stream(s):
+        for mode in ("per_item", "fused"):
+            for graph in (False, True):
+                ms = time_runs(lambda: b.run(mode, graph=graph, stream=s), s)
+                res[mode + ("_graph" if graph else "")] = ms
+            outs[mode] = [o.clone() for o in b.outs]
+    s.synchronize()
+    same = all(torch.equal(x, y) for x, y in zip(outs["per_item"], outs["fused"]))
+    Q, N = int(qs.sum()), int(ns.sum())
+    b.free()
+    return {
+        "workload": (f"{count} arrays, n log-uniform in [1e4,1e7] (total {N}), q log-uniform "
+                     f"in [10,1e5] (total {Q}), int32 uniform values, uniform queries"),
+        "plans": {"full": sum(p == "full" for _, p in plans),
+                  "contracted": sum(p == "contracted" for _, p in plans),
+                  "block_sizes": sorted({k for k, _ in plans})},
+        "ms": {k: round(v, 4) for k, v in res.items()},
+        "queries_per_s": {k: round(Q / (v / 1e3), 1) for k, v in res.items()},
+        "input_GB_per_s": {k: round(4 * N / (v / 1e3) / 1e9, 1) for k, v in res.items()},
+        "speedup_vs_per_item": {k: round(res["per_item"] / v, 3) for k, v in res.items()},
+        "fused_equals_per_item": same,
+    }
+
+
+def bench_served(d, n_req):
+    """64 resident arrays (n log-uniform in [1e6, 1e8]) and their block Sparse
+    Tables; requests of q log-uniform in [1, 1e5] uniform queries on a
+    uniformly chosen array.  Capacity with every request arriving at once,
+    then Poisson arrivals at 0.5 / 0.8 / 0.95 of it; the same for the plain
+    per-request server (one slot, one request per launch)."""
+    import numpy as np
+
+    import workloads as W
+    from paper_1706_06940_amd import serving
+
+    seed = W.BASE_SEED + 5
+    ns = W.loguniform_ints(64, 1e6, 1e8, seed, 1)
+    arrays = [W.uniform_int31_torch(int(n), seed, 200 + j, device=d) for j, n in enumerate(ns)]
+    reqs = serving.make_requests(ns, n_req, 1, 1e5, seed)
+    out = {"workload": (f"64 resident arrays, n log-uniform in [1e6,1e8] (total {int(ns.sum())}); "
+                        f"{n_req} requests, q log-uniform in [1,1e5], uniform queries")}
+    for name, cfg in (("coalesced", dict(num_streams=4, max_requests_per_batch=4096,
+                                         hbm_budget_bytes=4 * 12 * (1 << 21) + (1 << 20))),
+                      ("per_request", dict(num_streams=1, max_requests_per_batch=1,
+                                           hbm_budget_bytes=12 * (1 << 21) + (1 << 20)))):
+        with serving.Server(max_tables=64, **cfg) as srv:
+            for A in arrays:
+                srv.add_array(A)
+            serving.run_schedule(srv, reqs[:200], [serving.clock()] * 200)  # warm-up
+            sat = serving.run_schedule(srv, reqs, [serving.clock()] * len(reqs))
+            entry = {"capacity": sat.summary(),
+                     "capacity_requests_per_s": round(len(reqs) / sat.makespan_s, 1)}
+            if name == "coalesced":
+                base_rate = len(reqs) / sat.makespan_s
+            for frac in (0.5, 0.8, 0.95):
+                t0 = serving.clock() + 5e-3
+                arr = serving.poisson_schedule(len(reqs), frac * base_rate, seed + int(100 * frac), t0)
+                r = serving.run_schedule(srv, reqs, arr)
+                entry[f"poisson_{frac}"] = dict(r.summary(), rate_requests_per_s=round(frac * base_rate, 1))
+            st = srv.stats()
+            entry["max_batches_in_flight"] = st["max_inflight"]
+            entry["index_bytes"] = st["index_bytes"]
+            out[name] = entry
+    out["poisson_rates_are_fractions_of"] = "the coalesced server's capacity"
+    return out
 
 
 if __name__ == "__main__":

@@ -266,6 +266,84 @@ size_t rmq_batch_workspace_bytes(rmq_batch b);
 rmq_status rmq_batch_free(rmq_batch b);
 
 /* ----------------------------------------------------------------------------
+ * Serving.  A server keeps arrays and their block Sparse Tables resident
+ * (Section 3.2's index, built once per array) and answers query requests as
+ * they arrive.  Requests wait in a queue; a dispatcher thread packs whatever
+ * is pending into the next free slot -- a stream with its own pinned staging
+ * and device query buffers -- while their queries fit the slot (admission by
+ * HBM footprint: the slots' device buffers are carved from hbm_budget_bytes),
+ * and answers the whole coalesced batch with one query launch over the
+ * resident tables; requests that arrive meanwhile go to the next slot, so
+ * batches overlap on the device.  A completion thread copies each request's
+ * answers to its output buffer.  All threads are native; the calls below are
+ * thread-safe. */
+typedef struct rmq_server_config {
+    int32_t num_streams;             /* slots in flight, 1..16                    */
+    int32_t max_tables;              /* resident arrays the server can hold       */
+    int32_t max_requests_per_batch;  /* requests coalesced into one launch        */
+    int32_t reserved;
+    size_t hbm_budget_bytes;         /* device bytes for in-flight query buffers  */
+} rmq_server_config;
+
+typedef struct rmq_server_stats {
+    int64_t submitted, completed, batches, queries;
+    int64_t slot_capacity;           /* queries one slot (one batch) can hold     */
+    int64_t max_inflight;            /* most batches seen on the device at once   */
+    size_t index_bytes;              /* device bytes of the resident tables       */
+} rmq_server_stats;
+
+typedef struct rmq_request_info {
+    double t_submit, t_launch, t_done;  /* rmq_server_clock() seconds           */
+    int32_t batch_requests;             /* requests in the batch it went with   */
+    int32_t reserved;
+} rmq_request_info;
+
+typedef struct rmq_server_s *rmq_server;
+
+rmq_status rmq_server_create(const rmq_server_config *cfg, rmq_server *out);
+
+/* Build and keep a resident index of device array A (k = block_size, 0 = auto);
+ * synchronous.  A must stay alive and unmodified for the server's life. */
+rmq_status rmq_server_add_array(rmq_server s, const int32_t *A, int64_t n, int32_t block_size,
+                                int32_t *table_id);
+
+/* Queue q >= 1 queries on a resident array.  L, R and out are HOST pointers
+ * that must stay valid until rmq_server_wait returns for the ticket; out
+ * receives the leftmost argmin of each query (-1 for an invalid one).  q may
+ * not exceed the slot capacity (see rmq_server_stats). */
+rmq_status rmq_server_submit(rmq_server s, int32_t table_id, const int32_t *L, const int32_t *R,
+                             int64_t q, int32_t *out, uint64_t *ticket);
+
+/* A request with its arrival time on rmq_server_clock(). */
+typedef struct rmq_request_spec {
+    int32_t table_id;
+    int32_t reserved;
+    const int32_t *L, *R;   /* host */
+    int64_t q;
+    int32_t *out;           /* host */
+    double t_arrival;
+} rmq_request_spec;
+
+/* Submit count requests, each at its arrival time (a load generator for an
+ * arrival process fixed in advance, e.g. Poisson); blocks in the calling
+ * thread until the last one is submitted.  tickets[i] gets request i's
+ * ticket. */
+rmq_status rmq_server_submit_schedule(rmq_server s, int32_t count, const rmq_request_spec *specs,
+                                      uint64_t *tickets);
+
+/* Block until the request is answered; releases the ticket (wait once). */
+rmq_status rmq_server_wait(rmq_server s, uint64_t ticket, rmq_request_info *info);
+
+rmq_status rmq_server_stats_get(rmq_server s, rmq_server_stats *out);
+
+/* The server's clock (seconds, monotonic), for timestamps comparable with
+ * rmq_request_info. */
+double rmq_server_clock(void);
+
+/* Drain every queued request, stop the threads and free everything. */
+rmq_status rmq_server_destroy(rmq_server s);
+
+/* ----------------------------------------------------------------------------
  * Per-stage timing (Table 1's stages).  A timer collects HIP events that
  * rmq_query_batch_ex records on its stream; rmq_timer_read waits for them and
  * returns the milliseconds of each stage of the last call that used the

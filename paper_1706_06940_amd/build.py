@@ -25,6 +25,7 @@ SOURCES = [
     "radix_sort.hip",
     "contract.hip",
     "capi.hip",
+    "server.hip",
 ]
 
 ARCH = "gfx950"

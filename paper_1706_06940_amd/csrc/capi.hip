@@ -8,6 +8,7 @@
 #include <new>
 #include <vector>
 
+#include "index.h"
 #include "kernels.h"
 #include "rmq.h"
 
@@ -21,16 +22,6 @@ struct rmq_timer_s {
 
 thread_local rmq::StageClock* rmq::tl_clock = nullptr;
 
-struct rmq_index_s {
-  int device;
-  const int32_t* A;
-  int64_t n;
-  int kshift;
-  int64_t nb;
-  int levels;
-  uint64_t* st;
-  size_t bytes;
-};
 
 namespace {
 

@@ -94,6 +94,11 @@ hipError_t launch_sparse_table_multi(const ArrayDesc* items, const int64_t* tile
 hipError_t launch_query_multi(const ArrayDesc* items, const int64_t* q_prefix, int count,
                               int64_t total_q, int64_t* bad_count, uint64_t* stats,
                               hipStream_t stream);
+// Serving: one launch over a coalesced batch of requests on resident tables.
+hipError_t launch_query_segments(const ArrayDesc* tables, const int64_t* seg_prefix,
+                                 const int32_t* seg_table, int nseg, const int32_t* L,
+                                 const int32_t* R, int32_t* out, int64_t total,
+                                 hipStream_t stream);
 hipError_t launch_query_full(const int32_t* A, int64_t n, int kshift, const uint64_t* st,
                              int64_t nb, const int32_t* L, const int32_t* R, int64_t q,
                              int32_t* out, int64_t* bad_count, uint64_t* stats,

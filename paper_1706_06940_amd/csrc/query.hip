@@ -260,7 +260,40 @@ __global__ __launch_bounds__(WG) void k_query_multi(const ArrayDesc* __restrict_
              bad_count, stats);
 }
 
+// A coalesced batch of requests (serving): queries g in
+// [seg_prefix[s], seg_prefix[s+1]) belong to request s, which targets the
+// resident table tables[seg_table[s]].
+__global__ __launch_bounds__(WG) void k_query_segments(const ArrayDesc* __restrict__ tables,
+                                                       const int64_t* __restrict__ seg_prefix,
+                                                       const int32_t* __restrict__ seg_table,
+                                                       int nseg, const int32_t* __restrict__ L,
+                                                       const int32_t* __restrict__ R,
+                                                       int32_t* __restrict__ out) {
+  const int64_t g = (int64_t)blockIdx.x * WG + threadIdx.x;
+  const bool live = g < seg_prefix[nseg];
+  const int sg = live ? find_item(seg_prefix, nseg, g) : 0;
+  const ArrayDesc& d = tables[seg_table[sg]];
+  int64_t l = 0, r = -1;
+  if (live) {
+    l = L[g];
+    r = R[g];
+  }
+  query_core(SrcA{d.A, d.n}, d.n, d.n, d.kshift, d.st, d.nb, l, r, l, r, live,
+             out + (live ? g : 0), nullptr, nullptr);
+}
+
 }  // namespace
+
+hipError_t launch_query_segments(const ArrayDesc* tables, const int64_t* seg_prefix,
+                                 const int32_t* seg_table, int nseg, const int32_t* L,
+                                 const int32_t* R, int32_t* out, int64_t total,
+                                 hipStream_t stream) {
+  if (total <= 0) return hipSuccess;
+  const int64_t grid = (total + WG - 1) / WG;
+  RMQ_TRY(launch(k_query_segments, dim3((unsigned)grid), dim3(WG), 0, stream, tables, seg_prefix,
+                 seg_table, nseg, L, R, out));
+  return hipSuccess;
+}
 
 hipError_t launch_query_full(const int32_t* A, int64_t n, int kshift, const uint64_t* st,
                              int64_t nb, const int32_t* L, const int32_t* R, int64_t q,

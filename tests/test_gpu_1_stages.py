@@ -128,3 +128,14 @@ def test_contract(orc, n, q):
         assert np.array_equal(host(Lc), eLc) and np.array_equal(host(Rc), eRc), name
         exp = orc.contract(A, ep)
         check_keys(host(aq).view(np.uint64), A, exp, f"A_Q {name} n={n} q={q}")
+
+
+def test_device_generator_matches_host():
+    """The torch form of the seeded generator gives the same values on the GPU."""
+    d = need_gpu()
+    say("device_generator")
+    got = W.uniform_int31_torch(1_000_003, 5, 3, device=d).cpu().numpy()
+    assert np.array_equal(got, W.uniform_int31(1_000_003, 5, 3))
+    Lt, Rt = W.uniform_queries_torch(10 ** 8, 20_000, 6, 8, device=d)
+    Ln, Rn = W.uniform_queries(10 ** 8, 20_000, 6, 8)
+    assert np.array_equal(Lt.cpu().numpy(), Ln) and np.array_equal(Rt.cpu().numpy(), Rn)

@@ -41,3 +41,14 @@ def test_paper_permutation_is_a_permutation():
     a = W.paper_permutation(10_001, 5)
     assert np.array_equal(np.sort(a), np.arange(1, 10_002))
     assert np.mean(a != np.arange(1, 10_002)) > 0.5
+
+
+def test_torch_form_is_bit_identical():
+    assert np.array_equal(W.hashes_torch(77, 3, 5, 10_000).numpy().view(np.uint64),
+                          W.hashes(77, 3, 5, 10_000))
+    assert np.array_equal(W.uniform_int31_torch(300_001, 9, 2, chunk=1 << 16).numpy(),
+                          W.uniform_int31(300_001, 9, 2))
+    for n in (1, 7, 10 ** 8, 2 ** 31 - 1):
+        Lt, Rt = W.uniform_queries_torch(n, 5000, 11, 4)
+        Ln, Rn = W.uniform_queries(n, 5000, 11, 4)
+        assert np.array_equal(Lt.numpy(), Ln) and np.array_equal(Rt.numpy(), Rn)

@@ -146,6 +146,58 @@ def loguniform_ints(count: int, lo: float, hi: float, seed: int, stream: int) ->
     return np.clip(v, lo, hi).astype(np.int64)
 
 
+# ------------------------------------------------------------ torch form
+# The same draws computed with torch int64 tensor arithmetic (two's-complement
+# wrap-around gives the uint64 products mod 2^64; logical shifts are masked
+# arithmetic shifts), so large inputs can be drawn where they are used,
+# e.g. in device memory.  Bit-identical to the numpy form above.
+def _signed(x: int) -> int:
+    x &= (1 << 64) - 1
+    return x - (1 << 64) if x >= (1 << 63) else x
+
+
+def _lshr(z, s: int):
+    import torch
+
+    return (z >> s) & ((1 << (64 - s)) - 1)
+
+
+def hashes_torch(seed: int, stream: int, start: int, count: int, device="cpu"):
+    import torch
+
+    base = _signed((seed ^ (stream * 0xD1B54A32D192ED03)) & ((1 << 64) - 1))
+    z = torch.arange(start + 1, start + count + 1, dtype=torch.int64, device=device)
+    z.mul_(_signed(0x9E3779B97F4A7C15)).add_(base)
+    z ^= _lshr(z, 30)
+    z.mul_(_signed(0xBF58476D1CE4E5B9))
+    z ^= _lshr(z, 27)
+    z.mul_(_signed(0x94D049BB133111EB))
+    z ^= _lshr(z, 31)
+    return z
+
+
+def uniform_int31_torch(n: int, seed: int, stream: int = 0, device="cpu", chunk: int = 1 << 26):
+    """uniform_int31 drawn with torch on `device` (identical values)."""
+    import torch
+
+    out = torch.empty(n, dtype=torch.int32, device=device)
+    for c0 in range(0, n, chunk):
+        c1 = min(n, c0 + chunk)
+        out[c0:c1] = _lshr(hashes_torch(seed, stream, c0, c1 - c0, device), 33).to(torch.int32)
+    return out
+
+
+def uniform_queries_torch(n: int, q: int, seed: int, stream: int = 1, device="cpu"):
+    """uniform_queries drawn with torch on `device` (identical values)."""
+    import torch
+
+    def idx(st):
+        return (_lshr(hashes_torch(seed, st, 0, q, device), 32) * n) >> 32
+
+    a, b = idx(stream), idx(stream + 1)
+    return torch.minimum(a, b).to(torch.int32), torch.maximum(a, b).to(torch.int32)
+
+
 # ---------------------------------------------------------------- native part
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
