@@ -112,7 +112,7 @@ FullLayout full_layout(int64_t n, int64_t k) {
 struct ConLayout {
   int64_t M, m, nb;
   int levels;
-  size_t off_pos, off_tag, off_sort, off_lr, off_aq, off_tiles, off_st, bytes;
+  size_t off_E, off_sort, off_lr, off_aq, off_tiles, off_st, bytes;
 };
 
 ConLayout con_layout(int64_t n, int64_t q, int64_t k) {
@@ -122,10 +122,8 @@ ConLayout con_layout(int64_t n, int64_t q, int64_t k) {
   c.nb = num_blocks(c.m, k);
   c.levels = rmq_table_levels(c.nb);
   size_t o = 0;
-  c.off_pos = o;
-  o = align_up(o + sizeof(int32_t) * (size_t)c.M);
-  c.off_tag = o;
-  o = align_up(o + sizeof(int32_t) * (size_t)c.M);
+  c.off_E = o;
+  o = align_up(o + sizeof(uint64_t) * (size_t)c.M);
   c.off_sort = o;
   o = align_up(o + sort_workspace_bytes(q));
   c.off_lr = o;
@@ -220,22 +218,20 @@ rmq_status run_contracted(const int32_t* A, int64_t n, const int32_t* L, const i
                           const Plan& p, char* ws) {
   rmq_timer* t = opt ? opt->timer : nullptr;
   const ConLayout c = con_layout(n, q, p.k);
-  int32_t* pos = reinterpret_cast<int32_t*>(ws + c.off_pos);
-  int32_t* tag = reinterpret_cast<int32_t*>(ws + c.off_tag);
+  uint64_t* E = reinterpret_cast<uint64_t*>(ws + c.off_E);
   int32_t* LR = reinterpret_cast<int32_t*>(ws + c.off_lr);
   uint64_t* aq = reinterpret_cast<uint64_t*>(ws + c.off_aq);
   int32_t* tiles = reinterpret_cast<int32_t*>(ws + c.off_tiles);
   uint64_t* st = reinterpret_cast<uint64_t*>(ws + c.off_st);
   ClockGuard guard;
   stage_begin(t, 0);
-  hipError_t e = launch_sort_endpoints(L, R, q, n, pos, tag, ws + c.off_sort,
-                                       sort_workspace_bytes(q), s);
-  if (e != hipSuccess) return from_hip(e);
-  e = launch_remap(tag, q, LR, ws + c.off_sort, sort_workspace_bytes(q), s);
+  // the sort's last pass writes the remap as well
+  hipError_t e =
+      launch_sort_endpoints(L, R, q, n, E, LR, ws + c.off_sort, sort_workspace_bytes(q), s);
   if (e != hipSuccess) return from_hip(e);
   stage_end(t, 0, s);
   stage_begin(t, 1);
-  e = launch_contract(A, n, pos, q, aq, tiles, s);
+  e = launch_contract(A, n, E, q, aq, tiles, s);
   if (e != hipSuccess) return from_hip(e);
   stage_end(t, 1, s);
   stage_begin(t, 2);
@@ -484,9 +480,15 @@ rmq_status rmq_sparse_table_build(uint64_t* st, int64_t nb, int32_t levels, void
   return from_hip(launch_sparse_table(st, nb, levels, static_cast<hipStream_t>(stream)));
 }
 
+// The sort's own workspace, then the packed list it leaves before splitting
+// it into positions and tags.
+static size_t stage_sort_bytes(int64_t q) {
+  return q > 0 ? align_up(sort_workspace_bytes(q)) + sizeof(uint64_t) * 2 * (size_t)q : 0;
+}
+
 size_t rmq_sort_workspace_bytes(int64_t q) {
   if (q < 0 || q > RMQ_MAX_Q) return 0;
-  return sort_workspace_bytes(q);
+  return stage_sort_bytes(q);
 }
 
 rmq_status rmq_sort_endpoints(const int32_t* L, const int32_t* R, int64_t q, int64_t n,
@@ -498,9 +500,13 @@ rmq_status rmq_sort_endpoints(const int32_t* L, const int32_t* R, int64_t q, int
   if (!aligned_to(L, 4) || !aligned_to(R, 4) || !aligned_to(pos, 4) || !aligned_to(tag, 4) ||
       !aligned_to(workspace, ALIGN))
     return RMQ_ERR_MISALIGNED;
-  if (ws_bytes < sort_workspace_bytes(q)) return RMQ_ERR_WORKSPACE_SMALL;
-  return from_hip(launch_sort_endpoints(L, R, q, n, pos, tag, workspace, ws_bytes,
-                                        static_cast<hipStream_t>(stream)));
+  if (ws_bytes < stage_sort_bytes(q)) return RMQ_ERR_WORKSPACE_SMALL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t sort_b = align_up(sort_workspace_bytes(q));
+  uint64_t* E = reinterpret_cast<uint64_t*>(static_cast<char*>(workspace) + sort_b);
+  hipError_t e = launch_sort_endpoints(L, R, q, n, E, nullptr, workspace, sort_b, s);
+  if (e == hipSuccess) e = launch_unpack_endpoints(E, q, pos, tag, s);
+  return from_hip(e);
 }
 
 rmq_status rmq_contract(const int32_t* A, int64_t n, const int32_t* pos, const int32_t* tag,
@@ -514,13 +520,16 @@ rmq_status rmq_contract(const int32_t* A, int64_t n, const int32_t* pos, const i
   hipStream_t s = static_cast<hipStream_t>(stream);
   prepare_pool();
   const size_t sort_b = align_up(sort_workspace_bytes(q));
+  const size_t list_b = align_up(sizeof(uint64_t) * 2 * (size_t)q);
   void* scratch = nullptr;
-  hipError_t e = hipMallocAsync(&scratch, sort_b + contract_tile_start_bytes(n), s);
+  hipError_t e = hipMallocAsync(&scratch, sort_b + list_b + contract_tile_start_bytes(n), s);
   if (e != hipSuccess) return from_hip(e);
   char* w = static_cast<char*>(scratch);
-  e = launch_remap(tag, q, LR, w, sort_b, s);
+  uint64_t* E = reinterpret_cast<uint64_t*>(w + sort_b);
+  e = launch_pack_endpoints(pos, tag, q, E, s);
+  if (e == hipSuccess) e = launch_remap(E, q, LR, w, sort_b, s);
   if (e == hipSuccess)
-    e = launch_contract(A, n, pos, q, aq, reinterpret_cast<int32_t*>(w + sort_b), s);
+    e = launch_contract(A, n, E, q, aq, reinterpret_cast<int32_t*>(w + sort_b + list_b), s);
   hipFreeAsync(scratch, s);
   return from_hip(e);
 }

@@ -35,7 +35,12 @@ constexpr int EPL = T / 64;     // elements per lane
 
 // One thread per 4 consecutive slots s = 4i .. 4i+3 (and the past-the-end
 // slot M, which closes the tile table).
-__global__ __launch_bounds__(WG) void k_tiles(const int32_t* __restrict__ pos, int64_t M,
+// Position of sorted endpoint j: the list holds (position << 32) | tag.
+__device__ __forceinline__ int32_t epos(const uint64_t* __restrict__ E, int64_t j) {
+  return (int32_t)(E[j] >> 32);
+}
+
+__global__ __launch_bounds__(WG) void k_tiles(const uint64_t* __restrict__ E, int64_t M,
                                               uint64_t* __restrict__ aq,
                                               int32_t* __restrict__ tile_start,
                                               int64_t num_tiles) {
@@ -45,11 +50,11 @@ __global__ __launch_bounds__(WG) void k_tiles(const int32_t* __restrict__ pos, i
   // writes below against a malformed list
   const int64_t last = num_tiles * T - 1;
   auto clampp = [last](int64_t e) { return e < 0 ? 0 : (e > last ? last : e); };
-  int64_t e[6];  // pos[s0-1 .. s0+4]
+  int64_t e[6];  // positions of slots s0-1 .. s0+4
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
     const int64_t s = s0 - 1 + i;
-    e[i] = (s >= 0 && s < M) ? clampp(pos[s]) : -1;
+    e[i] = (s >= 0 && s < M) ? clampp(epos(E, s)) : -1;
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
@@ -75,7 +80,7 @@ __device__ __forceinline__ v4i32 load4(const int32_t* __restrict__ A, int64_t p,
 }
 
 __global__ __launch_bounds__(WG) void k_contract(const int32_t* __restrict__ A, int64_t n,
-                                                 const int32_t* __restrict__ E, int64_t M,
+                                                 const uint64_t* __restrict__ E, int64_t M,
                                                  const int32_t* __restrict__ tile_start,
                                                  int64_t num_tiles, uint64_t* __restrict__ aq) {
   __shared__ __align__(16) int32_t head_last[WG / 64][T];
@@ -127,8 +132,8 @@ __global__ __launch_bounds__(WG) void k_contract(const int32_t* __restrict__ A, 
   __syncthreads();
   if (marked) {
     for (int64_t j = jlo + lane; j < jend; j += 64) {
-      const int32_t e = E[j];
-      const bool last_dup = (j + 1 == M) || (E[j + 1] != e);
+      const int32_t e = epos(E, j);
+      const bool last_dup = (j + 1 == M) || (epos(E, j + 1) != e);
       if (last_dup && e >= t0 && e < t0 + T) hl[e - t0] = (int32_t)j;
     }
   }
@@ -225,16 +230,16 @@ __global__ __launch_bounds__(WG) void k_contract(const int32_t* __restrict__ A, 
 
 }  // namespace
 
-hipError_t launch_contract(const int32_t* A, int64_t n, const int32_t* pos, int64_t q,
+hipError_t launch_contract(const int32_t* A, int64_t n, const uint64_t* E, int64_t q,
                            uint64_t* aq, int32_t* tile_start, hipStream_t stream) {
   if (q <= 0) return hipSuccess;
   const int64_t M = 2 * q;
   const int64_t num_tiles = (n + T - 1) / T;
   const int64_t threads = M / 4 + 1;  // slots 0 .. M, four per thread
-  RMQ_TRY(launch(k_tiles, dim3((unsigned)((threads + WG - 1) / WG)), dim3(WG), 0, stream, pos, M,
+  RMQ_TRY(launch(k_tiles, dim3((unsigned)((threads + WG - 1) / WG)), dim3(WG), 0, stream, E, M,
                  aq, tile_start, num_tiles));
   const int64_t grid = (num_tiles + (WG / 64) - 1) / (WG / 64);
-  RMQ_TRY(launch(k_contract, dim3((unsigned)grid), dim3(WG), 0, stream, A, n, pos, M, tile_start,
+  RMQ_TRY(launch(k_contract, dim3((unsigned)grid), dim3(WG), 0, stream, A, n, E, M, tile_start,
                  num_tiles, aq));
   return hipSuccess;
 }

@@ -105,19 +105,26 @@ hipError_t launch_query_full(const int32_t* A, int64_t n, int kshift, const uint
                              hipStream_t stream);
 
 // ---- contracted path (Section 3.1) ----
-// Device LSD radix sort of the 2q endpoints by (position, tag).
+// Device LSD radix sort of the 2q endpoints by (position, tag).  The sorted
+// list E holds (position << 32) | tag per slot.  With LR non-null the last
+// pass also writes the remap (as launch_remap does).
 size_t sort_workspace_bytes(int64_t q);
 hipError_t launch_sort_endpoints(const int32_t* L, const int32_t* R, int64_t q, int64_t n,
-                                 int32_t* pos, int32_t* tag, void* ws, size_t ws_bytes,
+                                 uint64_t* E, int32_t* LR, void* ws, size_t ws_bytes,
                                  hipStream_t stream);
-// Remap: LR[2i] = Lc[i], LR[2i+1] = Rc[i] from the sorted tags; uses the
+// Remap: LR[2i] = Lc[i], LR[2i+1] = Rc[i] from the sorted list; uses the
 // sort's workspace.
-hipError_t launch_remap(const int32_t* tag, int64_t q, int32_t* LR, void* ws, size_t ws_bytes,
+hipError_t launch_remap(const uint64_t* E, int64_t q, int32_t* LR, void* ws, size_t ws_bytes,
                         hipStream_t stream);
+// Split E into positions and tags, or join them into E.
+hipError_t launch_unpack_endpoints(const uint64_t* E, int64_t q, int32_t* pos, int32_t* tag,
+                                   hipStream_t stream);
+hipError_t launch_pack_endpoints(const int32_t* pos, const int32_t* tag, int64_t q, uint64_t* E,
+                                 hipStream_t stream);
 // Contraction: A_Q over the closed areas between consecutive endpoints.
 // tile_start: scratch of contract_tile_start_bytes(n).
 size_t contract_tile_start_bytes(int64_t n);
-hipError_t launch_contract(const int32_t* A, int64_t n, const int32_t* pos, int64_t q,
+hipError_t launch_contract(const int32_t* A, int64_t n, const uint64_t* E, int64_t q,
                            uint64_t* aq, int32_t* tile_start, hipStream_t stream);
 hipError_t launch_query_contracted(const uint64_t* aq, int64_t m, int64_t n, int kshift,
                                    const uint64_t* st, int64_t nb, const int32_t* L,

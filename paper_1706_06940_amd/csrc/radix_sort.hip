@@ -6,25 +6,36 @@
 // sort keeps equal positions in tag order, so the result is ordered by
 // (position, tag) -- the same order any sort on the pair gives.
 //
-// Each pass handles 8 bits of the position (ceil(log2 n) bits in all) with
-// three kernels and no inter-workgroup waiting:
-//   count   -- per-tile digit histogram (LDS atomics), stored digit-major;
-//   rowscan -- one workgroup per digit turns its row of tile counts into
-//              exclusive offsets and a digit total;
-//   scatter -- recomputes stable ranks inside the tile (8 wave ballots give
-//              the lanes that share a digit), stages the tile in LDS in
-//              digit order and writes runs of equal digits contiguously.
-// Tiles are 4096 items: 4 waves x 16 rounds x 64 lanes, each wave owning a
-// contiguous quarter so that (wave, round, lane) order is item order.
-// Workgroups are dealt round-robin over the 8 XCDs; tiles are numbered so that
-// each XCD gets a contiguous range of them, so the runs that neighbouring
-// tiles write for one digit meet in the same L2 and leave it as whole lines.
+// One sweep per digit of the position (ceil(log2 n) bits in all):
+//   k_os_clear  -- clears digit totals, tickets and the first status words;
+//   k_os_hist   -- one read of the input: digit totals of every pass at once
+//                  (per workgroup in LDS, then global atomics);
+//   k_os_pass   -- per pass, one workgroup per 4096-item tile, tiles taken in
+//                  order from an atomic ticket.  The tile ranks its items
+//                  stably (one wave ballot per digit bit gives the lanes that
+//                  share a digit), publishes its per-digit counts at once,
+//                  stages the tile in LDS in digit order, and meanwhile finds
+//                  the number of same-digit items in all earlier tiles by a
+//                  decoupled look-back over their published words (count +
+//                  "aggregate" or "inclusive" flag in one 64-bit word, read
+//                  eight predecessors at a time).  It then writes runs of
+//                  equal digits contiguously.  A tile only ever waits on tiles
+//                  that took their ticket earlier and are therefore running,
+//                  so the waits end; each is also bounded, and an exceeded
+//                  bound sets an abort word that ends every wait at once.
+// Items are 8 bytes, (position << 32) | tag, so each digit run a tile writes
+// is whole cache lines; the key bits are split into the fewest passes of at
+// most 8 bits with equal widths (27 bits -> 7, 7, 7, 6).
+// The first pass reads L and R directly (invalid queries sort as position
+// 0; the query kernel re-checks them), the last writes the output list E.
 //
 // Remap: slot s of the sorted list holding tag t gives Lc[t/2] = s (t even)
-// or Rc[t/2] = s - 1 (t odd).  Written directly these are 2q scattered 4-byte
-// stores; instead one more radix pass orders the (tag, slot) pairs by the top
-// bits of the tag, and the stores then go out window by window, each window
-// of the interleaved LR array written while it sits in one XCD's L2.
+// or Rc[t/2] = s - 1 (t odd).  Inside the whole pipeline the last sort pass
+// writes these 2q scattered 4-byte stores itself, as it places each item.
+// The stand-alone remap (from a given sorted list) instead orders the
+// (tag, slot) pairs by the top bits of the tag with one more sweep and then
+// writes window by window, each window of the interleaved LR array while it
+// sits in one XCD's L2.
 #include "device.h"
 #include "kernels.h"
 
@@ -39,11 +50,13 @@ constexpr int RADIX_BITS = 8;
 constexpr int RADIX = 1 << RADIX_BITS;
 constexpr int NXCD = 8;
 
-// where a pass takes its items from
+// Items are 8 bytes: (key << 32) | value, so a digit run of a tile is one
+// contiguous run of whole cache lines in the output.
+// Where a pass takes its items from:
 enum Mode : int {
-  ARRAYS = 0,   // keys_in[j], vals_in[j]
-  QUERIES = 1,  // item j = (L[j/2] or R[j/2], j)
-  KEY_IDX = 2,  // keys_in[j], value j
+  ITEMS = 0,    // items_in[j]
+  QUERIES = 1,  // item j = ((L[j/2] or R[j/2]) << 32) | j
+  E_TAGS = 2,   // item j = (low half of items_in[j] << 32) | j
 };
 
 // Tile handled by this workgroup: XCD x = blockIdx % 8 takes the x-th
@@ -59,59 +72,135 @@ __device__ __forceinline__ int64_t item_index(int64_t tile0, int wave, int round
   return tile0 + (int64_t)wave * (64 * ROUNDS) + round * 64 + lane;
 }
 
-// Item j read straight from the queries.  Lanes 2i and 2i+1 of a round hold
-// the two ends of one query, so validity is shared through a lane swap.
-__device__ __forceinline__ void load_from_queries(const int32_t* __restrict__ L,
-                                                  const int32_t* __restrict__ R, int64_t N,
-                                                  int64_t n, int64_t j, uint32_t& key,
-                                                  uint32_t& val) {
-  int32_t x = 0;
-  if (j < N) x = (j & 1) ? R[j >> 1] : L[j >> 1];
-  const int32_t other = __shfl_xor(x, 1);
-  const int32_t l = (j & 1) ? other : x, r = (j & 1) ? x : other;
-  const bool ok = 0 <= l && l <= r && (int64_t)r < n;
-  key = ok ? (uint32_t)x : 0u;
-  val = (uint32_t)j;
+// Loading item j takes two steps so that a tile's loads can all be in
+// flight at once: load_raw reads memory (index clamped to the list, no
+// branch), finish_item builds the item.  Items j >= N are never counted.
+template <int MODE>
+__device__ __forceinline__ uint64_t load_raw(const uint64_t* __restrict__ items_in,
+                                             const int32_t* __restrict__ L,
+                                             const int32_t* __restrict__ R, int64_t N, int64_t j) {
+  const int64_t jc = j < N ? j : N - 1;
+  if (MODE == QUERIES) return (uint32_t)((jc & 1) ? R[jc >> 1] : L[jc >> 1]);
+  return items_in[jc];
 }
 
+// From the queries, item j is (position << 32) | j.  Lanes 2i and 2i+1 of a
+// round hold the two ends of one query, so validity is shared through a lane
+// swap; an invalid query's ends sort as position 0.
 template <int MODE>
-__device__ __forceinline__ void load_item(const uint32_t* __restrict__ keys_in,
-                                          const uint32_t* __restrict__ vals_in,
-                                          const int32_t* __restrict__ L,
-                                          const int32_t* __restrict__ R, int64_t N, int64_t n,
-                                          int64_t j, uint32_t& key, uint32_t& val) {
+__device__ __forceinline__ uint64_t finish_item(uint64_t raw, int64_t n, int64_t j) {
   if (MODE == QUERIES) {
-    load_from_queries(L, R, N, n, j, key, val);
-  } else {
-    const bool valid = j < N;
-    key = valid ? keys_in[j] : 0u;
-    val = MODE == KEY_IDX ? (uint32_t)j : (valid ? vals_in[j] : 0u);
+    const int32_t x = (int32_t)(uint32_t)raw;
+    const int32_t other = __shfl_xor(x, 1);
+    const int32_t l = (j & 1) ? other : x, r = (j & 1) ? x : other;
+    const bool ok = 0 <= l && l <= r && (int64_t)r < n;
+    return ((uint64_t)(ok ? (uint32_t)x : 0u) << 32) | (uint32_t)j;
   }
+  if (MODE == E_TAGS) return (raw << 32) | (uint32_t)j;
+  return raw;
 }
 
+__device__ __forceinline__ uint32_t digit_of(uint64_t item, int shift, uint32_t mask) {
+  return (uint32_t)(item >> (32 + shift)) & mask;
+}
+
+constexpr int MAX_PASSES = 4;
+// Tiles per histogram workgroup: one while the grid is small (every tile's
+// loads then start at once), up to 8 for long lists (fewer global atomics).
+int hist_tiles(int64_t num_tiles) {
+  const int64_t t = num_tiles / 1024;
+  return t < 1 ? 1 : (t > 8 ? 8 : (int)t);
+}
+constexpr int LOOKBACK = 8;  // predecessors read per look-back step
+constexpr uint64_t ST_AGG = 1ull << 62;
+constexpr uint64_t ST_INC = 2ull << 62;
+constexpr uint64_t ST_VAL = (1ull << 62) - 1;
+constexpr uint32_t SPIN_LIMIT = 1u << 18;
+
+struct Digits {  // the digit split of one sort: pass p covers key bits
+  int passes;    // [shift[p], shift[p] + bits[p])
+  int shift[MAX_PASSES];
+  int bits[MAX_PASSES];
+};
+
+// Balanced split of nbits key bits starting at bit `base` into the fewest
+// passes of at most 8 bits (27 bits -> 7, 7, 7, 6): every pass then has
+// digits of similar spread, which keeps LDS counters uncontended and digit
+// runs long.
+Digits split_digits(int base, int nbits) {
+  Digits d{};
+  d.passes = (nbits + RADIX_BITS - 1) / RADIX_BITS;
+  if (d.passes < 1) d.passes = 1;
+  const int w = (nbits + d.passes - 1) / d.passes;
+  int at = 0;
+  for (int p = 0; p < d.passes; ++p) {
+    d.shift[p] = base + at;
+    d.bits[p] = nbits - at < w ? nbits - at : w;
+    if (d.bits[p] < 1) d.bits[p] = 1;
+    at += w;
+  }
+  return d;
+}
+
+__device__ __forceinline__ uint64_t load_status(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_status(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Clears what the sweeps accumulate into: digit totals, tickets, abort word,
+// and the first pass's tile status words.
+__global__ __launch_bounds__(WG) void k_os_clear(uint32_t* __restrict__ hist,
+                                                 uint32_t* __restrict__ tickets,
+                                                 uint32_t* __restrict__ abort_word,
+                                                 uint64_t* __restrict__ status0,
+                                                 int64_t status_words) {
+  const int64_t i0 = (int64_t)blockIdx.x * WG + threadIdx.x;
+  if (blockIdx.x == 0) {
+#pragma unroll
+    for (int p = 0; p < MAX_PASSES; ++p) hist[p * RADIX + threadIdx.x] = 0;
+    if (threadIdx.x < MAX_PASSES) tickets[threadIdx.x] = 0;
+    if (threadIdx.x == 0) *abort_word = 0;
+  }
+  for (int64_t i = i0; i < status_words; i += (int64_t)gridDim.x * WG) status0[i] = 0;
+}
+
+// Digit totals of every pass: per-workgroup counts in LDS over per_group
+// tiles, then one global atomic add per digit.
 template <int MODE>
-__global__ __launch_bounds__(WG) void k_radix_count(const uint32_t* __restrict__ keys_in,
-                                                    const int32_t* __restrict__ L,
-                                                    const int32_t* __restrict__ R, int64_t N,
-                                                    int64_t n, int shift, int bits,
-                                                    uint32_t* __restrict__ counts,
-                                                    int64_t num_tiles) {
-  __shared__ uint32_t hist[RADIX];
-  const int64_t tile = xcd_tile(num_tiles);
-  if (tile < 0) return;
+__global__ __launch_bounds__(WG) void k_os_hist(const uint64_t* __restrict__ items_in,
+                                                const int32_t* __restrict__ L,
+                                                const int32_t* __restrict__ R, int64_t N,
+                                                int64_t n, Digits dg, int per_group,
+                                                uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[MAX_PASSES][RADIX];
   const int lane = lane_id(), wave = threadIdx.x >> 6;
-  const int64_t tile0 = tile * TILE;
-  const uint32_t mask = (1u << bits) - 1u;
-  hist[threadIdx.x] = 0;
+#pragma unroll
+  for (int p = 0; p < MAX_PASSES; ++p) h[p][threadIdx.x] = 0;
   __syncthreads();
-  for (int rd = 0; rd < ROUNDS; ++rd) {
-    const int64_t j = item_index(tile0, wave, rd, lane);
-    uint32_t key, val;
-    load_item<MODE == QUERIES ? QUERIES : KEY_IDX>(keys_in, nullptr, L, R, N, n, j, key, val);
-    if (j < N) atomicAdd(&hist[(key >> shift) & mask], 1u);
+  for (int t = 0; t < per_group; ++t) {
+    const int64_t tile0 = ((int64_t)blockIdx.x * per_group + t) * TILE;
+    if (tile0 >= N) break;
+    uint64_t it[ROUNDS];
+#pragma unroll
+    for (int rd = 0; rd < ROUNDS; ++rd)
+      it[rd] = load_raw<MODE>(items_in, L, R, N, item_index(tile0, wave, rd, lane));
+#pragma unroll
+    for (int rd = 0; rd < ROUNDS; ++rd)
+      it[rd] = finish_item<MODE>(it[rd], n, item_index(tile0, wave, rd, lane));
+#pragma unroll
+    for (int rd = 0; rd < ROUNDS; ++rd) {
+      if (item_index(tile0, wave, rd, lane) < N)
+        for (int p = 0; p < dg.passes; ++p)
+          atomicAdd(&h[p][digit_of(it[rd], dg.shift[p], (1u << dg.bits[p]) - 1u)], 1u);
+    }
   }
   __syncthreads();
-  counts[(int64_t)threadIdx.x * num_tiles + tile] = hist[threadIdx.x];
+  for (int p = 0; p < dg.passes; ++p) {
+    const uint32_t c = h[p][threadIdx.x];
+    if (c) atomicAdd(&hist[p * RADIX + threadIdx.x], c);
+  }
 }
 
 // Exclusive scan of 256 values held one per thread; returns the total.
@@ -137,65 +226,54 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* t
   return total;
 }
 
-__global__ __launch_bounds__(WG) void k_radix_rowscan(uint32_t* __restrict__ counts,
-                                                      int64_t num_tiles,
-                                                      uint32_t* __restrict__ row_total) {
-  __shared__ uint32_t tmp[WG / 64];
-  uint32_t* row = counts + (int64_t)blockIdx.x * num_tiles;
-  uint32_t carry = 0;
-  for (int64_t base = 0; base < num_tiles; base += 4 * WG) {
-    uint32_t v[4], s = 0;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int64_t t = base + threadIdx.x * 4 + c;
-      v[c] = t < num_tiles ? row[t] : 0u;
-      s += v[c];
-    }
-    uint32_t excl;
-    const uint32_t total = block_exclusive_scan(s, tmp, excl);
-    uint32_t run = carry + excl;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int64_t t = base + threadIdx.x * 4 + c;
-      if (t < num_tiles) row[t] = run;
-      run += v[c];
-    }
-    carry += total;
-  }
-  if (threadIdx.x == 0) row_total[blockIdx.x] = carry;
-}
-
 template <int MODE>
-__global__ __launch_bounds__(WG) void k_radix_scatter(
-    const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
-    const int32_t* __restrict__ L, const int32_t* __restrict__ R, int64_t N, int64_t n, int shift,
-    int bits, const uint32_t* __restrict__ counts, const uint32_t* __restrict__ row_total,
-    int64_t num_tiles, uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out) {
+__global__ __launch_bounds__(WG) void k_os_pass(const uint64_t* __restrict__ items_in,
+                                                const int32_t* __restrict__ L,
+                                                const int32_t* __restrict__ R, int64_t N,
+                                                int64_t n, int shift, int bits,
+                                                const uint32_t* __restrict__ hist,
+                                                uint64_t* status, uint64_t* status_next,
+                                                uint32_t* ticket, uint32_t* abort_word,
+                                                uint64_t* __restrict__ items_out,
+                                                int32_t* __restrict__ LR) {
   __shared__ uint32_t wave_cnt[WG / 64][RADIX];
   __shared__ uint32_t local_start[RADIX];
   __shared__ uint32_t global_start[RADIX];
   __shared__ uint32_t tmp[WG / 64];
-  __shared__ uint32_t s_key[TILE];
-  __shared__ uint32_t s_val[TILE];
+  __shared__ uint64_t s_item[TILE];
+  __shared__ uint32_t s_tile;
 
-  const int64_t tile = xcd_tile(num_tiles);
-  if (tile < 0) return;
   const int lane = lane_id(), wave = threadIdx.x >> 6;
+  const uint32_t total = hist[threadIdx.x];  // in flight with the ticket
+  if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
+#pragma unroll
+  for (int w = 0; w < WG / 64; ++w) wave_cnt[w][threadIdx.x] = 0;
+  // digit offsets of this pass: exclusive scan of the digit totals
+  uint32_t digit_base;
+  block_exclusive_scan(total, tmp, digit_base);
+  const int64_t tile = s_tile;  // tiles in the order workgroups started
   const int64_t tile0 = tile * TILE;
   const uint32_t mask = (1u << bits) - 1u;
   const uint64_t lt = (1ull << lane) - 1ull;
+  if (status_next) status_next[tile * RADIX + threadIdx.x] = 0;  // for the next pass
 
+  // this wave's items: tile0 + wave * 64 * ROUNDS + round * 64 + lane, the
+  // first nval of them inside the list
+  const int64_t wbase = tile0 + (int64_t)wave * (64 * ROUNDS);
+  const int nval = N - wbase <= 0 ? 0 : (N - wbase >= 64 * ROUNDS ? 64 * ROUNDS : (int)(N - wbase));
+  uint64_t item[ROUNDS];
+  uint32_t rank[ROUNDS];
+  // all loads of the tile first, so they are in flight together
 #pragma unroll
-  for (int w = 0; w < WG / 64; ++w) wave_cnt[w][threadIdx.x] = 0;
-  __syncthreads();
-
-  uint32_t key[ROUNDS], val[ROUNDS], rank[ROUNDS];
+  for (int rd = 0; rd < ROUNDS; ++rd)
+    item[rd] = load_raw<MODE>(items_in, L, R, N, wbase + rd * 64 + lane);
+#pragma unroll
+  for (int rd = 0; rd < ROUNDS; ++rd)
+    item[rd] = finish_item<MODE>(item[rd], n, wbase + rd * 64 + lane);
 #pragma unroll
   for (int rd = 0; rd < ROUNDS; ++rd) {
-    const int64_t j = item_index(tile0, wave, rd, lane);
-    const bool valid = j < N;
-    load_item<MODE>(keys_in, vals_in, L, R, N, n, j, key[rd], val[rd]);
-    const uint32_t d = (key[rd] >> shift) & mask;
+    const bool valid = rd * 64 + lane < nval;
+    const uint32_t d = digit_of(item[rd], shift, mask);
     uint64_t match = ballot(valid);
     for (int b = 0; b < bits; ++b) {
       const bool bit = (d >> b) & 1u;
@@ -209,54 +287,88 @@ __global__ __launch_bounds__(WG) void k_radix_scatter(
   }
   __syncthreads();
 
-  // per digit: offsets of the waves inside the tile, then digit order in the tile
-  {
-    const int d = threadIdx.x;
-    uint32_t run = 0;
+  // thread d: this tile's count of digit d, published at once so that later
+  // tiles can go on; then the tile is staged in LDS in digit order while
+  // earlier tiles publish theirs
+  const int d = threadIdx.x;
+  uint32_t run = 0;  // items of digit d in this tile; waves' offsets in place
 #pragma unroll
-    for (int w = 0; w < WG / 64; ++w) {
-      const uint32_t c = wave_cnt[w][d];
-      wave_cnt[w][d] = run;
-      run += c;
-    }
+  for (int w = 0; w < WG / 64; ++w) {
+    const uint32_t c = wave_cnt[w][d];
+    wave_cnt[w][d] = run;
+    run += c;
+  }
+  uint64_t* mine = status + tile * RADIX + d;
+  store_status(mine, (tile == 0 ? ST_INC : ST_AGG) | run);
+  {
     uint32_t excl;
     block_exclusive_scan(run, tmp, excl);
     local_start[d] = excl;
-    uint32_t base_excl;
-    block_exclusive_scan(row_total[d], tmp, base_excl);
-    global_start[d] = base_excl + counts[(int64_t)d * num_tiles + tile];
   }
   __syncthreads();
-
 #pragma unroll
   for (int rd = 0; rd < ROUNDS; ++rd) {
-    const int64_t j = item_index(tile0, wave, rd, lane);
-    if (j < N) {
-      const uint32_t d = (key[rd] >> shift) & mask;
-      const uint32_t lp = local_start[d] + wave_cnt[wave][d] + rank[rd];
-      if (lp < (uint32_t)TILE) {  // always true for consistent ranks
-        s_key[lp] = key[rd];
-        s_val[lp] = val[rd];
-      }
+    if (rd * 64 + lane < nval) {
+      const uint32_t dd = digit_of(item[rd], shift, mask);
+      const uint32_t lp = local_start[dd] + wave_cnt[wave][dd] + rank[rd];
+      if (lp < (uint32_t)TILE) s_item[lp] = item[rd];  // always true for consistent ranks
     }
   }
+
+  // look back for the number of digit-d items in all earlier tiles: read
+  // LOOKBACK predecessors' words at once, newest first, and take values up to
+  // the first inclusive one, or stop at an unpublished one and read again
+  uint64_t before = 0;
+  if (tile > 0) {
+    int64_t j = tile - 1;
+    uint32_t spins = 0;
+    for (;;) {
+      uint64_t w[LOOKBACK];
+#pragma unroll
+      for (int i = 0; i < LOOKBACK; ++i)
+        w[i] = j - i >= 0 ? load_status(status + (j - i) * RADIX + d) : 0;
+      bool done = false;
+      int used = 0;
+#pragma unroll
+      for (int i = 0; i < LOOKBACK; ++i) {
+        if (done || used != i || (w[i] & ~ST_VAL) == 0) continue;
+        before += w[i] & ST_VAL;
+        done = (w[i] & ST_INC) != 0;
+        used = i + 1;
+      }
+      if (done) break;
+      j -= used;
+      if (used == 0) {  // the nearest unread predecessor has not published yet
+        if (++spins > SPIN_LIMIT ||
+            __hip_atomic_load(abort_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          __hip_atomic_store(abort_word, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+    store_status(mine, ST_INC | (before + run));
+  }
+  global_start[d] = digit_base + (uint32_t)before;
   __syncthreads();
 
   const int64_t tile_n = N - tile0 < TILE ? N - tile0 : TILE;
   for (int t = threadIdx.x; t < tile_n; t += WG) {
-    const uint32_t k = s_key[t];
-    const uint32_t d = (k >> shift) & mask;
-    const uint32_t dst = global_start[d] + (uint32_t)t - local_start[d];
+    const uint64_t x = s_item[t];
+    const uint32_t dd = digit_of(x, shift, mask);
+    const uint32_t dst = global_start[dd] + (uint32_t)t - local_start[dd];
     if ((int64_t)dst < N) {  // always true for consistent counts
-      keys_out[dst] = k;
-      vals_out[dst] = s_val[t];
+      items_out[dst] = x;
+      // last pass of the endpoint sort: the remap, LR[tag] = slot (minus
+      // one for a right end), written here directly
+      const uint32_t g = (uint32_t)x;
+      if (LR && (int64_t)g < N) LR[g] = (g & 1u) ? (int32_t)dst - 1 : (int32_t)dst;
     }
   }
 }
 
-// Remap writes from (tag, slot) pairs ordered by the top bits of the tag.
-__global__ __launch_bounds__(WG) void k_remap_apply(const uint32_t* __restrict__ tags,
-                                                    const uint32_t* __restrict__ slots,
+// Remap writes from (tag, slot) items ordered by the top bits of the tag.
+__global__ __launch_bounds__(WG) void k_remap_apply(const uint64_t* __restrict__ items,
                                                     int64_t N, int32_t* __restrict__ LR,
                                                     int64_t num_chunks) {
   const int64_t chunk = xcd_tile(num_chunks);
@@ -265,10 +377,28 @@ __global__ __launch_bounds__(WG) void k_remap_apply(const uint32_t* __restrict__
   for (int i = 0; i < 4; ++i) {
     const int64_t j = chunk * (4 * WG) + i * WG + threadIdx.x;
     if (j < N) {
-      const uint32_t t = tags[j], s = slots[j];
+      const uint64_t x = items[j];
+      const uint32_t t = (uint32_t)(x >> 32), s = (uint32_t)x;
       if ((int64_t)t < N) LR[t] = (t & 1u) ? (int32_t)s - 1 : (int32_t)s;
     }
   }
+}
+
+// Split / join of the packed sorted list (for the single-stage entry points).
+__global__ __launch_bounds__(WG) void k_unpack(const uint64_t* __restrict__ E, int64_t N,
+                                               int32_t* __restrict__ pos,
+                                               int32_t* __restrict__ tag) {
+  const int64_t j = (int64_t)blockIdx.x * WG + threadIdx.x;
+  if (j < N) {
+    pos[j] = (int32_t)(E[j] >> 32);
+    tag[j] = (int32_t)(uint32_t)E[j];
+  }
+}
+__global__ __launch_bounds__(WG) void k_pack(const int32_t* __restrict__ pos,
+                                             const int32_t* __restrict__ tag, int64_t N,
+                                             uint64_t* __restrict__ E) {
+  const int64_t j = (int64_t)blockIdx.x * WG + threadIdx.x;
+  if (j < N) E[j] = ((uint64_t)(uint32_t)pos[j] << 32) | (uint32_t)tag[j];
 }
 
 int bit_length(uint64_t x) {
@@ -281,8 +411,9 @@ int bit_length(uint64_t x) {
 }
 
 struct SortLayout {
-  int64_t N, num_tiles;
-  size_t off_key, off_val, off_counts, off_total, bytes;
+  int64_t N, num_tiles, hist_groups;
+  int hist_per_group;
+  size_t off_items, off_status0, off_status1, off_hist, off_tickets, off_abort, bytes;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -291,44 +422,76 @@ SortLayout sort_layout(int64_t q) {
   SortLayout s{};
   s.N = 2 * q;
   s.num_tiles = (s.N + TILE - 1) / TILE;
+  s.hist_per_group = hist_tiles(s.num_tiles);
+  s.hist_groups = (s.num_tiles + s.hist_per_group - 1) / s.hist_per_group;
   size_t o = 0;
-  s.off_key = o;
-  o = align256(o + sizeof(uint32_t) * (size_t)s.N);
-  s.off_val = o;
-  o = align256(o + sizeof(uint32_t) * (size_t)s.N);
-  s.off_counts = o;
-  o = align256(o + sizeof(uint32_t) * (size_t)RADIX * (size_t)s.num_tiles);
-  s.off_total = o;
-  o = align256(o + sizeof(uint32_t) * RADIX);
+  auto take = [&o](size_t bytes) {
+    const size_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  s.off_items = take(sizeof(uint64_t) * (size_t)s.N);
+  s.off_status0 = take(sizeof(uint64_t) * (size_t)RADIX * (size_t)s.num_tiles);
+  s.off_status1 = take(sizeof(uint64_t) * (size_t)RADIX * (size_t)s.num_tiles);
+  s.off_hist = take(sizeof(uint32_t) * (size_t)MAX_PASSES * RADIX);
+  s.off_tickets = take(sizeof(uint32_t) * MAX_PASSES);
+  s.off_abort = take(sizeof(uint32_t));
   s.bytes = o;
   return s;
 }
 
 struct SortBufs {
-  uint32_t *tkey, *tval, *counts, *total;
+  uint64_t* items;
+  uint64_t* status[2];
+  uint32_t *hist, *tickets, *abort_word;
 };
 
 SortBufs sort_bufs(const SortLayout& lay, void* ws) {
   char* base = static_cast<char*>(ws);
-  return {reinterpret_cast<uint32_t*>(base + lay.off_key),
-          reinterpret_cast<uint32_t*>(base + lay.off_val),
-          reinterpret_cast<uint32_t*>(base + lay.off_counts),
-          reinterpret_cast<uint32_t*>(base + lay.off_total)};
+  SortBufs b;
+  b.items = reinterpret_cast<uint64_t*>(base + lay.off_items);
+  b.status[0] = reinterpret_cast<uint64_t*>(base + lay.off_status0);
+  b.status[1] = reinterpret_cast<uint64_t*>(base + lay.off_status1);
+  b.hist = reinterpret_cast<uint32_t*>(base + lay.off_hist);
+  b.tickets = reinterpret_cast<uint32_t*>(base + lay.off_tickets);
+  b.abort_word = reinterpret_cast<uint32_t*>(base + lay.off_abort);
+  return b;
 }
 
-// One stable pass: count, scan, scatter.
+hipError_t clear(const SortLayout& lay, const SortBufs& b, hipStream_t stream) {
+  const int64_t status_words = lay.num_tiles * RADIX;
+  const int64_t grid = status_words / (4 * WG) + 1;
+  return launch(k_os_clear, dim3((unsigned)(grid < 1024 ? grid : 1024)), dim3(WG), 0, stream,
+                b.hist, b.tickets, b.abort_word, b.status[0], status_words);
+}
+
+// A whole sort: clear, histograms of every pass, then the passes.  Passes
+// alternate between the scratch buffer and `out` so the last lands in `out`.
 template <int MODE>
-hipError_t radix_pass(const uint32_t* kin, const uint32_t* vin, const int32_t* L, const int32_t* R,
-                      int64_t N, int64_t n, int shift, int bits, const SortLayout& lay,
-                      const SortBufs& b, uint32_t* kout, uint32_t* vout, hipStream_t stream) {
-  const dim3 grid((unsigned)xcd_grid(lay.num_tiles)), block(WG);
-  RMQ_TRY(launch(k_radix_count<MODE>, grid, block, 0, stream, kin, L, R, N, n, shift, bits,
-                 b.counts, lay.num_tiles));
-  // all RADIX rows, so that digits unused by a short pass get total 0
-  RMQ_TRY(launch(k_radix_rowscan, dim3(RADIX), block, 0, stream, b.counts, lay.num_tiles,
-                 b.total));
-  RMQ_TRY(launch(k_radix_scatter<MODE>, grid, block, 0, stream, kin, vin, L, R, N, n, shift,
-                 bits, b.counts, b.total, lay.num_tiles, kout, vout));
+hipError_t onesweep(const uint64_t* src, const int32_t* L, const int32_t* R, int64_t N, int64_t n,
+                    const Digits& dg, const SortLayout& lay, const SortBufs& b, uint64_t* out,
+                    int32_t* LR, hipStream_t stream) {
+  RMQ_TRY(clear(lay, b, stream));
+  RMQ_TRY(launch(k_os_hist<MODE>, dim3((unsigned)lay.hist_groups), dim3(WG), 0, stream, src, L, R,
+                 N, n, dg, lay.hist_per_group, b.hist));
+  const uint64_t* in = src;
+  for (int p = 0; p < dg.passes; ++p) {
+    const bool to_out = ((dg.passes - 1 - p) % 2) == 0;
+    uint64_t* dst = to_out ? out : b.items;
+    uint64_t* st = b.status[p & 1];
+    uint64_t* st_next = p + 1 < dg.passes ? b.status[(p + 1) & 1] : nullptr;
+    int32_t* lr = p + 1 < dg.passes ? nullptr : LR;
+    const dim3 grid((unsigned)lay.num_tiles), block(WG);
+    if (p == 0)
+      RMQ_TRY(launch(k_os_pass<MODE>, grid, block, 0, stream, in, L, R, N, n, dg.shift[p],
+                     dg.bits[p], b.hist + p * RADIX, st, st_next, b.tickets + p, b.abort_word,
+                     dst, lr));
+    else
+      RMQ_TRY(launch(k_os_pass<ITEMS>, grid, block, 0, stream, in, L, R, N, n, dg.shift[p],
+                     dg.bits[p], b.hist + p * RADIX, st, st_next, b.tickets + p, b.abort_word,
+                     dst, lr));
+    in = dst;
+  }
   return hipSuccess;
 }
 
@@ -337,52 +500,62 @@ hipError_t radix_pass(const uint32_t* kin, const uint32_t* vin, const int32_t* L
 size_t sort_workspace_bytes(int64_t q) { return q > 0 ? sort_layout(q).bytes : 0; }
 
 hipError_t launch_sort_endpoints(const int32_t* L, const int32_t* R, int64_t q, int64_t n,
-                                 int32_t* pos, int32_t* tag, void* ws, size_t ws_bytes,
+                                 uint64_t* E, int32_t* LR, void* ws, size_t ws_bytes,
                                  hipStream_t stream) {
   if (q <= 0) return hipSuccess;
   const SortLayout lay = sort_layout(q);
   if (ws_bytes < lay.bytes) return hipErrorInvalidValue;
   const SortBufs b = sort_bufs(lay, ws);
-  uint32_t* okey = reinterpret_cast<uint32_t*>(pos);
-  uint32_t* oval = reinterpret_cast<uint32_t*>(tag);
-
   const int nbits = n > 1 ? bit_length((uint64_t)(n - 1)) : 1;
-  const int passes = (nbits + RADIX_BITS - 1) / RADIX_BITS;
-  const uint32_t* src_k = nullptr;
-  const uint32_t* src_v = nullptr;
-  for (int p = 0; p < passes; ++p) {
-    const int shift = p * RADIX_BITS;
-    const int bits = nbits - shift < RADIX_BITS ? nbits - shift : RADIX_BITS;
-    // passes alternate between the scratch pair and the output pair so that
-    // the last one lands in the output
-    const bool to_out = ((passes - 1 - p) % 2) == 0;
-    uint32_t* dk = to_out ? okey : b.tkey;
-    uint32_t* dv = to_out ? oval : b.tval;
-    if (p == 0)
-      RMQ_TRY(radix_pass<QUERIES>(nullptr, nullptr, L, R, lay.N, n, shift, bits, lay, b, dk, dv,
-                                  stream));
-    else
-      RMQ_TRY(radix_pass<ARRAYS>(src_k, src_v, nullptr, nullptr, lay.N, n, shift, bits, lay, b,
-                                 dk, dv, stream));
-    src_k = dk;
-    src_v = dv;
-  }
-  return hipSuccess;
+  return onesweep<QUERIES>(nullptr, L, R, lay.N, n, split_digits(0, nbits), lay, b, E, LR,
+                           stream);
 }
 
-hipError_t launch_remap(const int32_t* tag, int64_t q, int32_t* LR, void* ws, size_t ws_bytes,
+hipError_t launch_remap(const uint64_t* E, int64_t q, int32_t* LR, void* ws, size_t ws_bytes,
                         hipStream_t stream) {
   if (q <= 0) return hipSuccess;
   const SortLayout lay = sort_layout(q);
   if (ws_bytes < lay.bytes) return hipErrorInvalidValue;
   const SortBufs b = sort_bufs(lay, ws);
+  // one sweep on the top (at most 8) bits of the tag; its output goes to the
+  // scratch item buffer (E itself is still needed by the contraction)
   const int tbits = lay.N > 1 ? bit_length((uint64_t)(lay.N - 1)) : 1;
-  const int shift = tbits > RADIX_BITS ? tbits - RADIX_BITS : 0;
-  RMQ_TRY(radix_pass<KEY_IDX>(reinterpret_cast<const uint32_t*>(tag), nullptr, nullptr, nullptr,
-                              lay.N, 0, shift, tbits - shift, lay, b, b.tkey, b.tval, stream));
+  const int top = tbits > RADIX_BITS ? RADIX_BITS : tbits;
+  Digits dg{};
+  dg.passes = 1;
+  dg.shift[0] = tbits - top;
+  dg.bits[0] = top;
+  uint64_t* sorted = b.items;
+  RMQ_TRY(clear(lay, b, stream));
+  RMQ_TRY(launch(k_os_hist<E_TAGS>, dim3((unsigned)lay.hist_groups), dim3(WG), 0, stream, E,
+                 static_cast<const int32_t*>(nullptr), static_cast<const int32_t*>(nullptr),
+                 lay.N, (int64_t)0, dg, lay.hist_per_group, b.hist));
+  RMQ_TRY(launch(k_os_pass<E_TAGS>, dim3((unsigned)lay.num_tiles), dim3(WG), 0, stream, E,
+                 static_cast<const int32_t*>(nullptr), static_cast<const int32_t*>(nullptr),
+                 lay.N, (int64_t)0, dg.shift[0], dg.bits[0], b.hist, b.status[0],
+                 static_cast<uint64_t*>(nullptr), b.tickets, b.abort_word, sorted,
+                 static_cast<int32_t*>(nullptr)));
   const int64_t chunks = (lay.N + 4 * WG - 1) / (4 * WG);
-  RMQ_TRY(launch(k_remap_apply, dim3((unsigned)xcd_grid(chunks)), dim3(WG), 0, stream, b.tkey,
-                 b.tval, lay.N, LR, chunks));
+  RMQ_TRY(launch(k_remap_apply, dim3((unsigned)xcd_grid(chunks)), dim3(WG), 0, stream, sorted,
+                 lay.N, LR, chunks));
+  return hipSuccess;
+}
+
+hipError_t launch_unpack_endpoints(const uint64_t* E, int64_t q, int32_t* pos, int32_t* tag,
+                                   hipStream_t stream) {
+  if (q <= 0) return hipSuccess;
+  const int64_t N = 2 * q;
+  RMQ_TRY(launch(k_unpack, dim3((unsigned)((N + WG - 1) / WG)), dim3(WG), 0, stream, E, N, pos,
+                 tag));
+  return hipSuccess;
+}
+
+hipError_t launch_pack_endpoints(const int32_t* pos, const int32_t* tag, int64_t q, uint64_t* E,
+                                 hipStream_t stream) {
+  if (q <= 0) return hipSuccess;
+  const int64_t N = 2 * q;
+  RMQ_TRY(launch(k_pack, dim3((unsigned)((N + WG - 1) / WG)), dim3(WG), 0, stream, pos, tag, N,
+                 E));
   return hipSuccess;
 }
 
