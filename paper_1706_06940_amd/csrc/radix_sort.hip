@@ -101,7 +101,7 @@ __device__ __forceinline__ uint64_t finish_item(uint64_t raw, int64_t n, int64_t
 }
 
 __device__ __forceinline__ uint32_t digit_of(uint64_t item, int shift, uint32_t mask) {
-  return (uint32_t)(item >> (32 + shift)) & mask;
+  return ((uint32_t)(item >> 32) >> shift) & mask;
 }
 
 constexpr int MAX_PASSES = 4;
@@ -274,16 +274,24 @@ __global__ __launch_bounds__(WG) void k_os_pass(const uint64_t* __restrict__ ite
   for (int rd = 0; rd < ROUNDS; ++rd) {
     const bool valid = rd * 64 + lane < nval;
     const uint32_t d = digit_of(item[rd], shift, mask);
-    uint64_t match = ballot(valid);
-    for (int b = 0; b < bits; ++b) {
-      const bool bit = (d >> b) & 1u;
-      const uint64_t m = ballot(bit);
-      match &= bit ? m : ~m;
+    // lanes holding digit d: AND over the digit's bits of the ballot of that
+    // bit (or of its complement); digits have at most RADIX_BITS bits and
+    // the bits above `bits` are zero in every lane
+    const uint64_t vm = ballot(valid);
+    uint32_t mlo = (uint32_t)vm, mhi = (uint32_t)(vm >> 32);
+#pragma unroll
+    for (int b = 0; b < RADIX_BITS; ++b) {
+      const uint32_t x = (uint32_t)((int32_t)(d << (31 - b)) >> 31);  // bit b, spread
+      const uint64_t m = ballot(x != 0);
+      mlo &= ~((uint32_t)m ^ x);
+      mhi &= ~((uint32_t)(m >> 32) ^ x);
     }
+    const uint64_t match = ((uint64_t)mhi << 32) | mlo;
     const uint32_t before = wave_cnt[wave][d];
     rank[rd] = before + (uint32_t)__popcll(match & lt);
-    const bool leader = (match >> lane) == 1ull;  // highest lane of its digit group
-    if (valid && leader) wave_cnt[wave][d] = before + (uint32_t)__popcll(match);
+    // every lane of a digit group stores the same new count (an invalid
+    // lane's group holds the valid lanes of its digit, or none)
+    wave_cnt[wave][d] = before + (uint32_t)__popcll(match);
   }
   __syncthreads();
 
