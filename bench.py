@@ -62,6 +62,9 @@ def main() -> int:
     ap.add_argument("--no-batched", action="store_true", help="skip the many-arrays measurement")
     ap.add_argument("--no-served", action="store_true", help="skip the serving measurement")
     ap.add_argument("--served-requests", type=int, default=3000)
+    ap.add_argument("--blockmin-sweep", default="",
+                    help="counter-profiling mode: after --copy-calibration, one block-minima "
+                         "launch per listed block size on the n-element array, then exit")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -88,17 +91,26 @@ def main() -> int:
     A = torch.from_numpy(A_h).to(d)
     batches = [(torch.from_numpy(L).to(d), torch.from_numpy(R).to(d)) for L, R in batches_h]
     outs = [torch.empty(q, dtype=torch.int32, device=d) for q in qs]
-    k_full = args.k_full or rmq.default_block(n, max(qs), "full")
-    ks = {"full": k_full, "contracted": args.k_con}
-    k_used = {"full": {q: k_full for q in qs},
-              "contracted": {q: args.k_con or rmq.default_block(n, q, "contracted") for q in qs}}
+    # block size per batch: the autotuner's table for the full method (its
+    # entries all choose that method at this n), the contracted default else
+    rmq.load_plan_table()
+
+    def k_for(p, q):
+        if p == "full":
+            if args.k_full:
+                return args.k_full
+            k, path = rmq.plan(n, q)
+            return k if path == "full" else rmq.default_block(n, q, "full")
+        return args.k_con or rmq.default_block(n, q, "contracted")
+
+    k_used = {p: {q: k_for(p, q) for q in qs} for p in ("full", "contracted")}
     torch.cuda.synchronize()
 
     def step(timers=None):
         for p in paths:
             for j, q in enumerate(qs):
                 L, R = batches[j]
-                rmq.query_batch(A, L, R, path=p, block_size=ks[p], out=outs[j],
+                rmq.query_batch(A, L, R, path=p, block_size=k_used[p][q], out=outs[j],
                                 timer=timers[(p, j)] if timers else None)
 
     if args.copy_calibration:
@@ -108,6 +120,14 @@ def main() -> int:
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+
+    if args.blockmin_sweep:
+        ks = [int(x) for x in args.blockmin_sweep.split(",") if x]
+        for k in ks:
+            rmq.block_minima(A, k)
+        torch.cuda.synchronize()
+        print(json.dumps({"blockmin_sweep": ks, "n": n}), flush=True)
+        return 0
 
     for _ in range(args.warmup):
         step()
@@ -120,7 +140,7 @@ def main() -> int:
         for p in paths:
             for j, q in enumerate(qs):
                 L, R = batches[j]
-                got = rmq.query_batch(A, L, R, path=p, block_size=ks[p]).cpu().numpy()
+                got = rmq.query_batch(A, L, R, path=p, block_size=k_used[p][q]).cpu().numpy()
                 exp = orc.rmq_sparse_table(A_h, batches_h[j][0], batches_h[j][1], 32)
                 if not np.array_equal(got, exp):
                     print(f"[bench] MISMATCH path={p} q={q}", file=sys.stderr, flush=True)
@@ -145,7 +165,7 @@ def main() -> int:
 
     # per-call and per-stage figures from the library's stage events
     breakdown = {}
-    blockmin_ms = []
+    blockmin = []  # (block size, ms) of every full-method block-minima launch
     for p in paths:
         for j, q in enumerate(qs):
             per = [timers[s][(p, j)].read() for s in range(args.steps)]
@@ -153,20 +173,27 @@ def main() -> int:
             stages = [statistics.median(st[i] for st, _ in per) for i in range(4)]
             breakdown[f"{p}/q={q}"] = {
                 "ms": round(tot, 4), "queries_per_s": round(q / (tot / 1e3), 1),
+                "block_size": k_used[p][q],
                 "stage_ms": {name: round(v, 4) for name, v in zip(rmq.STAGE_NAMES, stages)}}
             if p == "full":
-                blockmin_ms += [st[1] for st, _ in per]
+                blockmin += [(k_used[p][q], st[1]) for st, _ in per]
     roofline = None
-    if blockmin_ms:
-        avg = sum(blockmin_ms) / len(blockmin_ms)
-        nb = -(-n // k_full)
-        algo_bytes = 4 * n + 8 * nb
-        achieved = algo_bytes / (avg / 1e3) / 1e9
+    if blockmin:
+        # algorithmic bytes of one launch: A once + one 8-byte key per block
+        algo = [4 * n + 8 * (-(-n // k)) for k, _ in blockmin]
+        avg_ms = sum(ms for _, ms in blockmin) / len(blockmin)
+        avg_bytes = sum(algo) / len(algo)
+        achieved = sum(algo) / (sum(ms for _, ms in blockmin) / 1e3) / 1e9
+        prof = profiled_traffic(n)
+        traffic = None
+        if prof is not None and all(str(k) in prof for k, _ in blockmin):
+            traffic = round(sum(prof[str(k)] for k, _ in blockmin) / len(blockmin))
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": profiled_traffic(n, k_full),
-                    "kernel": "k_blockmin_i32", "avg_ms": round(avg, 5),
-                    "algorithmic_bytes": algo_bytes,
+                    "traffic": traffic,
+                    "kernel": "k_blockmin_i32", "avg_ms": round(avg_ms, 5),
+                    "algorithmic_bytes": round(avg_bytes),
+                    "launches": len(blockmin),
                     "traffic_source": os.path.relpath(TRAFFIC_PROFILE, ROOT)}
 
     cpu = None
@@ -212,20 +239,23 @@ def main() -> int:
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_blockmin_i32_n1e8_traffic.md")
 
 
-def profiled_traffic(n: int, k: int):
-    """HBM bytes per launch of the block-minima kernel from the committed
-    counter profile (FETCH_SIZE / WRITE_SIZE, calibrated), when it was taken on
-    this workload and on the kernel source as it is now; else None."""
+def profiled_traffic(n: int):
+    """HBM bytes per launch of the block-minima kernel, by block size, from the
+    committed counter profile (FETCH_SIZE / WRITE_SIZE, calibrated), when it
+    was taken on this workload and on the kernel source as it is now; else
+    None."""
     import hashlib
 
-    if (n, k) != (10 ** 8, 1024) or not os.path.exists(TRAFFIC_PROFILE):
+    if n != 10 ** 8 or not os.path.exists(TRAFFIC_PROFILE):
         return None
     text = open(TRAFFIC_PROFILE).read()
     block = text.split("```json", 1)[1].split("```", 1)[0]
     meta = json.loads(block)
     src = os.path.join(ROOT, meta["source"])
     cur = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    return meta["traffic_bytes"] if cur == meta["source_sha256"] else None
+    if cur != meta["source_sha256"] or meta.get("n") != n:
+        return None
+    return {k: v["traffic_bytes"] for k, v in meta["per_block_size"].items()}
 
 
 def time_runs(fn, stream, warmup=2, reps=5):

@@ -61,11 +61,24 @@ __device__ __forceinline__ void st_tile(uint64_t* __restrict__ st, int64_t nb, i
   const int64_t i0 = tile_r * TI;
   const uint64_t* src = st + (size_t)j0 * nb;
 
-  for (int idx = threadIdx.x; idx < rows * R; idx += WG) {
+  // all loads first (rows * R <= 2 * TILE entries, at most LOADS per
+  // thread), so that they are in flight together
+  constexpr int LOADS = 2 * TILE / WG;
+  uint64_t v[LOADS];
+#pragma unroll
+  for (int u = 0; u < LOADS; ++u) {
+    const int idx = threadIdx.x + u * WG;
     const int row = idx / R, c = idx % R;
     const int64_t r = r0 + c;
     const int64_t b = (i0 + row) * s + r;
-    buf0[idx] = (r < s && b < nb) ? src[b] : KEY_NONE;
+    const bool ok = idx < rows * R && r < s && b < nb;
+    v[u] = src[ok ? b : 0];
+    if (!ok) v[u] = KEY_NONE;
+  }
+#pragma unroll
+  for (int u = 0; u < LOADS; ++u) {
+    const int idx = threadIdx.x + u * WG;
+    if (idx < rows * R) buf0[idx] = v[u];
   }
   __syncthreads();
 
@@ -75,14 +88,24 @@ __device__ __forceinline__ void st_tile(uint64_t* __restrict__ st, int64_t nb, i
     const int half = 1 << (m - 1);
     const int rows_m = TI + H - ((1 << m) - 1);  // rows still needed by later levels
     uint64_t* dst = st + (size_t)(j0 + m) * nb;
-    for (int idx = threadIdx.x; idx < rows_m * R; idx += WG) {
-      const uint64_t v = umin64(cur[idx], cur[idx + half * R]);
-      nxt[idx] = v;
-      const int row = idx / R, c = idx % R;
-      if (row < TI) {
-        const int64_t r = r0 + c;
-        const int64_t b = (i0 + row) * s + r;
-        if (r < s && b < nb) dst[b] = v;
+    // unrolled, so the LDS reads of all of a thread's entries overlap
+    uint64_t w[LOADS];
+#pragma unroll
+    for (int u = 0; u < LOADS; ++u) {
+      const int idx = threadIdx.x + u * WG;
+      if (idx < rows_m * R) w[u] = umin64(cur[idx], cur[idx + half * R]);
+    }
+#pragma unroll
+    for (int u = 0; u < LOADS; ++u) {
+      const int idx = threadIdx.x + u * WG;
+      if (idx < rows_m * R) {
+        nxt[idx] = w[u];
+        const int row = idx / R, c = idx % R;
+        if (row < TI) {
+          const int64_t r = r0 + c;
+          const int64_t b = (i0 + row) * s + r;
+          if (r < s && b < nb) dst[b] = w[u];
+        }
       }
     }
     __syncthreads();
