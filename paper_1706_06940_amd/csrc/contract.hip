@@ -110,21 +110,25 @@ __global__ __launch_bounds__(WG) void k_contract(const int32_t* __restrict__ A, 
 
   // tile offsets of this lane's endpoint slots j = jlo + lane + 64k (first
   // KREG rounds), and of the slot before each; loads clamped to the list
+  // (rounds with no slot are skipped as a whole: the test is uniform)
+  const int rounds = marked ? (int)((jend - jlo + 63) >> 6) : 0;
   int32_t ep[KREG], epv[KREG];
   if (marked) {
+    const int32_t* Eh = reinterpret_cast<const int32_t*>(E) + 1;  // high words: positions
     int32_t raw[KREG];
 #pragma unroll
     for (int k = 0; k < KREG; ++k) {
       const int64_t j = jlo + lane + 64 * k;
-      raw[k] = (int32_t)(E[j < M ? j : M - 1] >> 32);
+      raw[k] = k < rounds ? Eh[2 * (j < M ? j : M - 1)] : 0;
     }
-    const int32_t raw_lo = (int32_t)(E[jlo > 0 ? jlo - 1 : 0] >> 32);
+    const int32_t raw_lo = Eh[2 * (jlo > 0 ? jlo - 1 : 0)];
 #pragma unroll
     for (int k = 0; k < KREG; ++k)
       ep[k] = jlo + lane + 64 * k < jend ? (int32_t)(raw[k] - t0) : T;
     const int32_t before_lo = jlo > 0 ? (int32_t)(raw_lo - t0) : -1;
 #pragma unroll
     for (int k = 0; k < KREG; ++k) {
+      if (k >= rounds) break;
       const int32_t up = __shfl_up(ep[k], 1);
       const int32_t wrap = k == 0 ? before_lo : __shfl(ep[k - 1], 63);
       epv[k] = lane == 0 ? wrap : up;
@@ -168,8 +172,10 @@ __global__ __launch_bounds__(WG) void k_contract(const int32_t* __restrict__ A, 
   }
   if (marked) {
 #pragma unroll
-    for (int k = 0; k < KREG; ++k)
+    for (int k = 0; k < KREG; ++k) {
+      if (k >= rounds) break;
       if (ep[k] >= 0 && ep[k] < T) atomicOr(&heads[wave][ep[k] >> 5], 1u << (ep[k] & 31));
+    }
     for (int64_t j = jlo + 64 * KREG + lane; j < jend; j += 64) {
       const int64_t e = epos(E, j) - t0;
       if (e >= 0 && e < T) atomicOr(&heads[wave][e >> 5], 1u << (e & 31));
@@ -243,6 +249,7 @@ __global__ __launch_bounds__(WG) void k_contract(const int32_t* __restrict__ A, 
   };
 #pragma unroll
   for (int k = 0; k < KREG; ++k) {
+    if (k >= rounds) break;
     const int64_t j = jlo + lane + 64 * k;
     if (j < jend) finish(j, ep[k], epv[k]);
   }
