@@ -274,19 +274,20 @@ __global__ __launch_bounds__(WG) void k_os_pass(const uint64_t* __restrict__ ite
   for (int rd = 0; rd < ROUNDS; ++rd) {
     const bool valid = rd * 64 + lane < nval;
     const uint32_t d = digit_of(item[rd], shift, mask);
-    // lanes holding digit d: AND over the digit's bits of the ballot of that
-    // bit (or of its complement); digits have at most RADIX_BITS bits and
-    // the bits above `bits` are zero in every lane
+    // lanes holding digit d: those whose every digit bit equals this lane's,
+    // i.e. outside the OR over the bits of (ballot of the bit) XOR (own bit
+    // spread over the word); bits above `bits` are zero in every lane and
+    // add nothing
     const uint64_t vm = ballot(valid);
-    uint32_t mlo = (uint32_t)vm, mhi = (uint32_t)(vm >> 32);
+    uint32_t xlo = 0, xhi = 0;
 #pragma unroll
     for (int b = 0; b < RADIX_BITS; ++b) {
       const uint32_t x = (uint32_t)((int32_t)(d << (31 - b)) >> 31);  // bit b, spread
       const uint64_t m = ballot(x != 0);
-      mlo &= ~((uint32_t)m ^ x);
-      mhi &= ~((uint32_t)(m >> 32) ^ x);
+      xlo |= (uint32_t)m ^ x;
+      xhi |= (uint32_t)(m >> 32) ^ x;
     }
-    const uint64_t match = ((uint64_t)mhi << 32) | mlo;
+    const uint64_t match = vm & ~(((uint64_t)xhi << 32) | xlo);
     const uint32_t before = wave_cnt[wave][d];
     rank[rd] = before + (uint32_t)__popcll(match & lt);
     // every lane of a digit group stores the same new count (an invalid
