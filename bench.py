@@ -62,6 +62,11 @@ def main() -> int:
     ap.add_argument("--no-batched", action="store_true", help="skip the many-arrays measurement")
     ap.add_argument("--no-served", action="store_true", help="skip the serving measurement")
     ap.add_argument("--served-requests", type=int, default=3000)
+    ap.add_argument("--no-flushed", action="store_true",
+                    help="skip the cache-flushed block-minima measurement")
+    ap.add_argument("--flushed-reps", type=int, default=7)
+    ap.add_argument("--no-resident", action="store_true",
+                    help="skip the resident-index query-only measurement")
     ap.add_argument("--blockmin-sweep", default="",
                     help="counter-profiling mode: after --copy-calibration, one block-minima "
                          "launch per listed block size on the n-element array, then exit")
@@ -196,6 +201,55 @@ def main() -> int:
                     "launches": len(blockmin),
                     "traffic_source": os.path.relpath(TRAFFIC_PROFILE, ROOT)}
 
+    # the same block-minima launches after a 1 GB write that evicts A from the
+    # L2s and the MALL (the paper's cache flush before every repetition)
+    if roofline is not None and not args.no_flushed:
+        scratch = torch.empty(1 << 28, dtype=torch.int32, device=d)
+        t_fl = rmq.Timer()
+        ms_fl, bytes_fl = [], []
+        for j, q in enumerate(qs):
+            L, R = batches[j]
+            for _ in range(args.flushed_reps):
+                scratch.fill_(j)
+                rmq.query_batch(A, L, R, path="full", block_size=k_used["full"][q], out=outs[j],
+                                timer=t_fl)
+                ms_fl.append(t_fl.read()[0][1])
+                bytes_fl.append(4 * n + 8 * (-(-n // k_used["full"][q])))
+        del scratch
+        med = statistics.median(b / (m / 1e3) / 1e9 for b, m in zip(bytes_fl, ms_fl))
+        roofline["flushed"] = {"achieved": round(med, 1), "frac": round(med / HBM_PEAK_GBS, 4),
+                               "launches": len(ms_fl),
+                               "how": "median over launches, each after writing 1 GiB of scratch"}
+
+    # resident index: build once, then query-only batches (Section 3.2's
+    # structure kept in HBM between batches)
+    resident = None
+    if not args.no_resident and "full" in paths:
+        k_res = k_used["full"][max(qs)]
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        idx = rmq.Index(A, k_res)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        build_ms = e0.elapsed_time(e1)
+        q_ms = {}
+        for j, q in enumerate(qs):
+            L, R = batches[j]
+            reps = []
+            for r in range(9):
+                e0.record(stream)
+                idx.query(L, R, out=outs[j])
+                e1.record(stream)
+                torch.cuda.synchronize()
+                if r >= 2:
+                    reps.append(e0.elapsed_time(e1))
+            q_ms[str(q)] = round(statistics.median(reps), 4)
+        resident = {"block_size": k_res, "index_bytes": idx.bytes, "build_ms": round(build_ms, 4),
+                    "query_ms": q_ms,
+                    "queries_per_s": {q: round(int(q) / (ms / 1e3), 1) for q, ms in q_ms.items()}}
+        del idx
+
     cpu = None
     if not args.no_cpu:
         import oracle
@@ -214,6 +268,16 @@ def main() -> int:
                "sample": (f"oracle Sparse Table over 32-element blocks, build + answers for "
                           f"each batch of the sweep q={qs} on the same n={n} array, "
                           f"{reps} sweeps in {dt:.1f}s on the host")}
+        # one thread, one sweep
+        threads = orc.num_threads()
+        orc.set_threads(1)
+        t = time.perf_counter()
+        for j, q in enumerate(qs):
+            orc.rmq_sparse_table(A_h, batches_h[j][0], batches_h[j][1], 32)
+        dt1 = time.perf_counter() - t
+        orc.set_threads(threads)
+        cpu["value_1thread"] = round(sum(qs) / dt1, 1)
+        cpu["sample_1thread"] = f"the same sweep once on 1 thread in {dt1:.1f}s"
 
     batched = None if args.no_batched else bench_batched(d)
     served = None if args.no_served else bench_served(d, args.served_requests)
@@ -230,6 +294,7 @@ def main() -> int:
                    "block_size": {p: k_used[p] for p in paths},
                    "parallelism": "single GPU"},
         "roofline": roofline, "cpu_baseline": cpu, "breakdown": breakdown,
+        "resident": resident,
         "batched": batched, "served": served,
     }
     print(json.dumps(line), flush=True)

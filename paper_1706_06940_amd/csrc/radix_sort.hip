@@ -18,7 +18,7 @@
 //                  the number of same-digit items in all earlier tiles by a
 //                  decoupled look-back over their published words (count +
 //                  "aggregate" or "inclusive" flag in one 64-bit word, read
-//                  eight predecessors at a time).  It then writes runs of
+//                  four predecessors at a time).  It then writes runs of
 //                  equal digits contiguously.  A tile only ever waits on tiles
 //                  that took their ticket earlier and are therefore running,
 //                  so the waits end; each is also bounded, and an exceeded
@@ -111,7 +111,7 @@ int hist_tiles(int64_t num_tiles) {
   const int64_t t = num_tiles / 1024;
   return t < 1 ? 1 : (t > 8 ? 8 : (int)t);
 }
-constexpr int LOOKBACK = 8;  // predecessors read per look-back step
+constexpr int LOOKBACK = 4;  // predecessors read per look-back step
 constexpr uint64_t ST_AGG = 1ull << 62;
 constexpr uint64_t ST_INC = 2ull << 62;
 constexpr uint64_t ST_VAL = (1ull << 62) - 1;
