@@ -65,6 +65,8 @@ def main() -> int:
     ap.add_argument("--no-flushed", action="store_true",
                     help="skip the cache-flushed block-minima measurement")
     ap.add_argument("--flushed-reps", type=int, default=7)
+    ap.add_argument("--no-skewed", action="store_true",
+                    help="skip the n = 1e9 skewed-query measurement")
     ap.add_argument("--no-resident", action="store_true",
                     help="skip the resident-index query-only measurement")
     ap.add_argument("--blockmin-sweep", default="",
@@ -279,6 +281,9 @@ def main() -> int:
         cpu["value_1thread"] = round(sum(qs) / dt1, 1)
         cpu["sample_1thread"] = f"the same sweep once on 1 thread in {dt1:.1f}s"
 
+    del A, batches, outs
+    torch.cuda.empty_cache()
+    skewed = None if args.no_skewed else bench_skewed(d)
     batched = None if args.no_batched else bench_batched(d)
     served = None if args.no_served else bench_served(d, args.served_requests)
 
@@ -294,7 +299,7 @@ def main() -> int:
                    "block_size": {p: k_used[p] for p in paths},
                    "parallelism": "single GPU"},
         "roofline": roofline, "cpu_baseline": cpu, "breakdown": breakdown,
-        "resident": resident,
+        "resident": resident, "skewed": skewed,
         "batched": batched, "served": served,
     }
     print(json.dumps(line), flush=True)
@@ -335,6 +340,53 @@ def time_runs(fn, stream, warmup=2, reps=5):
     e1.record(stream)
     stream.synchronize()
     return e0.elapsed_time(e1) / reps
+
+
+def bench_skewed(d, reps=5):
+    """n = 1e9 uniform int32 (4 GB, drawn in HBM by the generator's torch
+    form), q = 1e7: half short ranges (length uniform in [1, 1024]), half
+    uniform long ones.  The plain method with one block level and with two
+    (Section 3.3), and the contracted method; whole offline jobs (mean of
+    `reps` after a first run that also counts the entries read by partial-block
+    scans)."""
+    import torch
+
+    import paper_1706_06940_amd as rmq
+    import workloads as W
+
+    n, q = 10 ** 9, 10 ** 7
+    seed = W.BASE_SEED + 2
+    A = W.uniform_int31_torch(n, seed, 0, device=d)
+    L_h, R_h = W.skewed_queries(n, q, seed)
+    L, R = torch.from_numpy(L_h).to(d), torch.from_numpy(R_h).to(d)
+    out = torch.empty(q, dtype=torch.int32, device=d)
+    stream = torch.cuda.current_stream(d)
+    configs = [("full", 4096, 0), ("full", 16384, 0), ("full", 16384, 256), ("full", 65536, 256),
+               ("full", 65536, 1024), ("contracted", 0, 0)]
+    res = {}
+    ref = None
+    for path, k, k1 in configs:
+        stats = torch.zeros(2, dtype=torch.int64, device=d)
+        run = lambda st=None: rmq.query_batch(A, L, R, path=path, block_size=k,
+                                              sub_block_size=k1, out=out, stats=st)
+        run(stats)
+        torch.cuda.synchronize()
+        got = out.clone()
+        if ref is None:
+            ref = got
+        same = bool(torch.equal(got, ref))
+        ms = time_runs(run, stream, warmup=0, reps=reps)
+        name = f"{path}/k={k or 'default'}" + (f"/k1={k1}" if k1 else "")
+        scans, reads = stats.tolist()
+        res[name] = {"ms": round(ms, 4), "queries_per_s": round(q / (ms / 1e3), 1),
+                     "partial_scans": scans, "entries_read_by_scans": reads,
+                     "same_answers_as_first": same}
+        print(f"[bench] skewed {name}: {ms:.3f} ms", file=sys.stderr, flush=True)
+    del A
+    torch.cuda.empty_cache()
+    return {"workload": "n=1e9 int32 uniform in [0,2^31), q=1e7: 5e6 short ranges (length "
+                        "uniform in [1,1024]) and 5e6 uniform long ranges, shuffled",
+            "results": res}
 
 
 def bench_batched(d, count=256):

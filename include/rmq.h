@@ -92,10 +92,19 @@ typedef struct rmq_options {
     int32_t path;            /* rmq_path                                         */
     int64_t *bad_count;      /* device int64, optional: += invalid queries       */
     uint64_t *stats;         /* device uint64[2], optional: += scans performed,
-                                += elements scanned by partial-block scans       */
+                                += entries read by partial-block scans (elements,
+                                and k1-block minima with two block levels)       */
     void *workspace;         /* device scratch, optional (see rmq_workspace_bytes) */
     size_t workspace_bytes;
     rmq_timer *timer;        /* optional: records per-stage events on the stream */
+    int32_t sub_block_size;  /* Section 3.3, two block levels: k1, the size of the
+                                small blocks whose minima are also kept (0 = one
+                                level).  A power of two, 16 <= k1 < k.  Selects the
+                                plain method (path AUTO or FULL); partial blocks
+                                of size k are then read as k1-block minima plus
+                                at most two partial k1-blocks.  With block_size 0,
+                                k is the power of two nearest
+                                sqrt(n) * log2(n)^(2/3) (at least 2 * k1). */
 } rmq_options;
 
 /* A human-readable name for a status code (static storage). */
@@ -151,8 +160,11 @@ int32_t rmq_default_block(int64_t n, int64_t q, int32_t path);
  * with block size k, kept in device memory for any number of later query
  * batches.  A must stay alive and unmodified while the index is used, since
  * partial-block scans read it.  opt->block_size 0 picks k ~ sqrt(n)
- * (Section 3.2 sets k = Theta(sqrt(n))); opt->path is ignored.  *idx is set
- * only on success.  The build is enqueued on `stream`. */
+ * (Section 3.2 sets k = Theta(sqrt(n))); opt->path is ignored.  With
+ * opt->sub_block_size > 0 the index has two block levels (Section 3.3): the
+ * k1-block minima are kept beside the table and partial blocks are read
+ * through them.  *idx is set only on success.  The build is enqueued on
+ * `stream`. */
 rmq_status rmq_build(const int32_t *A, int64_t n, const rmq_options *opt, void *stream,
                      rmq_index *idx);
 
@@ -167,7 +179,8 @@ rmq_status rmq_query_index_ex(rmq_index idx, const int32_t *L, const int32_t *R,
 /* Free an index.  The caller must make sure no enqueued work still uses it. */
 rmq_status rmq_index_free(rmq_index idx);
 
-/* Facts about an index (any output pointer may be NULL). */
+/* Facts about an index (any output pointer may be NULL).  bytes counts the
+ * table and, for a two-level index, the k1-block minima (8 * ceil(n / k1)). */
 rmq_status rmq_index_info(rmq_index idx, int64_t *n, int32_t *block_size, int64_t *num_blocks,
                           int32_t *levels, size_t *bytes);
 

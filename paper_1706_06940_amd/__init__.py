@@ -48,6 +48,7 @@ class _Options(ctypes.Structure):
         ("workspace", ctypes.c_void_p),
         ("workspace_bytes", ctypes.c_size_t),
         ("timer", ctypes.c_void_p),
+        ("sub_block_size", ctypes.c_int32),
     ]
 
 
@@ -155,9 +156,10 @@ class Timer:
 
 
 def _options(block_size=0, path="auto", bad_count=None, stats=None, workspace=None,
-             timer: Optional[Timer] = None) -> _Options:
+             timer: Optional[Timer] = None, sub_block_size: int = 0) -> _Options:
     o = _Options()
     o.block_size = int(block_size)
+    o.sub_block_size = int(sub_block_size)
     o.path = PATHS[path] if isinstance(path, str) else int(path)
     o.bad_count = _dev_u64(bad_count, "bad_count") if bad_count is not None else None
     o.stats = _dev_u64(stats, "stats") if stats is not None else None
@@ -222,8 +224,9 @@ def default_block(n: int, q: int, path: str) -> int:
     return int(lib().rmq_default_block(n, q, PATHS[path]))
 
 
-def workspace_bytes(n: int, q: int, path="auto", block_size: int = 0) -> int:
-    o = _options(block_size, path)
+def workspace_bytes(n: int, q: int, path="auto", block_size: int = 0,
+                    sub_block_size: int = 0) -> int:
+    o = _options(block_size, path, sub_block_size=sub_block_size)
     return int(lib().rmq_workspace_bytes(n, q, ctypes.byref(o)))
 
 
@@ -236,16 +239,18 @@ def table_levels(num_blocks: int) -> int:
 
 
 def query_batch(A: torch.Tensor, L: torch.Tensor, R: torch.Tensor, *, path="auto",
-                block_size: int = 0, out: Optional[torch.Tensor] = None, bad_count=None,
-                stats=None, workspace=None, timer: Optional[Timer] = None,
-                stream=None) -> torch.Tensor:
-    """Answer all queries of one offline batch (Section 1); returns int32 out."""
+                block_size: int = 0, sub_block_size: int = 0,
+                out: Optional[torch.Tensor] = None, bad_count=None, stats=None, workspace=None,
+                timer: Optional[Timer] = None, stream=None) -> torch.Tensor:
+    """Answer all queries of one offline batch (Section 1); returns int32 out.
+    sub_block_size > 0 selects two block levels (Section 3.3) on the plain
+    method."""
     n, q = A.numel(), L.numel()
     if R.numel() != q:
         raise ValueError("L and R differ in length")
     if out is None:
         out = torch.empty(q, dtype=torch.int32, device=A.device)
-    o = _options(block_size, path, bad_count, stats, workspace, timer)
+    o = _options(block_size, path, bad_count, stats, workspace, timer, sub_block_size)
     st = lib().rmq_query_batch_ex(_dev_i32(A, "A"), n, _dev_i32(L, "L") if q else None,
                                   _dev_i32(R, "R") if q else None, q,
                                   _dev_i32(out, "out") if q else None,
@@ -255,12 +260,14 @@ def query_batch(A: torch.Tensor, L: torch.Tensor, R: torch.Tensor, *, path="auto
 
 
 class Index:
-    """Resident block Sparse Table of A (Section 3.2) for repeated batches.
+    """Resident block Sparse Table of A (Section 3.2) for repeated batches,
+    with the k1-block minima too when sub_block_size > 0 (Section 3.3).
     Keeps a reference to A, which partial-block scans read."""
 
-    def __init__(self, A: torch.Tensor, block_size: int = 0, stream=None):
+    def __init__(self, A: torch.Tensor, block_size: int = 0, stream=None,
+                 sub_block_size: int = 0):
         h = ctypes.c_void_p()
-        o = _options(block_size, "full")
+        o = _options(block_size, "full", sub_block_size=sub_block_size)
         _check("rmq_build", lib().rmq_build(_dev_i32(A, "A"), A.numel(), ctypes.byref(o),
                                             _stream(A.device, stream), ctypes.byref(h)))
         self.handle = h

@@ -72,14 +72,38 @@ struct Plan {
   int path;
   int32_t k;
   int kshift;
+  int k1shift;  // two block levels (Section 3.3): k1 = 2^k1shift; -1 = one level
 };
+
+// Section 3.3's choice for two levels: k2 = sqrt(n) log^(2/3) n, as a power
+// of two, at least 2 * k1.
+int32_t default_block_two_level(int64_t n, int32_t k1) {
+  const double ln = log2((double)(n > 2 ? n : 2));
+  const double t = sqrt((double)n) * pow(ln, 2.0 / 3.0);
+  int64_t k = 2 * (int64_t)k1;
+  while (k < RMQ_MAX_BLOCK && (double)(k * 2) <= t * 1.41421356) k *= 2;
+  return (int32_t)k;
+}
 
 rmq_status make_plan(int64_t n, int64_t q, const rmq_options* opt, Plan* p) {
   int32_t path = opt ? opt->path : RMQ_PATH_AUTO;
   int32_t k = opt ? opt->block_size : 0;
+  const int32_t k1 = opt ? opt->sub_block_size : 0;
   if (path != RMQ_PATH_AUTO && path != RMQ_PATH_FULL && path != RMQ_PATH_CONTRACTED)
     return RMQ_ERR_INVALID_ARG;
   if (k != 0 && !is_pow2_block(k)) return RMQ_ERR_INVALID_ARG;
+  p->k1shift = -1;
+  if (k1 != 0) {
+    // two block levels: the plain method with k1 < k
+    if (!is_pow2_block(k1) || path == RMQ_PATH_CONTRACTED) return RMQ_ERR_INVALID_ARG;
+    if (k == 0) k = default_block_two_level(n, k1);
+    if (k1 >= k) return RMQ_ERR_INVALID_ARG;
+    p->path = RMQ_PATH_FULL;
+    p->k = k;
+    p->kshift = ilog2_i64(k);
+    p->k1shift = ilog2_i64(k1);
+    return RMQ_OK;
+  }
   if (path == RMQ_PATH_AUTO) {
     int32_t pk = 0, pp = 0;
     rmq_plan(n, q, &pk, &pp);
@@ -95,17 +119,20 @@ rmq_status make_plan(int64_t n, int64_t q, const rmq_options* opt, Plan* p) {
 
 // ---- workspace layouts ----
 struct FullLayout {
-  int64_t nb;
+  int64_t nb, nb1;
   int levels;
-  size_t off_st, bytes;
+  size_t off_st, off_sub, bytes;
 };
 
-FullLayout full_layout(int64_t n, int64_t k) {
+// The table, then (two block levels) the k1-block minima.
+FullLayout full_layout(int64_t n, int64_t k, int k1shift) {
   FullLayout f{};
   f.nb = num_blocks(n, k);
   f.levels = rmq_table_levels(f.nb);
   f.off_st = 0;
-  f.bytes = align_up(sizeof(uint64_t) * (size_t)f.nb * (size_t)f.levels);
+  f.off_sub = align_up(sizeof(uint64_t) * (size_t)f.nb * (size_t)f.levels);
+  f.nb1 = k1shift >= 0 ? num_blocks(n, 1ll << k1shift) : 0;
+  f.bytes = f.off_sub + align_up(sizeof(uint64_t) * (size_t)f.nb1);
   return f;
 }
 
@@ -139,7 +166,7 @@ ConLayout con_layout(int64_t n, int64_t q, int64_t k) {
 }
 
 size_t plan_bytes(int64_t n, int64_t q, const Plan& p) {
-  if (p.path == RMQ_PATH_FULL) return full_layout(n, p.k).bytes;
+  if (p.path == RMQ_PATH_FULL) return full_layout(n, p.k, p.k1shift).bytes;
   return con_layout(n, q, p.k).bytes;
 }
 
@@ -195,10 +222,19 @@ rmq_status run_full(const int32_t* A, int64_t n, const int32_t* L, const int32_t
   rmq_timer* t = opt ? opt->timer : nullptr;
   ClockGuard guard;
   if (t) t->ran[0] = false;  // no sort stage on this path
-  const FullLayout f = full_layout(n, p.k);
+  const FullLayout f = full_layout(n, p.k, p.k1shift);
   uint64_t* st = reinterpret_cast<uint64_t*>(ws + f.off_st);
+  uint64_t* sub = reinterpret_cast<uint64_t*>(ws + f.off_sub);
+  const bool two = p.k1shift >= 0;
   stage_begin(t, 1);
-  hipError_t e = launch_blockmin_i32(A, n, p.kshift, st, s);
+  hipError_t e;
+  if (two) {
+    // Section 3.3: minima of the k1-blocks, then of the k-blocks from them
+    e = launch_blockmin_i32(A, n, p.k1shift, sub, s);
+    if (e == hipSuccess) e = launch_blockmin_keys(sub, f.nb1, p.kshift - p.k1shift, st, s);
+  } else {
+    e = launch_blockmin_i32(A, n, p.kshift, st, s);
+  }
   if (e != hipSuccess) return from_hip(e);
   stage_end(t, 1, s);
   stage_begin(t, 2);
@@ -206,8 +242,11 @@ rmq_status run_full(const int32_t* A, int64_t n, const int32_t* L, const int32_t
   if (e != hipSuccess) return from_hip(e);
   stage_end(t, 2, s);
   stage_begin(t, 3);
-  e = launch_query_full(A, n, p.kshift, st, f.nb, L, R, q, out, opt ? opt->bad_count : nullptr,
-                        opt ? opt->stats : nullptr, s);
+  int64_t* bad = opt ? opt->bad_count : nullptr;
+  uint64_t* stats = opt ? opt->stats : nullptr;
+  e = two ? launch_query_full2(A, n, p.kshift, st, f.nb, sub, p.k1shift, L, R, q, out, bad, stats,
+                               s)
+          : launch_query_full(A, n, p.kshift, st, f.nb, L, R, q, out, bad, stats, s);
   if (e != hipSuccess) return from_hip(e);
   stage_end(t, 3, s);
   return RMQ_OK;
@@ -379,14 +418,18 @@ rmq_status rmq_build(const int32_t* A, int64_t n, const rmq_options* opt, void* 
   if (!A || !idx || n < 1 || n > RMQ_MAX_N) return RMQ_ERR_INVALID_ARG;
   if (!aligned_to(A, 4)) return RMQ_ERR_MISALIGNED;
   int32_t k = opt ? opt->block_size : 0;
-  if (k == 0) {
+  const int32_t k1 = opt ? opt->sub_block_size : 0;
+  if (k1 != 0 && !is_pow2_block(k1)) return RMQ_ERR_INVALID_ARG;
+  if (k == 0 && k1 != 0) {
+    k = default_block_two_level(n, k1);
+  } else if (k == 0) {
     // Section 3.2: k = Theta(sqrt(n)) keeps both the query time and the
     // space of the index low; a power of two near sqrt(n) / 4.
     const double tgt = sqrt((double)n) / 4.0;
     k = 256;
     while (k < (1 << 20) && (double)(k * 2) <= tgt) k *= 2;
   }
-  if (!is_pow2_block(k)) return RMQ_ERR_INVALID_ARG;
+  if (!is_pow2_block(k) || (k1 != 0 && k1 >= k)) return RMQ_ERR_INVALID_ARG;
   rmq_index_s* ix = static_cast<rmq_index_s*>(calloc(1, sizeof(rmq_index_s)));
   if (!ix) return RMQ_ERR_OUT_OF_MEMORY;
   hipGetDevice(&ix->device);
@@ -395,7 +438,10 @@ rmq_status rmq_build(const int32_t* A, int64_t n, const rmq_options* opt, void* 
   ix->kshift = ilog2_i64(k);
   ix->nb = num_blocks(n, k);
   ix->levels = rmq_table_levels(ix->nb);
-  ix->bytes = sizeof(uint64_t) * (size_t)ix->nb * (size_t)ix->levels;
+  ix->k1shift = k1 != 0 ? ilog2_i64(k1) : -1;
+  ix->nb1 = k1 != 0 ? num_blocks(n, k1) : 0;
+  const size_t table_bytes = sizeof(uint64_t) * (size_t)ix->nb * (size_t)ix->levels;
+  ix->bytes = table_bytes + sizeof(uint64_t) * (size_t)ix->nb1;
   void* mem = nullptr;
   hipError_t e = hipMalloc(&mem, ix->bytes);
   if (e != hipSuccess) {
@@ -403,8 +449,16 @@ rmq_status rmq_build(const int32_t* A, int64_t n, const rmq_options* opt, void* 
     return from_hip(e);
   }
   ix->st = static_cast<uint64_t*>(mem);
+  ix->sub = k1 != 0 ? ix->st + (size_t)ix->nb * (size_t)ix->levels : nullptr;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  e = launch_blockmin_i32(A, n, ix->kshift, ix->st, s);
+  if (ix->sub) {
+    // Section 3.3: k1-block minima, then the k-block minima from them
+    e = launch_blockmin_i32(A, n, ix->k1shift, ix->sub, s);
+    if (e == hipSuccess) e = launch_blockmin_keys(ix->sub, ix->nb1, ix->kshift - ix->k1shift,
+                                                  ix->st, s);
+  } else {
+    e = launch_blockmin_i32(A, n, ix->kshift, ix->st, s);
+  }
   if (e == hipSuccess) e = launch_sparse_table(ix->st, ix->nb, ix->levels, s);
   if (e != hipSuccess) {
     hipFree(mem);
@@ -422,9 +476,14 @@ rmq_status rmq_query_index_ex(rmq_index idx, const int32_t* L, const int32_t* R,
   if (q && (!aligned_to(L, 4) || !aligned_to(R, 4) || !aligned_to(out, 4)))
     return RMQ_ERR_MISALIGNED;
   if (q == 0) return RMQ_OK;
-  hipError_t e = launch_query_full(idx->A, idx->n, idx->kshift, idx->st, idx->nb, L, R, q, out,
-                                   opt ? opt->bad_count : nullptr, opt ? opt->stats : nullptr,
-                                   static_cast<hipStream_t>(stream));
+  int64_t* bad = opt ? opt->bad_count : nullptr;
+  uint64_t* stats = opt ? opt->stats : nullptr;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e =
+      idx->sub ? launch_query_full2(idx->A, idx->n, idx->kshift, idx->st, idx->nb, idx->sub,
+                                    idx->k1shift, L, R, q, out, bad, stats, s)
+               : launch_query_full(idx->A, idx->n, idx->kshift, idx->st, idx->nb, L, R, q, out,
+                                   bad, stats, s);
   return from_hip(e);
 }
 
@@ -453,7 +512,8 @@ rmq_status rmq_index_info(rmq_index idx, int64_t* n, int32_t* block_size, int64_
 
 rmq_status rmq_index_copy_table(rmq_index idx, uint64_t* st, void* stream) {
   if (!idx || !st) return RMQ_ERR_INVALID_ARG;
-  return from_hip(hipMemcpyAsync(st, idx->st, idx->bytes, hipMemcpyDeviceToDevice,
+  const size_t table_bytes = sizeof(uint64_t) * (size_t)idx->nb * (size_t)idx->levels;
+  return from_hip(hipMemcpyAsync(st, idx->st, table_bytes, hipMemcpyDeviceToDevice,
                                  static_cast<hipStream_t>(stream)));
 }
 
@@ -687,7 +747,7 @@ rmq_status rmq_batch_create(const rmq_batch_item* items, int32_t count, rmq_batc
   for (int c = 0; c < cnt; ++c) {
     const int i = b->full_items[c];
     const rmq_batch_item& it = items[i];
-    const FullLayout f = full_layout(it.n, b->plans[i].k);
+    const FullLayout f = full_layout(it.n, b->plans[i].k, -1);
     desc[c] = ArrayDesc{it.A, it.n, b->plans[i].kshift, f.levels, f.nb, nullptr,
                         it.L, it.R, it.q, it.out};
     wg[c + 1] = wg[c] + blockmin_grid(it.n, b->plans[i].kshift, 4);

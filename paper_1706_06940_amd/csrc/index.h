@@ -12,5 +12,8 @@ struct rmq_index_s {
   int64_t nb;        // number of blocks
   int levels;        // Sparse Table levels
   uint64_t* st;      // level-major levels x nb keys (device)
-  size_t bytes;
+  uint64_t* sub;     // two block levels (Section 3.3): k1-block minima, else null
+  int k1shift;       // k1 = 2^k1shift when sub is set
+  int64_t nb1;       // number of k1-blocks
+  size_t bytes;      // table + k1-block minima
 };

@@ -103,6 +103,11 @@ hipError_t launch_query_full(const int32_t* A, int64_t n, int kshift, const uint
                              int64_t nb, const int32_t* L, const int32_t* R, int64_t q,
                              int32_t* out, int64_t* bad_count, uint64_t* stats,
                              hipStream_t stream);
+// Two block levels (Section 3.3): sub holds the minima of the 2^k1shift-blocks.
+hipError_t launch_query_full2(const int32_t* A, int64_t n, int kshift, const uint64_t* st,
+                              int64_t nb, const uint64_t* sub, int k1shift, const int32_t* L,
+                              const int32_t* R, int64_t q, int32_t* out, int64_t* bad_count,
+                              uint64_t* stats, hipStream_t stream);
 
 // ---- contracted path (Section 3.1) ----
 // Device LSD radix sort of the 2q endpoints by (position, tag).  The sorted

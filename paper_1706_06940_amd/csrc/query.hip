@@ -28,6 +28,13 @@ namespace rmq {
 namespace {
 
 constexpr int WG = 256;
+// On sources that allow it (two block levels), when at least LANE_SCAN_MIN
+// lanes of a wave need a partial scan, those whose range reads at most
+// LANE_SCAN_MAX entries read it alone, all at once; the others are queued and
+// read by the whole wave one range at a time (a step covers 512 elements, so
+// a lone scan finishes fast).
+constexpr int LANE_SCAN_MIN = 16;
+constexpr int64_t LANE_SCAN_MAX = 1024;
 
 // --- sources -----------------------------------------------------------------
 // The plain array: index == position in A, key built from the int32 value.
@@ -47,13 +54,44 @@ struct SrcA {
     }
     return x;
   }
+  // Whole ranges are not scanned lane by lane on this source: one lane's
+  // loads touch 64 different lines per instruction, so queued wave-wide
+  // scans (8 lines per load) are faster even when every lane has a range.
+  static constexpr bool kLaneScans = false;
+  // min key over A[lo..hi] by this lane alone (a short piece); 16 elements
+  // per step, their loads in flight together.
+  __device__ uint64_t lane_scan(int64_t lo, int64_t hi, uint64_t bound, int64_t& reads) const {
+    reads += hi - lo + 1;
+    uint64_t best = KEY_NONE;
+    if (((uintptr_t)A & 15) == 0) {
+      for (int64_t p = lo & ~3ll; p <= hi; p += 16) {
+        v4i32 x[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) x[u] = load4(p + 4 * u, hi);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const int64_t e = p + 4 * u + c;
+            if (e >= lo && e <= hi) best = umin64(best, make_key(x[u][c], (uint32_t)e));
+          }
+      }
+    } else {
+      for (int64_t e = lo; e <= hi; ++e) best = umin64(best, make_key(A[e], (uint32_t)e));
+    }
+    return best;
+  }
   // This lane's source as seen by the whole wave (for a wave-wide scan).
   __device__ __forceinline__ SrcA broadcast(int src_lane) const {
     return {reinterpret_cast<const int32_t*>(readlane64((int64_t)(uintptr_t)A, src_lane)),
             readlane64(len, src_lane)};
   }
   // min key over A[lo..hi], whole wave cooperating (everything wave-uniform).
-  __device__ uint64_t scan(int64_t lo, int64_t hi, int lane) const {
+  // `bound` (the query's best key so far) is not needed here; `reads` counts
+  // the entries read.
+  __device__ uint64_t scan(int64_t lo, int64_t hi, int lane, uint64_t bound,
+                           int64_t& reads) const {
+    reads += hi - lo + 1;
     uint64_t best = KEY_NONE;
     if (((uintptr_t)A & 15) == 0) {
       const int64_t a0 = lo & ~3ll;
@@ -89,11 +127,14 @@ struct SrcKeys {
     return x;
   }
   __device__ __forceinline__ uint32_t pos_of(uint64_t key) const { return key_pos(key); }
+  static constexpr bool kLaneScans = false;  // as for the plain array
   __device__ __forceinline__ SrcKeys broadcast(int src_lane) const {
     return {reinterpret_cast<const uint64_t*>(readlane64((int64_t)(uintptr_t)S, src_lane)),
             readlane64(len, src_lane)};
   }
-  __device__ uint64_t scan(int64_t lo, int64_t hi, int lane) const {
+  __device__ uint64_t scan(int64_t lo, int64_t hi, int lane, uint64_t bound,
+                           int64_t& reads) const {
+    reads += hi - lo + 1;
     uint64_t best = KEY_NONE;
     if (((uintptr_t)S & 15) == 0) {
       const int64_t a0 = lo & ~1ll;
@@ -111,6 +152,82 @@ struct SrcKeys {
       for (int64_t p = lo + lane; p <= hi; p += 64) best = umin64(best, S[p]);
     }
     return wave_min_u64(best);
+  }
+};
+
+// The plain array with two block levels (Section 3.3): the minima of its
+// k1-blocks are kept, so a partial k-block [lo, hi] is read as the k1-block
+// minima of the k1-blocks it covers plus at most two partial k1-blocks, and
+// those again only when their k1-block minimum can still beat the query's
+// best key (the same speculation as at the upper level).
+struct SrcA2 {
+  SrcA a;
+  const uint64_t* __restrict__ sub;  // k1-block minima
+  int64_t nsub;
+  int s1;  // k1 = 2^s1
+  __device__ __forceinline__ uint32_t pos_of(uint64_t key) const { return key_pos(key); }
+  __device__ __forceinline__ SrcA2 broadcast(int src_lane) const {
+    return {a.broadcast(src_lane),
+            reinterpret_cast<const uint64_t*>(readlane64((int64_t)(uintptr_t)sub, src_lane)),
+            readlane64(nsub, src_lane), __builtin_amdgcn_readlane(s1, src_lane)};
+  }
+  // min over the elements of A[lo..hi], which lie in one k1-block: its
+  // minimum if that lies inside, nothing if it cannot beat `bound`, else a
+  // scan of the elements
+  __device__ uint64_t part(int64_t lo, int64_t hi, int lane, uint64_t bound,
+                           int64_t& reads) const {
+    const uint64_t kb = sub[lo >> s1];
+    reads += 1;
+    const int64_t p = (int64_t)key_pos(kb);
+    if (lo <= p && p <= hi) return kb;
+    if (!(kb < bound)) return KEY_NONE;
+    return a.scan(lo, hi, lane, bound, reads);
+  }
+  // Dense short ranges are read lane by lane here: the lane reads k1-block
+  // minima and at most two pieces of at most k1 elements (only while k1 <=
+  // 256: longer pieces read by one lane cost more than wave-wide scans).
+  static constexpr bool kLaneScans = true;
+  __device__ __forceinline__ int64_t lane_cost(int64_t lo, int64_t hi) const {
+    if (s1 > 8) return INT64_MAX;
+    const int64_t elems = hi - lo + 1, two = 2ll << s1;
+    return (hi >> s1) - (lo >> s1) + 1 + (elems < two ? elems : two);
+  }
+  // the same decomposition by this lane alone (short ranges): k1-blocks
+  // b_lo+1 .. b_hi-1 whole, then the pieces of b_lo and b_hi in the range
+  // (a whole k1-block's minimum always lies inside, so it needs no scan)
+  __device__ uint64_t lane_scan(int64_t lo, int64_t hi, uint64_t bound, int64_t& reads) const {
+    const int64_t b_lo = lo >> s1, b_hi = hi >> s1;
+    const int64_t k1 = 1ll << s1;
+    const uint64_t kh = sub[b_lo], kt = sub[b_hi];  // both loads in flight
+    uint64_t best = KEY_NONE;
+    for (int64_t b = b_lo + 1; b < b_hi; ++b) best = umin64(best, sub[b]);
+    reads += b_hi - b_lo + 1;
+    auto piece = [&](uint64_t kb, int64_t p_lo, int64_t p_hi) {
+      const int64_t p = (int64_t)key_pos(kb);
+      if (p_lo <= p && p <= p_hi) best = umin64(best, kb);
+      else if (kb < umin64(best, bound))
+        best = umin64(best, a.lane_scan(p_lo, p_hi, bound, reads));
+    };
+    piece(kh, lo, b_lo == b_hi ? hi : (b_lo + 1) * k1 - 1);
+    if (b_hi != b_lo) piece(kt, b_hi * k1, hi);
+    return best;
+  }
+  __device__ uint64_t scan(int64_t lo, int64_t hi, int lane, uint64_t bound,
+                           int64_t& reads) const {
+    const int64_t b_lo = lo >> s1, b_hi = hi >> s1;
+    if (b_lo == b_hi) return part(lo, hi, lane, bound, reads);
+    const int64_t k1 = 1ll << s1;
+    // whole k1-blocks inside [lo, hi]
+    const int64_t f = (lo & (k1 - 1)) == 0 ? b_lo : b_lo + 1;
+    const int64_t g = ((hi + 1) & (k1 - 1)) == 0 ? b_hi : b_hi - 1;
+    uint64_t best = KEY_NONE;
+    for (int64_t b = f + lane; b <= g; b += 64) best = umin64(best, sub[b]);
+    best = wave_min_u64(best);
+    reads += g >= f ? g - f + 1 : 0;
+    if (f != b_lo)
+      best = umin64(best, part(lo, (b_lo + 1) * k1 - 1, lane, umin64(best, bound), reads));
+    if (g != b_hi) best = umin64(best, part(b_hi * k1, hi, lane, umin64(best, bound), reads));
+    return best;
   }
 };
 
@@ -171,28 +288,50 @@ __device__ __forceinline__ void query_core(const Src& src, int64_t src_len, int6
     }
   }
 
-  // ---- wave-cooperative partial-block scans ----
-  uint64_t n_scans = 0, n_elems = 0;
+  // ---- partial-block scans: a short range is read by its own lane (many
+  // of them at once); a long one is queued and read by the whole wave ----
+  uint64_t n_scans = 0, n_elems = 0;  // wave-uniform counts of queued scans
+  int64_t lane_scans = 0, lane_reads = 0;
+  if constexpr (Src::kLaneScans) {
+    if (__popcll(ballot(needL)) >= LANE_SCAN_MIN && needL &&
+        src.lane_cost(loL, hiL) <= LANE_SCAN_MAX) {
+      best = umin64(best, src.lane_scan(loL, hiL, best, lane_reads));
+      lane_scans += 1;
+      needL = false;
+    }
+  }
   uint64_t pend = ballot(needL);
   while (pend) {
     const int src_lane = __builtin_ctzll(pend);
     pend &= pend - 1;
     const int64_t lo = readlane64(loL, src_lane), hi = readlane64(hiL, src_lane);
-    const uint64_t m = src.broadcast(src_lane).scan(lo, hi, lane);
+    const uint64_t bound = (uint64_t)readlane64((int64_t)best, src_lane);
+    int64_t reads = 0;
+    const uint64_t m = src.broadcast(src_lane).scan(lo, hi, lane, bound, reads);
     if (lane == src_lane) best = umin64(best, m);
     n_scans += 1;
-    n_elems += (uint64_t)(hi - lo + 1);
+    n_elems += (uint64_t)reads;
   }
   if (needR && !(kr < best)) needR = false;  // the left scan already beat this block
+  if constexpr (Src::kLaneScans) {
+    if (__popcll(ballot(needR)) >= LANE_SCAN_MIN && needR &&
+        src.lane_cost(loR, hiR) <= LANE_SCAN_MAX) {
+      best = umin64(best, src.lane_scan(loR, hiR, best, lane_reads));
+      lane_scans += 1;
+      needR = false;
+    }
+  }
   pend = ballot(needR);
   while (pend) {
     const int src_lane = __builtin_ctzll(pend);
     pend &= pend - 1;
     const int64_t lo = readlane64(loR, src_lane), hi = readlane64(hiR, src_lane);
-    const uint64_t m = src.broadcast(src_lane).scan(lo, hi, lane);
+    const uint64_t bound = (uint64_t)readlane64((int64_t)best, src_lane);
+    int64_t reads = 0;
+    const uint64_t m = src.broadcast(src_lane).scan(lo, hi, lane, bound, reads);
     if (lane == src_lane) best = umin64(best, m);
     n_scans += 1;
-    n_elems += (uint64_t)(hi - lo + 1);
+    n_elems += (uint64_t)reads;
   }
 
   if (live) *outp = ok ? (int32_t)src.pos_of(best) : -1;
@@ -201,9 +340,17 @@ __device__ __forceinline__ void query_core(const Src& src, int64_t src_len, int6
     const uint64_t bad = ballot(live && !ok);
     if (bad && lane == 0) atomicAdd(bad_count, (unsigned long long)__popcll(bad));
   }
-  if (stats && n_scans && lane == 0) {
-    atomicAdd(stats, (unsigned long long)n_scans);
-    atomicAdd(stats + 1, (unsigned long long)n_elems);
+  if (stats) {
+    for (int d = 1; d < 64; d <<= 1) {
+      lane_scans += __shfl_xor(lane_scans, d);
+      lane_reads += __shfl_xor(lane_reads, d);
+    }
+    n_scans += (uint64_t)lane_scans;
+    n_elems += (uint64_t)lane_reads;
+    if (n_scans && lane == 0) {
+      atomicAdd(stats, (unsigned long long)n_scans);
+      atomicAdd(stats + 1, (unsigned long long)n_elems);
+    }
   }
 }
 
@@ -304,6 +451,20 @@ hipError_t launch_query_full(const int32_t* A, int64_t n, int kshift, const uint
   RMQ_TRY(launch(k_query<SrcA>, dim3((unsigned)grid), dim3(WG), 0, stream, SrcA{A, n}, n, n,
                  kshift, st, nb, L, R, static_cast<const int32_t*>(nullptr), q, out,
                  (unsigned long long*)bad_count, (unsigned long long*)stats));
+  return hipGetLastError();
+}
+
+hipError_t launch_query_full2(const int32_t* A, int64_t n, int kshift, const uint64_t* st,
+                              int64_t nb, const uint64_t* sub, int k1shift, const int32_t* L,
+                              const int32_t* R, int64_t q, int32_t* out, int64_t* bad_count,
+                              uint64_t* stats, hipStream_t stream) {
+  if (q <= 0) return hipSuccess;
+  const int64_t grid = (q + WG - 1) / WG;
+  const int64_t nsub = (n + (1ll << k1shift) - 1) >> k1shift;
+  RMQ_TRY(launch(k_query<SrcA2>, dim3((unsigned)grid), dim3(WG), 0, stream,
+                 SrcA2{SrcA{A, n}, sub, nsub, k1shift}, n, n, kshift, st, nb, L, R,
+                 static_cast<const int32_t*>(nullptr), q, out, (unsigned long long*)bad_count,
+                 (unsigned long long*)stats));
   return hipGetLastError();
 }
 

@@ -1,7 +1,8 @@
 """Parity at the largest configurations, checked on every output:
 
 * n = 1e9 int32 uniform values (4 GB), q = 1e7 queries, half short (length
-  uniform in [1, 1024]) and half uniform long, both methods;
+  uniform in [1, 1024]) and half uniform long, both methods and the plain
+  method with two block levels (Section 3.3);
 * Euler-tour depth array of a random recursive tree with 5e8 nodes
   (999,999,999 steps, +-1), 1e7 LCA queries: the answer's tour node is the
   LCA found by climbing parent pointers, and equals the oracle's answer;
@@ -47,11 +48,13 @@ def test_c3_billion_skewed(orc):
     assert np.array_equal(A[torch.from_numpy(idx).to(d)].cpu().numpy(), A_h[idx])
     L, R = W.skewed_queries(n, q, seed)
     Lt, Rt = dev(L, d), dev(R, d)
-    for path in ("full", "contracted"):
-        log("running", path)
-        got = rmq.query_batch(A, Lt, Rt, path=path).cpu().numpy()
+    exp = orc.rmq_sparse_table(A_h, L, R, 32)
+    for path, k1 in (("full", 0), ("contracted", 0), ("full", 1024)):
+        log("running", path, "two levels" if k1 else "")
+        got = rmq.query_batch(A, Lt, Rt, path=path, sub_block_size=k1).cpu().numpy()
         log("checking", path)
-        compare_all(orc, A_h, L, R, got, path)
+        bad = np.nonzero(got != exp)[0]
+        assert bad.size == 0, (path, k1, bad.size, L[bad[:3]], R[bad[:3]], got[bad[:3]], exp[bad[:3]])
     log("done")
 
 

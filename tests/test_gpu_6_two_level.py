@@ -1,0 +1,99 @@
+"""Two block levels (Section 3.3): k1-block minima under the block Sparse
+Table of k-blocks, partial k-blocks read through the k1 minima.  Every
+answer bit-exact against the oracle; same answers as one level."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1706_06940_amd as rmq
+import workloads as W
+from tests._gpu import arrays, dev, host, need_gpu, query_sets, reference, say
+
+pytestmark = pytest.mark.gpu
+
+
+def run(A_t, L, R, k, k1, d, **kw):
+    return host(rmq.query_batch(A_t, dev(L, d), dev(R, d), path="full", block_size=k,
+                                sub_block_size=k1, **kw))
+
+
+@pytest.mark.parametrize("n,k,k1", [(1, 32, 16), (17, 32, 16), (255, 64, 16), (1025, 256, 32),
+                                    (4099, 1024, 16), (100_003, 4096, 256),
+                                    (100_003, 65_536, 16), (1_000_003, 16_384, 512),
+                                    (65_536, 65_536, 32_768), (70_000, 131_072, 1024)])
+def test_families(orc, n, k, k1):
+    d = need_gpu()
+    q = 3000 if n > 64 else 200
+    for aname, A in arrays(n, n + k + k1):
+        At = dev(A, d)
+        for qname, L, R in query_sets(n, k1, q, n * 7 + k + k1):
+            say("two_level", n, k, k1, aname, qname)
+            exp = reference(orc, A, L, R)
+            got = run(At, L, R, k, k1, d)
+            bad = np.nonzero(got != exp)[0]
+            assert bad.size == 0, (aname, qname, L[bad[:4]], R[bad[:4]], got[bad[:4]], exp[bad[:4]])
+
+
+def test_all_ranges_tiny(orc):
+    d = need_gpu()
+    for n in (1, 2, 5, 16, 17, 40, 64, 100):
+        for aname, A in arrays(n, n):
+            L, R = np.triu_indices(n)
+            L, R = L.astype(np.int32), R.astype(np.int32)
+            say("two_level_all_ranges", n, aname)
+            exp = orc.rmq_scan(A, L, R)
+            for k, k1 in ((32, 16), (64, 16), (64, 32)):
+                assert np.array_equal(run(dev(A, d), L, R, k, k1, d), exp), (n, aname, k, k1)
+
+
+def test_short_and_long_mix_agrees_with_one_level(orc):
+    """The skewed mix (half short ranges of length <= 1024, half uniform),
+    where partial blocks are scanned most: two levels, one level and the
+    oracle agree, and two levels read fewer elements."""
+    d = need_gpu()
+    n, q = 3_000_017, 200_000
+    A = W.uniform_int31(n, 91)
+    L, R = W.skewed_queries(n, q, 92)
+    exp = reference(orc, A, L, R)
+    At, Lt, Rt = dev(A, d), dev(L, d), dev(R, d)
+    s1 = torch.zeros(2, dtype=torch.int64, device=d)
+    s2 = torch.zeros(2, dtype=torch.int64, device=d)
+    say("two_level_skewed")
+    one = host(rmq.query_batch(At, Lt, Rt, path="full", block_size=16384, stats=s1))
+    two = host(rmq.query_batch(At, Lt, Rt, path="full", block_size=16384, sub_block_size=256,
+                               stats=s2))
+    assert np.array_equal(one, exp) and np.array_equal(two, exp)
+    e1, e2 = host(s1), host(s2)
+    assert e2[1] < e1[1] / 4, (e1, e2)  # elements scanned by partial-block scans
+
+
+def test_default_block_and_resident_index(orc):
+    d = need_gpu()
+    say("two_level_index")
+    n = 2_000_003
+    A = W.uniform_int31(n, 93)
+    At = dev(A, d)
+    idx = rmq.Index(At, 0, sub_block_size=256)
+    assert idx.block_size > 256 and idx.bytes == 8 * (idx.num_blocks * idx.levels + -(-n // 256))
+    for seed in (94, 95):
+        L, R = W.skewed_queries(n, 50_000, seed)
+        exp = reference(orc, A, L, R)
+        assert np.array_equal(host(idx.query(dev(L, d), dev(R, d))), exp)
+    # the table copy holds the k-level table only, equal to a one-level build
+    one = rmq.Index(At, idx.block_size)
+    assert torch.equal(idx.table(), one.table())
+    got = run(At, *W.skewed_queries(n, 50_000, 96), 0, 256, d)
+    assert np.array_equal(got, reference(orc, A, *W.skewed_queries(n, 50_000, 96)))
+
+
+def test_invalid_options():
+    d = need_gpu()
+    say("two_level_invalid")
+    A = torch.zeros(1000, dtype=torch.int32, device=d)
+    L = torch.zeros(4, dtype=torch.int32, device=d)
+    for k, k1, path in ((256, 256, "full"), (256, 512, "full"), (256, 24, "full"),
+                        (256, 8, "full"), (256, 16, "contracted")):
+        with pytest.raises(rmq.RMQError):
+            rmq.query_batch(A, L, L, path=path, block_size=k, sub_block_size=k1)
+    with pytest.raises(rmq.RMQError):
+        rmq.Index(A, 256, sub_block_size=512)
