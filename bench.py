@@ -65,6 +65,8 @@ def main() -> int:
     ap.add_argument("--no-flushed", action="store_true",
                     help="skip the cache-flushed block-minima measurement")
     ap.add_argument("--flushed-reps", type=int, default=7)
+    ap.add_argument("--no-lca", action="store_true",
+                    help="skip the LCA front-end measurement (5e8-node tree)")
     ap.add_argument("--no-skewed", action="store_true",
                     help="skip the n = 1e9 skewed-query measurement")
     ap.add_argument("--no-resident", action="store_true",
@@ -284,6 +286,7 @@ def main() -> int:
     del A, batches, outs
     torch.cuda.empty_cache()
     skewed = None if args.no_skewed else bench_skewed(d)
+    lca = None if args.no_lca else bench_lca(d)
     batched = None if args.no_batched else bench_batched(d)
     served = None if args.no_served else bench_served(d, args.served_requests)
 
@@ -299,7 +302,7 @@ def main() -> int:
                    "block_size": {p: k_used[p] for p in paths},
                    "parallelism": "single GPU"},
         "roofline": roofline, "cpu_baseline": cpu, "breakdown": breakdown,
-        "resident": resident, "skewed": skewed,
+        "resident": resident, "skewed": skewed, "lca": lca,
         "batched": batched, "served": served,
     }
     print(json.dumps(line), flush=True)
@@ -387,6 +390,39 @@ def bench_skewed(d, reps=5):
     return {"workload": "n=1e9 int32 uniform in [0,2^31), q=1e7: 5e6 short ranges (length "
                         "uniform in [1,1024]) and 5e6 uniform long ranges, shuffled",
             "results": res}
+
+
+def bench_lca(d, N=5 * 10 ** 8, q=10 ** 7, reps=5):
+    """LCA through RMQ (Section 1) on a random recursive tree of N nodes
+    (parent(i) uniform in [0, i)): the device build of the Euler tour (2N - 1
+    steps) and its RMQ index, then batches of q uniform (u, v) pairs."""
+    import torch
+
+    import paper_1706_06940_amd as rmq
+    import workloads as W
+
+    seed = W.BASE_SEED + 2
+    parent = torch.from_numpy(W.random_recursive_tree(N, seed)).to(d)
+    rng = np.random.default_rng(seed)
+    u = torch.from_numpy(rng.integers(0, N, q).astype(np.int32)).to(d)
+    v = torch.from_numpy(rng.integers(0, N, q).astype(np.int32)).to(d)
+    out = torch.empty(q, dtype=torch.int32, device=d)
+    stream = torch.cuda.current_stream(d)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h = rmq.LCA(parent)
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - t0) * 1e3
+    ms = time_runs(lambda: h.query(u, v, out=out), stream, warmup=1, reps=reps)
+    res = {"workload": f"random recursive tree, N={N} nodes (Euler tour of {2 * N - 1} steps), "
+                       f"q={q} uniform node pairs",
+           "build_ms": round(build_ms, 2), "query_ms": round(ms, 4),
+           "queries_per_s": round(q / (ms / 1e3), 1), "device_bytes": h.bytes}
+    h.free()
+    del parent, u, v, out
+    torch.cuda.empty_cache()
+    print(f"[bench] lca build {build_ms:.1f} ms, query {ms:.3f} ms", file=sys.stderr, flush=True)
+    return res
 
 
 def bench_batched(d, count=256):

@@ -198,6 +198,44 @@ size_t rmq_index_bytes(int64_t n, int32_t block_size);
 int32_t rmq_table_levels(int64_t num_blocks);
 
 /* ----------------------------------------------------------------------------
+ * Lowest common ancestors through RMQ (Section 1: in the Euler tour of a
+ * rooted tree, the LCA of u and v is the node of minimum depth between the
+ * first occurrences of u and v).  Built entirely on the device: the children
+ * of each node ordered by id (stable radix sort of (parent, child)), the
+ * tour's arcs linked and ranked (list ranking by sampled sublists and
+ * pointer jumping over the samples), the depth array D, the tour's node
+ * array and each node's first position, and a resident RMQ index over D.
+ * ------------------------------------------------------------------------- */
+typedef struct rmq_lca_s *rmq_lca;
+
+/* parent: device int32[num_nodes]; parent[root] = -1 for exactly one root,
+ * every other entry in [0, num_nodes) and the parent links acyclic.
+ * 1 <= num_nodes <= 2^30.  The tour visits children in increasing id; it
+ * has 2 * num_nodes - 1 entries.  opt->block_size / sub_block_size choose
+ * the RMQ index over D as for rmq_build (NULL: defaults).  The call waits
+ * for the device (it checks the input and the tour) and returns
+ * RMQ_ERR_INVALID_ARG for a forest, a parent out of range or a cycle.
+ * Temporary device memory: about 60 bytes per node, freed before return. */
+rmq_status rmq_lca_build(const int32_t *parent, int64_t num_nodes, const rmq_options *opt,
+                         void *stream, rmq_lca *out);
+
+/* out[i] = LCA(u[i], v[i]) (int32); -1, and opt->bad_count += 1, for a node
+ * id outside [0, num_nodes).  u, v, out: device int32[q]; opt may be NULL. */
+rmq_status rmq_lca_query(rmq_lca h, const int32_t *u, const int32_t *v, int64_t q, int32_t *out,
+                         void *stream, const rmq_options *opt);
+
+/* Copies of the tour into caller device buffers (any may be NULL):
+ * depth int32[2N-1], node int32[2N-1], first int32[N]; on `stream`. */
+rmq_status rmq_lca_copy_tour(rmq_lca h, int32_t *depth, int32_t *node, int32_t *first,
+                             void *stream);
+
+/* num_nodes and the device bytes held (tour arrays and the RMQ index). */
+rmq_status rmq_lca_info(rmq_lca h, int64_t *num_nodes, size_t *bytes);
+
+/* Free the structure; no enqueued work may still use it. */
+rmq_status rmq_lca_free(rmq_lca h);
+
+/* ----------------------------------------------------------------------------
  * The steps of the two methods, one call each, for callers that want a
  * single stage (and for checking each stage on its own).  All enqueue on
  * `stream` and return at once.

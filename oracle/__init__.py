@@ -52,6 +52,8 @@ def load(path: str | None = None, fresh: bool = False):
     lib.oracle_remap.argtypes = [v, i64, v, v]
     lib.oracle_contract.argtypes = [v, v, i64, v]
     lib.oracle_contracted_answer.argtypes = [v, v, v, v, i64, v]
+    lib.oracle_euler_tour.argtypes = [v, i64, v, v, v]
+    lib.oracle_euler_tour.restype = ctypes.c_int
     if path is None:
         _LIB = lib
     return lib
@@ -136,6 +138,18 @@ class Oracle:
         aq = np.empty(max(m - 1, 0), dtype=np.int32)
         self.lib.oracle_contract(_p(A), _p(pos), m, _p(aq))
         return aq
+
+    def euler_tour(self, parent):
+        """Section 1 (LCA reduces to RMQ): (depth, node, first) of the Euler
+        tour, children in increasing id; None if parent[] is not one tree."""
+        parent = _i32(parent)
+        N = parent.shape[0]
+        depth = np.empty(2 * N - 1, dtype=np.int32)
+        node = np.empty(2 * N - 1, dtype=np.int32)
+        first = np.empty(N, dtype=np.int32)
+        if self.lib.oracle_euler_tour(_p(parent), N, _p(depth), _p(node), _p(first)) != 0:
+            return None
+        return depth, node, first
 
     def contracted_answer(self, A, aq, Lc, Rc):
         """Section 3.1 step 4 (without blocks): minimum over A_Q[Lc..Rc]."""

@@ -22,6 +22,9 @@
  *   oracle_remap               Section 3.1 step 1, queries remapped onto A_Q
  *   oracle_contract            Section 3.1 step 2, A_Q and its position map
  *   oracle_contracted_answer   Section 3.1 step 4, minimum over A_Q[Lc..Rc]
+ *   oracle_euler_tour          Section 1, the reduction of LCA to RMQ: the
+ *                              Euler tour of a rooted tree (depth and node of
+ *                              every step, first occurrence of every node)
  *
  * Conventions (the paper is 1-based and leaves ties open): positions are
  * 0-based, query ranges [l, r] are inclusive, and a minimum is the pair
@@ -278,4 +281,89 @@ void oracle_contracted_answer(const int32_t *A, const int32_t *aq, const int32_t
             best = better(A, best, aq[s]);
         out[i] = (int32_t)best;
     }
+}
+
+/* Section 1 (LCA reduces to RMQ): the Euler tour of the tree given by
+ * parent[] (parent[root] = -1), children visited in increasing id.  The tour
+ * lists the node reached by every step of a depth-first walk: the root, then
+ * for every edge the child when going down and the parent when coming back
+ * up -- 2N - 1 entries.  depth[i] and node[i] describe entry i; first[v] is
+ * the index of v's first entry.  Returns 0, or -1 if parent[] is not one
+ * tree (no single root, a parent out of range, or nodes the walk from the
+ * root never reaches).  Plain and serial: child lists by counting, then an
+ * explicit stack of (node, next child index). */
+int oracle_euler_tour(const int32_t *parent, int64_t N, int32_t *depth, int32_t *node,
+                      int32_t *first)
+{
+    int64_t root = -1, roots = 0;
+    for (int64_t v = 0; v < N; v++) {
+        if (parent[v] == -1) {
+            root = v;
+            roots++;
+        } else if (parent[v] < 0 || parent[v] >= N || parent[v] == v) {
+            return -1;
+        }
+    }
+    if (roots != 1)
+        return -1;
+    /* children of p, in increasing id: kids[start[p] .. start[p+1]) */
+    int64_t *start = calloc((size_t)N + 1, sizeof(int64_t));
+    int64_t *fill = calloc((size_t)N + 1, sizeof(int64_t));
+    int32_t *kids = malloc(sizeof(int32_t) * (size_t)(N > 1 ? N - 1 : 1));
+    int64_t *stack_node = malloc(sizeof(int64_t) * (size_t)N);
+    int64_t *stack_next = malloc(sizeof(int64_t) * (size_t)N);
+    int ok = start && fill && kids && stack_node && stack_next;
+    if (ok) {
+        for (int64_t v = 0; v < N; v++)
+            if (v != root)
+                start[parent[v] + 1]++;
+        for (int64_t p = 0; p < N; p++)
+            start[p + 1] += start[p];
+        for (int64_t v = 0; v < N; v++)  /* increasing v: each list in id order */
+            if (v != root) {
+                int64_t p = parent[v];
+                kids[start[p] + fill[p]++] = (int32_t)v;
+            }
+        for (int64_t v = 0; v < N; v++)
+            first[v] = -1;
+        int64_t len = 0, top = 0;
+        stack_node[0] = root;
+        stack_next[0] = start[root];
+        depth[len] = 0;
+        node[len] = (int32_t)root;
+        first[root] = 0;
+        len++;
+        while (top >= 0) {
+            int64_t v = stack_node[top];
+            if (stack_next[top] < start[v + 1]) {
+                int64_t c = kids[stack_next[top]++];  /* go down to the next child */
+                if (top + 1 >= N || len >= 2 * N - 1) {
+                    ok = 0;
+                    break;
+                }
+                top++;
+                stack_node[top] = c;
+                stack_next[top] = start[c];
+                depth[len] = (int32_t)top;
+                node[len] = (int32_t)c;
+                first[c] = (int32_t)len;
+                len++;
+            } else {
+                top--;  /* done with v: come back up to its parent */
+                if (top >= 0) {
+                    depth[len] = (int32_t)top;
+                    node[len] = (int32_t)stack_node[top];
+                    len++;
+                }
+            }
+        }
+        if (len != 2 * N - 1)
+            ok = 0;  /* some node is not below the root: a cycle */
+    }
+    free(start);
+    free(fill);
+    free(kids);
+    free(stack_node);
+    free(stack_next);
+    return ok ? 0 : -1;
 }

@@ -79,6 +79,11 @@ def lib() -> ctypes.CDLL:
         "rmq_query_index": ([v, v, v, i64, v, v], i32),
         "rmq_query_index_ex": ([v, v, v, i64, v, v, opt], i32),
         "rmq_index_free": ([v], i32),
+        "rmq_lca_build": ([v, i64, opt, v, ctypes.POINTER(v)], i32),
+        "rmq_lca_query": ([v, v, v, i64, v, v, opt], i32),
+        "rmq_lca_copy_tour": ([v, v, v, v, v], i32),
+        "rmq_lca_info": ([v, ctypes.POINTER(i64), ctypes.POINTER(sz)], i32),
+        "rmq_lca_free": ([v], i32),
         "rmq_index_info": ([v, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i64),
                             ctypes.POINTER(i32), ctypes.POINTER(sz)], i32),
         "rmq_index_copy_table": ([v, v, v], i32),
@@ -373,6 +378,63 @@ def key_values(keys: torch.Tensor) -> torch.Tensor:
     """High 32 bits of keys mapped back to the int32 values."""
     u = ((keys >> 32) & 0xFFFFFFFF) ^ 0x80000000
     return torch.where(u >= 2 ** 31, u - 2 ** 32, u).to(torch.int32)
+
+
+class LCA:
+    """Lowest common ancestors through RMQ (Section 1): the Euler tour of the
+    tree given by `parent` (int32 on the device, parent[root] = -1) and an
+    RMQ index over its depths, built on the device."""
+
+    def __init__(self, parent: torch.Tensor, block_size: int = 0, sub_block_size: int = 0,
+                 stream=None):
+        h = ctypes.c_void_p()
+        o = _options(block_size, "full", sub_block_size=sub_block_size)
+        _check("rmq_lca_build", lib().rmq_lca_build(_dev_i32(parent, "parent"), parent.numel(),
+                                                    ctypes.byref(o),
+                                                    _stream(parent.device, stream),
+                                                    ctypes.byref(h)))
+        self.handle = h
+        self.device = parent.device
+        self.num_nodes = parent.numel()
+        by = ctypes.c_size_t()
+        _check("rmq_lca_info", lib().rmq_lca_info(h, None, ctypes.byref(by)))
+        self.bytes = by.value
+
+    def query(self, u: torch.Tensor, v: torch.Tensor, out: Optional[torch.Tensor] = None,
+              bad_count=None, stream=None) -> torch.Tensor:
+        q = u.numel()
+        if v.numel() != q:
+            raise ValueError("u and v differ in length")
+        if out is None:
+            out = torch.empty(q, dtype=torch.int32, device=self.device)
+        o = _options(0, "full", bad_count)
+        _check("rmq_lca_query", lib().rmq_lca_query(
+            self.handle, _dev_i32(u, "u") if q else None, _dev_i32(v, "v") if q else None, q,
+            _dev_i32(out, "out") if q else None, _stream(self.device, stream), ctypes.byref(o)))
+        return out
+
+    def tour(self, stream=None):
+        """(depth, node, first) of the Euler tour, copied to new tensors."""
+        N = self.num_nodes
+        depth = torch.empty(2 * N - 1, dtype=torch.int32, device=self.device)
+        node = torch.empty(2 * N - 1, dtype=torch.int32, device=self.device)
+        first = torch.empty(N, dtype=torch.int32, device=self.device)
+        _check("rmq_lca_copy_tour", lib().rmq_lca_copy_tour(
+            self.handle, depth.data_ptr(), node.data_ptr(), first.data_ptr(),
+            _stream(self.device, stream)))
+        return depth, node, first
+
+    def free(self) -> None:
+        if getattr(self, "handle", None):
+            torch.cuda.synchronize(self.device)
+            _check("rmq_lca_free", lib().rmq_lca_free(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 class Batch:

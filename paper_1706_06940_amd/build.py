@@ -26,6 +26,7 @@ SOURCES = [
     "contract.hip",
     "capi.hip",
     "server.hip",
+    "lca.hip",
 ]
 
 ARCH = "gfx950"

@@ -103,6 +103,11 @@ hipError_t launch_query_full(const int32_t* A, int64_t n, int kshift, const uint
                              int64_t nb, const int32_t* L, const int32_t* R, int64_t q,
                              int32_t* out, int64_t* bad_count, uint64_t* stats,
                              hipStream_t stream);
+// LCA queries (Section 1) over the depth array D of an Euler tour.
+hipError_t launch_query_lca(const int32_t* D, int64_t len, int kshift, const uint64_t* st,
+                            int64_t nb, const uint64_t* sub, int k1shift, const int32_t* first,
+                            const int32_t* node, int64_t N, const int32_t* U, const int32_t* V,
+                            int64_t q, int32_t* out, int64_t* bad_count, hipStream_t stream);
 // Two block levels (Section 3.3): sub holds the minima of the 2^k1shift-blocks.
 hipError_t launch_query_full2(const int32_t* A, int64_t n, int kshift, const uint64_t* st,
                               int64_t nb, const uint64_t* sub, int k1shift, const int32_t* L,
@@ -121,6 +126,12 @@ hipError_t launch_sort_endpoints(const int32_t* L, const int32_t* R, int64_t q, 
 // sort's workspace.
 hipError_t launch_remap(const uint64_t* E, int64_t q, int32_t* LR, void* ws, size_t ws_bytes,
                         hipStream_t stream);
+// Stable sort of N 8-byte items by their high 32 bits (key < 2^key_bits),
+// the low 32 bits carried along.  items and out must not alias the
+// workspace of sort_pairs_workspace_bytes(N).
+size_t sort_pairs_workspace_bytes(int64_t N);
+hipError_t launch_sort_pairs(const uint64_t* items, int64_t N, int key_bits, uint64_t* out,
+                             void* ws, size_t ws_bytes, hipStream_t stream);
 // Split E into positions and tags, or join them into E.
 hipError_t launch_unpack_endpoints(const uint64_t* E, int64_t q, int32_t* pos, int32_t* tag,
                                    hipStream_t stream);

@@ -429,6 +429,37 @@ __global__ __launch_bounds__(WG) void k_query_segments(const ArrayDesc* __restri
              out + (live ? g : 0), nullptr, nullptr);
 }
 
+// Lowest common ancestors (Section 1): query i is the pair (U[i], V[i]) of
+// tree nodes; its range over the Euler tour's depth array runs between their
+// first occurrences, and the answer is the tour node at the minimum depth.
+template <class Src>
+__global__ __launch_bounds__(WG) void k_query_lca(Src src, int64_t len, int kshift,
+                                                  const uint64_t* __restrict__ st, int64_t nb,
+                                                  const int32_t* __restrict__ first,
+                                                  const int32_t* __restrict__ node, int64_t N,
+                                                  const int32_t* __restrict__ U,
+                                                  const int32_t* __restrict__ V, int64_t q,
+                                                  int32_t* __restrict__ out,
+                                                  unsigned long long* __restrict__ bad_count) {
+  const int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
+  const bool live = i < q;
+  int64_t l = -1, r = -1;  // an invalid node leaves l < 0: answered -1
+  if (live) {
+    const int64_t u = U[i], v = V[i];
+    if (0 <= u && u < N && 0 <= v && v < N) {
+      const int64_t fu = first[u], fv = first[v];
+      l = fu < fv ? fu : fv;
+      r = fu < fv ? fv : fu;
+    }
+  }
+  query_core(src, len, len, kshift, st, nb, l, r, l, r, live, out + (live ? i : 0), bad_count,
+             nullptr);
+  if (live) {
+    const int32_t p = out[i];
+    out[i] = p >= 0 ? node[p] : -1;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_query_segments(const ArrayDesc* tables, const int64_t* seg_prefix,
@@ -466,6 +497,25 @@ hipError_t launch_query_full2(const int32_t* A, int64_t n, int kshift, const uin
                  static_cast<const int32_t*>(nullptr), q, out, (unsigned long long*)bad_count,
                  (unsigned long long*)stats));
   return hipGetLastError();
+}
+
+hipError_t launch_query_lca(const int32_t* D, int64_t len, int kshift, const uint64_t* st,
+                            int64_t nb, const uint64_t* sub, int k1shift, const int32_t* first,
+                            const int32_t* node, int64_t N, const int32_t* U, const int32_t* V,
+                            int64_t q, int32_t* out, int64_t* bad_count, hipStream_t stream) {
+  if (q <= 0) return hipSuccess;
+  const int64_t grid = (q + WG - 1) / WG;
+  if (sub) {
+    const int64_t nsub = (len + (1ll << k1shift) - 1) >> k1shift;
+    RMQ_TRY(launch(k_query_lca<SrcA2>, dim3((unsigned)grid), dim3(WG), 0, stream,
+                   SrcA2{SrcA{D, len}, sub, nsub, k1shift}, len, kshift, st, nb, first, node, N,
+                   U, V, q, out, (unsigned long long*)bad_count));
+  } else {
+    RMQ_TRY(launch(k_query_lca<SrcA>, dim3((unsigned)grid), dim3(WG), 0, stream, SrcA{D, len},
+                   len, kshift, st, nb, first, node, N, U, V, q, out,
+                   (unsigned long long*)bad_count));
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_query_contracted(const uint64_t* aq, int64_t m, int64_t n, int kshift,

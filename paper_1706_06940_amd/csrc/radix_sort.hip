@@ -427,9 +427,10 @@ struct SortLayout {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-SortLayout sort_layout(int64_t q) {
+// Layout for N items (the endpoint sort has N = 2q).
+SortLayout sort_layout_items(int64_t N) {
   SortLayout s{};
-  s.N = 2 * q;
+  s.N = N;
   s.num_tiles = (s.N + TILE - 1) / TILE;
   s.hist_per_group = hist_tiles(s.num_tiles);
   s.hist_groups = (s.num_tiles + s.hist_per_group - 1) / s.hist_per_group;
@@ -504,9 +505,23 @@ hipError_t onesweep(const uint64_t* src, const int32_t* L, const int32_t* R, int
   return hipSuccess;
 }
 
+SortLayout sort_layout(int64_t q) { return sort_layout_items(2 * q); }
+
 }  // namespace
 
 size_t sort_workspace_bytes(int64_t q) { return q > 0 ? sort_layout(q).bytes : 0; }
+
+size_t sort_pairs_workspace_bytes(int64_t N) { return N > 0 ? sort_layout_items(N).bytes : 0; }
+
+hipError_t launch_sort_pairs(const uint64_t* items, int64_t N, int key_bits, uint64_t* out,
+                             void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (N <= 0) return hipSuccess;
+  const SortLayout lay = sort_layout_items(N);
+  if (ws_bytes < lay.bytes || key_bits < 1 || key_bits > 32) return hipErrorInvalidValue;
+  const SortBufs b = sort_bufs(lay, ws);
+  return onesweep<ITEMS>(items, nullptr, nullptr, N, 0, split_digits(0, key_bits), lay, b, out,
+                         nullptr, stream);
+}
 
 hipError_t launch_sort_endpoints(const int32_t* L, const int32_t* R, int64_t q, int64_t n,
                                  uint64_t* E, int32_t* LR, void* ws, size_t ws_bytes,

@@ -141,6 +141,71 @@ def check_lca(orc):
                 assert depth[o] == dn[lca]
 
 
+def first_occurrence(node, N):
+    f = np.full(N, -1, dtype=np.int64)
+    for i in range(node.shape[0] - 1, -1, -1):
+        f[node[i]] = i
+    return f
+
+
+def check_euler_tour(orc):
+    """The oracle's Euler tour (Section 1): hand-worked tour, structure of the
+    tour (2N-1 steps of +-1, node depths, first occurrences, every edge
+    walked down and up once), LCA by parent climbing, and None for inputs
+    that are not one tree."""
+    with open(GOLDEN) as f:
+        lg = json.load(f)["lca"]
+    res = orc.euler_tour(np.array(lg["parent"], dtype=np.int32))
+    assert res is not None
+    depth, node, first = res
+    assert depth.tolist() == lg["euler_depth"] and node.tolist() == lg["euler_node"]
+    assert first.tolist() == lg["first"]
+    rng = np.random.default_rng(21)
+    trees = [W.random_recursive_tree(N, N + 1) for N in (1, 2, 3, 50, 3000)]
+    trees.append(np.arange(-1, 999, dtype=np.int32))        # a path, depth 999
+    trees.append(np.r_[-1, np.zeros(500, dtype=np.int32)])   # a star
+    perm = rng.permutation(700)                                # relabelled random tree
+    base = W.random_recursive_tree(700, 5)
+    relab = np.empty(700, dtype=np.int32)
+    relab[perm] = np.where(base < 0, -1, perm[np.maximum(base, 0)])
+    trees.append(relab)
+    for parent in trees:
+        N = parent.shape[0]
+        res = orc.euler_tour(parent)
+        assert res is not None, N
+        depth, node, first = res
+        assert depth.shape[0] == 2 * N - 1 and node.shape[0] == 2 * N - 1
+        assert np.all(np.abs(np.diff(depth)) == 1)
+        root = int(np.nonzero(parent < 0)[0][0])
+        assert node[0] == root and node[-1] == root and depth[0] == 0
+        dn = np.zeros(N, dtype=np.int64)
+        for v in range(N):  # depth by climbing
+            x, d = v, 0
+            while parent[x] >= 0:
+                x, d = parent[x], d + 1
+            dn[v] = d
+        assert np.array_equal(depth, dn[node])
+        assert np.array_equal(first, first_occurrence(node, N))
+        steps = [(int(node[i]), int(node[i + 1])) for i in range(2 * N - 2)]
+        down = [(a, b) for i, (a, b) in enumerate(steps) if depth[i + 1] == depth[i] + 1]
+        up = [(b, a) for i, (a, b) in enumerate(steps) if depth[i + 1] == depth[i] - 1]
+        edges = sorted((int(parent[b]), b) for b in range(N) if parent[b] >= 0)
+        assert sorted(down) == edges and sorted(up) == edges  # each edge down once, up once
+        for v in range(N):  # children in increasing id
+            kids = [b for a, b in down if a == v]
+            assert kids == sorted(kids)
+        if N > 1:
+            u = rng.integers(0, N, 300)
+            w = rng.integers(0, N, 300)
+            L = np.minimum(first[u], first[w]).astype(np.int32)
+            R = np.maximum(first[u], first[w]).astype(np.int32)
+            out = orc.rmq_scan(depth, L, R)
+            for a, b, o in zip(u, w, out):
+                assert node[o] == naive_lca(parent, dn, int(a), int(b))
+    for bad in ([-1, -1, 0], [-1, 2, 1], [0], [-1, 5], [-1, 0, 3, 2], [1, 0, -1]):
+        assert orc.euler_tour(np.array(bad, dtype=np.int32)) is None, bad
+
+
 def check_golden(orc):
     with open(GOLDEN) as f:
         g = json.load(f)
@@ -241,7 +306,8 @@ def check_invalid(orc):
 
 
 ALL = [check_scan_bruteforce, check_sparse_table_bruteforce, check_whole_array, check_golden,
-       check_blocks, check_contraction, check_invalid, check_lca, check_invariants]
+       check_blocks, check_contraction, check_invalid, check_lca, check_invariants,
+       check_euler_tour]
 
 
 def run_all(orc):

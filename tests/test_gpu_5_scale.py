@@ -5,7 +5,9 @@
   method with two block levels (Section 3.3);
 * Euler-tour depth array of a random recursive tree with 5e8 nodes
   (999,999,999 steps, +-1), 1e7 LCA queries: the answer's tour node is the
-  LCA found by climbing parent pointers, and equals the oracle's answer;
+  LCA found by climbing parent pointers, and equals the oracle's answer; the
+  device LCA front-end builds the same tour as the oracle and gives the same
+  LCAs;
 * n = 1e8, q = 1e7 uniform (the benchmark's largest batch), both methods.
 
 The oracle here is its Sparse Table over 32-element blocks (pinned against
@@ -91,6 +93,15 @@ def test_c3_lca_half_billion_nodes(orc):
         a[m] = parent[a[m]]
         b[m] = parent[b[m]]
     assert np.array_equal(node[got], a)
+    log("device LCA front-end")
+    h = rmq.LCA(dev(parent, d))
+    got2 = h.query(dev(u, d), dev(v, d)).cpu().numpy()
+    assert np.array_equal(got2, a)
+    log("oracle tour")
+    exp = orc.euler_tour(parent)
+    tour = [t.cpu().numpy() for t in h.tour()]
+    h.free()
+    assert all(np.array_equal(x, y) for x, y in zip(tour, exp))
     log("done")
 
 

@@ -34,6 +34,12 @@ MUTANTS = {
     "block_drops_last_element": ("pos[j] = (int32_t)scan_argmin(A, j * k, hi - 1);",
                                  "pos[j] = (int32_t)scan_argmin(A, j * k, hi - 2 >= j * k ? hi - 2 : j * k);"),
     "accepts_reversed_range": ("return 0 <= l && l <= r && r < n;", "return 0 <= l && r < n;"),
+    "tour_children_descending": ("for (int64_t v = 0; v < N; v++)  /* increasing v: each list in id order */",
+                                 "for (int64_t v = N - 1; v >= 0; v--)  /* decreasing */"),
+    "tour_misses_up_steps": ("                if (top >= 0) {\n                    depth[len] = (int32_t)top;",
+                             "                if (top >= 0 && top > 0) {\n                    depth[len] = (int32_t)top;"),
+    "tour_first_is_last": ("                node[len] = (int32_t)stack_node[top];\n                    len++;",
+                           "                node[len] = (int32_t)stack_node[top];\n                    first[stack_node[top]] = (int32_t)len;\n                    len++;"),
     "answer_skips_first": ("int64_t best = aq[Lc[i]];\n        for (int64_t s = (int64_t)Lc[i] + 1;",
                            "int64_t best = aq[Rc[i]];\n        for (int64_t s = (int64_t)Lc[i] + 1;"),
 }
