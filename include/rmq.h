@@ -105,6 +105,15 @@ typedef struct rmq_options {
                                 at most two partial k1-blocks.  With block_size 0,
                                 k is the power of two nearest
                                 sqrt(n) * log2(n)^(2/3) (at least 2 * k1). */
+    int32_t table_arity_log2; /* Section 3.1, the table over powers of l instead
+                                 of 2: l = 2^table_arity_log2.  0 or 1: the
+                                 doubling table (l = 2).  2..5 (l = 4..32):
+                                 level i holds the minima of l^i consecutive
+                                 blocks, there are floor(log2(nb - 2) /
+                                 log2(l)) + 1 levels for nb > 3 blocks (1
+                                 otherwise), and a query reads at most l of
+                                 them.  Both methods and the resident index;
+                                 not the batched calls (RMQ_ERR_INVALID_ARG). */
 } rmq_options;
 
 /* A human-readable name for a status code (static storage). */
@@ -163,7 +172,8 @@ int32_t rmq_default_block(int64_t n, int64_t q, int32_t path);
  * (Section 3.2 sets k = Theta(sqrt(n))); opt->path is ignored.  With
  * opt->sub_block_size > 0 the index has two block levels (Section 3.3): the
  * k1-block minima are kept beside the table and partial blocks are read
- * through them.  *idx is set only on success.  The build is enqueued on
+ * through them.  opt->table_arity_log2 > 1 builds the table over powers of
+ * l instead of 2 (Section 3.1).  *idx is set only on success.  The build is enqueued on
  * `stream`. */
 rmq_status rmq_build(const int32_t *A, int64_t n, const rmq_options *opt, void *stream,
                      rmq_index *idx);
@@ -185,7 +195,8 @@ rmq_status rmq_index_info(rmq_index idx, int64_t *n, int32_t *block_size, int64_
                           int32_t *levels, size_t *bytes);
 
 /* Copy of the index's Sparse Table (level-major, levels x num_blocks uint64
- * keys; level 0 = block minima) into device memory `st`, on `stream`. */
+ * keys; level 0 = block minima; level i spans 2^i blocks, or l^i for a table
+ * over powers of l) into device memory `st`, on `stream`. */
 rmq_status rmq_index_copy_table(rmq_index idx, uint64_t *st, void *stream);
 
 /* Device bytes of a resident index for (n, k): 8 * nb * levels with
@@ -196,6 +207,11 @@ size_t rmq_index_bytes(int64_t n, int32_t block_size);
 
 /* Number of Sparse Table levels for nb blocks (see rmq_index_bytes). */
 int32_t rmq_table_levels(int64_t num_blocks);
+
+/* Levels of the table over powers of l = 2^table_arity_log2 (Section 3.1;
+ * see rmq_options.table_arity_log2) for nb blocks; 0 on invalid arguments.
+ * table_arity_log2 0 or 1 gives rmq_table_levels. */
+int32_t rmq_table_levels_ary(int64_t num_blocks, int32_t table_arity_log2);
 
 /* ----------------------------------------------------------------------------
  * Lowest common ancestors through RMQ (Section 1: in the Euler tour of a
@@ -211,8 +227,9 @@ typedef struct rmq_lca_s *rmq_lca;
 /* parent: device int32[num_nodes]; parent[root] = -1 for exactly one root,
  * every other entry in [0, num_nodes) and the parent links acyclic.
  * 1 <= num_nodes <= 2^30.  The tour visits children in increasing id; it
- * has 2 * num_nodes - 1 entries.  opt->block_size / sub_block_size choose
- * the RMQ index over D as for rmq_build (NULL: defaults).  The call waits
+ * has 2 * num_nodes - 1 entries.  opt->block_size, sub_block_size and
+ * table_arity_log2 choose the RMQ index over D as for rmq_build (NULL:
+ * defaults).  The call waits
  * for the device (it checks the input and the tour) and returns
  * RMQ_ERR_INVALID_ARG for a forest, a parent out of range or a cycle.
  * Temporary device memory: about 60 bytes per node, freed before return. */

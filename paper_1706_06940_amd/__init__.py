@@ -49,6 +49,7 @@ class _Options(ctypes.Structure):
         ("workspace_bytes", ctypes.c_size_t),
         ("timer", ctypes.c_void_p),
         ("sub_block_size", ctypes.c_int32),
+        ("table_arity_log2", ctypes.c_int32),
     ]
 
 
@@ -89,6 +90,7 @@ def lib() -> ctypes.CDLL:
         "rmq_index_copy_table": ([v, v, v], i32),
         "rmq_index_bytes": ([i64, i32], sz),
         "rmq_table_levels": ([i64], i32),
+        "rmq_table_levels_ary": ([i64, i32], i32),
         "rmq_block_minima": ([v, i64, i32, v, v], i32),
         "rmq_block_minima_keys": ([v, i64, i32, v, v], i32),
         "rmq_sparse_table_build": ([v, i64, i32, v], i32),
@@ -161,10 +163,12 @@ class Timer:
 
 
 def _options(block_size=0, path="auto", bad_count=None, stats=None, workspace=None,
-             timer: Optional[Timer] = None, sub_block_size: int = 0) -> _Options:
+             timer: Optional[Timer] = None, sub_block_size: int = 0,
+             arity_log2: int = 0) -> _Options:
     o = _Options()
     o.block_size = int(block_size)
     o.sub_block_size = int(sub_block_size)
+    o.table_arity_log2 = int(arity_log2)
     o.path = PATHS[path] if isinstance(path, str) else int(path)
     o.bad_count = _dev_u64(bad_count, "bad_count") if bad_count is not None else None
     o.stats = _dev_u64(stats, "stats") if stats is not None else None
@@ -230,8 +234,8 @@ def default_block(n: int, q: int, path: str) -> int:
 
 
 def workspace_bytes(n: int, q: int, path="auto", block_size: int = 0,
-                    sub_block_size: int = 0) -> int:
-    o = _options(block_size, path, sub_block_size=sub_block_size)
+                    sub_block_size: int = 0, arity_log2: int = 0) -> int:
+    o = _options(block_size, path, sub_block_size=sub_block_size, arity_log2=arity_log2)
     return int(lib().rmq_workspace_bytes(n, q, ctypes.byref(o)))
 
 
@@ -239,23 +243,29 @@ def index_bytes(n: int, block_size: int) -> int:
     return int(lib().rmq_index_bytes(n, block_size))
 
 
-def table_levels(num_blocks: int) -> int:
-    return int(lib().rmq_table_levels(num_blocks))
+def table_levels(num_blocks: int, arity_log2: int = 0) -> int:
+    """Levels of the block table: doubling, or over powers of
+    l = 2^arity_log2 (Section 3.1)."""
+    if arity_log2 <= 1:
+        return int(lib().rmq_table_levels(num_blocks))
+    return int(lib().rmq_table_levels_ary(num_blocks, arity_log2))
 
 
 def query_batch(A: torch.Tensor, L: torch.Tensor, R: torch.Tensor, *, path="auto",
-                block_size: int = 0, sub_block_size: int = 0,
+                block_size: int = 0, sub_block_size: int = 0, arity_log2: int = 0,
                 out: Optional[torch.Tensor] = None, bad_count=None, stats=None, workspace=None,
                 timer: Optional[Timer] = None, stream=None) -> torch.Tensor:
     """Answer all queries of one offline batch (Section 1); returns int32 out.
     sub_block_size > 0 selects two block levels (Section 3.3) on the plain
-    method."""
+    method; arity_log2 in 2..5 builds the block table over powers of
+    l = 2^arity_log2 instead of 2 (Section 3.1)."""
     n, q = A.numel(), L.numel()
     if R.numel() != q:
         raise ValueError("L and R differ in length")
     if out is None:
         out = torch.empty(q, dtype=torch.int32, device=A.device)
-    o = _options(block_size, path, bad_count, stats, workspace, timer, sub_block_size)
+    o = _options(block_size, path, bad_count, stats, workspace, timer, sub_block_size,
+                 arity_log2)
     st = lib().rmq_query_batch_ex(_dev_i32(A, "A"), n, _dev_i32(L, "L") if q else None,
                                   _dev_i32(R, "R") if q else None, q,
                                   _dev_i32(out, "out") if q else None,
@@ -266,13 +276,14 @@ def query_batch(A: torch.Tensor, L: torch.Tensor, R: torch.Tensor, *, path="auto
 
 class Index:
     """Resident block Sparse Table of A (Section 3.2) for repeated batches,
-    with the k1-block minima too when sub_block_size > 0 (Section 3.3).
-    Keeps a reference to A, which partial-block scans read."""
+    with the k1-block minima too when sub_block_size > 0 (Section 3.3), and
+    the table over powers of l = 2^arity_log2 when arity_log2 > 1 (Section
+    3.1).  Keeps a reference to A, which partial-block scans read."""
 
     def __init__(self, A: torch.Tensor, block_size: int = 0, stream=None,
-                 sub_block_size: int = 0):
+                 sub_block_size: int = 0, arity_log2: int = 0):
         h = ctypes.c_void_p()
-        o = _options(block_size, "full", sub_block_size=sub_block_size)
+        o = _options(block_size, "full", sub_block_size=sub_block_size, arity_log2=arity_log2)
         _check("rmq_build", lib().rmq_build(_dev_i32(A, "A"), A.numel(), ctypes.byref(o),
                                             _stream(A.device, stream), ctypes.byref(h)))
         self.handle = h
@@ -386,9 +397,9 @@ class LCA:
     RMQ index over its depths, built on the device."""
 
     def __init__(self, parent: torch.Tensor, block_size: int = 0, sub_block_size: int = 0,
-                 stream=None):
+                 stream=None, arity_log2: int = 0):
         h = ctypes.c_void_p()
-        o = _options(block_size, "full", sub_block_size=sub_block_size)
+        o = _options(block_size, "full", sub_block_size=sub_block_size, arity_log2=arity_log2)
         _check("rmq_lca_build", lib().rmq_lca_build(_dev_i32(parent, "parent"), parent.numel(),
                                                     ctypes.byref(o),
                                                     _stream(parent.device, stream),

@@ -73,7 +73,17 @@ struct Plan {
   int32_t k;
   int kshift;
   int k1shift;  // two block levels (Section 3.3): k1 = 2^k1shift; -1 = one level
+  int lg;       // table over powers of l = 2^lg (Section 3.1); 1 = doubling
 };
+
+// opt->table_arity_log2 as lg (0 and 1 both mean doubling); -1 if invalid.
+int arity_lg(const rmq_options* opt) {
+  const int32_t a = opt ? opt->table_arity_log2 : 0;
+  if (a < 0 || a > 5) return -1;
+  return a < 1 ? 1 : a;
+}
+
+int32_t table_levels(int64_t nb, int lg) { return lary_levels(nb, lg); }
 
 // Section 3.3's choice for two levels: k2 = sqrt(n) log^(2/3) n, as a power
 // of two, at least 2 * k1.
@@ -93,6 +103,8 @@ rmq_status make_plan(int64_t n, int64_t q, const rmq_options* opt, Plan* p) {
     return RMQ_ERR_INVALID_ARG;
   if (k != 0 && !is_pow2_block(k)) return RMQ_ERR_INVALID_ARG;
   p->k1shift = -1;
+  p->lg = arity_lg(opt);
+  if (p->lg < 0) return RMQ_ERR_INVALID_ARG;
   if (k1 != 0) {
     // two block levels: the plain method with k1 < k
     if (!is_pow2_block(k1) || path == RMQ_PATH_CONTRACTED) return RMQ_ERR_INVALID_ARG;
@@ -125,10 +137,10 @@ struct FullLayout {
 };
 
 // The table, then (two block levels) the k1-block minima.
-FullLayout full_layout(int64_t n, int64_t k, int k1shift) {
+FullLayout full_layout(int64_t n, int64_t k, int k1shift, int lg) {
   FullLayout f{};
   f.nb = num_blocks(n, k);
-  f.levels = rmq_table_levels(f.nb);
+  f.levels = table_levels(f.nb, lg);
   f.off_st = 0;
   f.off_sub = align_up(sizeof(uint64_t) * (size_t)f.nb * (size_t)f.levels);
   f.nb1 = k1shift >= 0 ? num_blocks(n, 1ll << k1shift) : 0;
@@ -142,12 +154,12 @@ struct ConLayout {
   size_t off_E, off_sort, off_lr, off_aq, off_tiles, off_st, bytes;
 };
 
-ConLayout con_layout(int64_t n, int64_t q, int64_t k) {
+ConLayout con_layout(int64_t n, int64_t q, int64_t k, int lg) {
   ConLayout c{};
   c.M = 2 * q;
   c.m = c.M - 1;
   c.nb = num_blocks(c.m, k);
-  c.levels = rmq_table_levels(c.nb);
+  c.levels = table_levels(c.nb, lg);
   size_t o = 0;
   c.off_E = o;
   o = align_up(o + sizeof(uint64_t) * (size_t)c.M);
@@ -166,8 +178,8 @@ ConLayout con_layout(int64_t n, int64_t q, int64_t k) {
 }
 
 size_t plan_bytes(int64_t n, int64_t q, const Plan& p) {
-  if (p.path == RMQ_PATH_FULL) return full_layout(n, p.k, p.k1shift).bytes;
-  return con_layout(n, q, p.k).bytes;
+  if (p.path == RMQ_PATH_FULL) return full_layout(n, p.k, p.k1shift, p.lg).bytes;
+  return con_layout(n, q, p.k, p.lg).bytes;
 }
 
 std::once_flag g_pool_once[64];
@@ -216,13 +228,19 @@ bool check_query_ptrs(const int32_t* L, const int32_t* R, int32_t* out, int64_t 
   return L && R && out;
 }
 
+// Section 3.1's table over the block minima at st[0 .. nb): doubling, or
+// powers of l = 2^lg.
+hipError_t build_table(uint64_t* st, int64_t nb, int levels, int lg, hipStream_t s) {
+  return lg > 1 ? launch_sparse_table_lary(st, nb, lg, s) : launch_sparse_table(st, nb, levels, s);
+}
+
 rmq_status run_full(const int32_t* A, int64_t n, const int32_t* L, const int32_t* R, int64_t q,
                     int32_t* out, hipStream_t s, const rmq_options* opt, const Plan& p,
                     char* ws) {
   rmq_timer* t = opt ? opt->timer : nullptr;
   ClockGuard guard;
   if (t) t->ran[0] = false;  // no sort stage on this path
-  const FullLayout f = full_layout(n, p.k, p.k1shift);
+  const FullLayout f = full_layout(n, p.k, p.k1shift, p.lg);
   uint64_t* st = reinterpret_cast<uint64_t*>(ws + f.off_st);
   uint64_t* sub = reinterpret_cast<uint64_t*>(ws + f.off_sub);
   const bool two = p.k1shift >= 0;
@@ -238,15 +256,15 @@ rmq_status run_full(const int32_t* A, int64_t n, const int32_t* L, const int32_t
   if (e != hipSuccess) return from_hip(e);
   stage_end(t, 1, s);
   stage_begin(t, 2);
-  e = launch_sparse_table(st, f.nb, f.levels, s);
+  e = build_table(st, f.nb, f.levels, p.lg, s);
   if (e != hipSuccess) return from_hip(e);
   stage_end(t, 2, s);
   stage_begin(t, 3);
   int64_t* bad = opt ? opt->bad_count : nullptr;
   uint64_t* stats = opt ? opt->stats : nullptr;
   e = two ? launch_query_full2(A, n, p.kshift, st, f.nb, sub, p.k1shift, L, R, q, out, bad, stats,
-                               s)
-          : launch_query_full(A, n, p.kshift, st, f.nb, L, R, q, out, bad, stats, s);
+                               s, p.lg)
+          : launch_query_full(A, n, p.kshift, st, f.nb, L, R, q, out, bad, stats, s, p.lg);
   if (e != hipSuccess) return from_hip(e);
   stage_end(t, 3, s);
   return RMQ_OK;
@@ -256,7 +274,7 @@ rmq_status run_contracted(const int32_t* A, int64_t n, const int32_t* L, const i
                           int64_t q, int32_t* out, hipStream_t s, const rmq_options* opt,
                           const Plan& p, char* ws) {
   rmq_timer* t = opt ? opt->timer : nullptr;
-  const ConLayout c = con_layout(n, q, p.k);
+  const ConLayout c = con_layout(n, q, p.k, p.lg);
   uint64_t* E = reinterpret_cast<uint64_t*>(ws + c.off_E);
   int32_t* LR = reinterpret_cast<int32_t*>(ws + c.off_lr);
   uint64_t* aq = reinterpret_cast<uint64_t*>(ws + c.off_aq);
@@ -276,12 +294,13 @@ rmq_status run_contracted(const int32_t* A, int64_t n, const int32_t* L, const i
   stage_begin(t, 2);
   e = launch_blockmin_keys(aq, c.m, p.kshift, st, s);
   if (e != hipSuccess) return from_hip(e);
-  e = launch_sparse_table(st, c.nb, c.levels, s);
+  e = build_table(st, c.nb, c.levels, p.lg, s);
   if (e != hipSuccess) return from_hip(e);
   stage_end(t, 2, s);
   stage_begin(t, 3);
   e = launch_query_contracted(aq, c.m, n, p.kshift, st, c.nb, L, R, LR, q, out,
-                              opt ? opt->bad_count : nullptr, opt ? opt->stats : nullptr, s);
+                              opt ? opt->bad_count : nullptr, opt ? opt->stats : nullptr, s,
+                              p.lg);
   if (e != hipSuccess) return from_hip(e);
   stage_end(t, 3, s);
   return RMQ_OK;
@@ -308,6 +327,11 @@ const char* rmq_version(void) { return "rmq-gfx950 1.0"; }
 int32_t rmq_table_levels(int64_t nb) {
   if (nb <= 3) return 1;
   return ilog2_i64(nb - 2) + 1;
+}
+
+int32_t rmq_table_levels_ary(int64_t nb, int32_t table_arity_log2) {
+  if (nb < 1 || table_arity_log2 < 0 || table_arity_log2 > 5) return 0;
+  return table_levels(nb, table_arity_log2 < 1 ? 1 : table_arity_log2);
 }
 
 size_t rmq_index_bytes(int64_t n, int32_t k) {
@@ -419,7 +443,8 @@ rmq_status rmq_build(const int32_t* A, int64_t n, const rmq_options* opt, void* 
   if (!aligned_to(A, 4)) return RMQ_ERR_MISALIGNED;
   int32_t k = opt ? opt->block_size : 0;
   const int32_t k1 = opt ? opt->sub_block_size : 0;
-  if (k1 != 0 && !is_pow2_block(k1)) return RMQ_ERR_INVALID_ARG;
+  const int lg = arity_lg(opt);
+  if (lg < 0 || (k1 != 0 && !is_pow2_block(k1))) return RMQ_ERR_INVALID_ARG;
   if (k == 0 && k1 != 0) {
     k = default_block_two_level(n, k1);
   } else if (k == 0) {
@@ -437,7 +462,8 @@ rmq_status rmq_build(const int32_t* A, int64_t n, const rmq_options* opt, void* 
   ix->n = n;
   ix->kshift = ilog2_i64(k);
   ix->nb = num_blocks(n, k);
-  ix->levels = rmq_table_levels(ix->nb);
+  ix->lg = lg;
+  ix->levels = table_levels(ix->nb, lg);
   ix->k1shift = k1 != 0 ? ilog2_i64(k1) : -1;
   ix->nb1 = k1 != 0 ? num_blocks(n, k1) : 0;
   const size_t table_bytes = sizeof(uint64_t) * (size_t)ix->nb * (size_t)ix->levels;
@@ -459,7 +485,7 @@ rmq_status rmq_build(const int32_t* A, int64_t n, const rmq_options* opt, void* 
   } else {
     e = launch_blockmin_i32(A, n, ix->kshift, ix->st, s);
   }
-  if (e == hipSuccess) e = launch_sparse_table(ix->st, ix->nb, ix->levels, s);
+  if (e == hipSuccess) e = build_table(ix->st, ix->nb, ix->levels, ix->lg, s);
   if (e != hipSuccess) {
     hipFree(mem);
     free(ix);
@@ -481,9 +507,9 @@ rmq_status rmq_query_index_ex(rmq_index idx, const int32_t* L, const int32_t* R,
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e =
       idx->sub ? launch_query_full2(idx->A, idx->n, idx->kshift, idx->st, idx->nb, idx->sub,
-                                    idx->k1shift, L, R, q, out, bad, stats, s)
+                                    idx->k1shift, L, R, q, out, bad, stats, s, idx->lg)
                : launch_query_full(idx->A, idx->n, idx->kshift, idx->st, idx->nb, L, R, q, out,
-                                   bad, stats, s);
+                                   bad, stats, s, idx->lg);
   return from_hip(e);
 }
 
@@ -747,9 +773,9 @@ rmq_status rmq_batch_create(const rmq_batch_item* items, int32_t count, rmq_batc
   for (int c = 0; c < cnt; ++c) {
     const int i = b->full_items[c];
     const rmq_batch_item& it = items[i];
-    const FullLayout f = full_layout(it.n, b->plans[i].k, -1);
+    const FullLayout f = full_layout(it.n, b->plans[i].k, -1, 1);
     desc[c] = ArrayDesc{it.A, it.n, b->plans[i].kshift, f.levels, f.nb, nullptr,
-                        it.L, it.R, it.q, it.out};
+                        it.L, it.R, it.q, it.out, 1};
     wg[c + 1] = wg[c] + blockmin_grid(it.n, b->plans[i].kshift, 4);
     qp[c + 1] = qp[c] + it.q;
     const int rounds = st_rounds(f.levels);

@@ -11,6 +11,7 @@ struct rmq_index_s {
   int kshift;        // block size k = 2^kshift
   int64_t nb;        // number of blocks
   int levels;        // Sparse Table levels
+  int lg;            // table arity l = 2^lg (1: doubling, Section 3.1)
   uint64_t* st;      // level-major levels x nb keys (device)
   uint64_t* sub;     // two block levels (Section 3.3): k1-block minima, else null
   int k1shift;       // k1 = 2^k1shift when sub is set

@@ -66,6 +66,7 @@ struct ArrayDesc {
   const int32_t* R;
   int64_t q;
   int32_t* out;
+  int32_t lg;  // table arity l = 2^lg (1: doubling)
 };
 
 // Sparse Table rounds: round r builds levels j0(r)+1 .. j0(r)+t; j0 = 0,
@@ -82,6 +83,10 @@ hipError_t launch_blockmin_i32(const int32_t* A, int64_t n, int kshift, uint64_t
 hipError_t launch_blockmin_keys(const uint64_t* S, int64_t m, int kshift, uint64_t* keys,
                                 hipStream_t stream);
 hipError_t launch_sparse_table(uint64_t* st, int64_t nb, int levels, hipStream_t stream);
+// l-ary table (Section 3.1), l = 2^lg >= 4: level i holds the minima over
+// l^i blocks (truncated at nb); levels = lary_levels(nb, lg).  Level 0 given.
+int lary_levels(int64_t nb, int lg);
+hipError_t launch_sparse_table_lary(uint64_t* st, int64_t nb, int lg, hipStream_t stream);
 int64_t blockmin_grid(int64_t n, int kshift, int elems_per_lane_load);
 // Batched forms: one launch per phase for all arrays of a batch.  The
 // prefix tables (count + 1 entries, starting at 0) give each array's first
@@ -99,20 +104,22 @@ hipError_t launch_query_segments(const ArrayDesc* tables, const int64_t* seg_pre
                                  const int32_t* seg_table, int nseg, const int32_t* L,
                                  const int32_t* R, int32_t* out, int64_t total,
                                  hipStream_t stream);
+// lg: the table's arity l = 2^lg (1: doubling; see launch_sparse_table_lary).
 hipError_t launch_query_full(const int32_t* A, int64_t n, int kshift, const uint64_t* st,
                              int64_t nb, const int32_t* L, const int32_t* R, int64_t q,
                              int32_t* out, int64_t* bad_count, uint64_t* stats,
-                             hipStream_t stream);
+                             hipStream_t stream, int lg = 1);
 // LCA queries (Section 1) over the depth array D of an Euler tour.
 hipError_t launch_query_lca(const int32_t* D, int64_t len, int kshift, const uint64_t* st,
                             int64_t nb, const uint64_t* sub, int k1shift, const int32_t* first,
                             const int32_t* node, int64_t N, const int32_t* U, const int32_t* V,
-                            int64_t q, int32_t* out, int64_t* bad_count, hipStream_t stream);
+                            int64_t q, int32_t* out, int64_t* bad_count, hipStream_t stream,
+                            int lg = 1);
 // Two block levels (Section 3.3): sub holds the minima of the 2^k1shift-blocks.
 hipError_t launch_query_full2(const int32_t* A, int64_t n, int kshift, const uint64_t* st,
                               int64_t nb, const uint64_t* sub, int k1shift, const int32_t* L,
                               const int32_t* R, int64_t q, int32_t* out, int64_t* bad_count,
-                              uint64_t* stats, hipStream_t stream);
+                              uint64_t* stats, hipStream_t stream, int lg = 1);
 
 // ---- contracted path (Section 3.1) ----
 // Device LSD radix sort of the 2q endpoints by (position, tag).  The sorted
@@ -145,6 +152,7 @@ hipError_t launch_contract(const int32_t* A, int64_t n, const uint64_t* E, int64
 hipError_t launch_query_contracted(const uint64_t* aq, int64_t m, int64_t n, int kshift,
                                    const uint64_t* st, int64_t nb, const int32_t* L,
                                    const int32_t* R, const int32_t* LR, int64_t q, int32_t* out,
-                                   int64_t* bad_count, uint64_t* stats, hipStream_t stream);
+                                   int64_t* bad_count, uint64_t* stats, hipStream_t stream,
+                                   int lg = 1);
 
 }  // namespace rmq

@@ -1,5 +1,6 @@
 // Block Sparse Table (Section 3.1 step 3; Section 2, the doubling of Bender
 // and Farach): st[j][b] = min(st[0][b .. min(b + 2^j, nb) - 1]), level-major.
+// The table over powers of l (Section 3.1's generalisation) is at the end.
 //
 // A round computes t consecutive levels j0+1 .. j0+t from level j0 inside
 // LDS.  With stride s = 2^j0, level j0+m at block b is the min of level j0 at
@@ -135,7 +136,45 @@ __global__ __launch_bounds__(WG) void k_st_multi(const ArrayDesc* __restrict__ i
   st_tile(d.st, d.nb, j0, t, R, col_tiles, blockIdx.x - tile_prefix[j], lds);
 }
 
+// One level of the table over powers of l = 2^lg (Section 3.1): level i at
+// block b is the min of level i-1 at b, b + s, ..., b + (l-1)s with
+// s = l^(i-1), entries past the last block left out (truncated spans, as in
+// the doubling table).  Consecutive threads take consecutive b, so each of
+// the l reads is a coalesced row; rows that neighbouring workgroups share
+// come from L2.
+__global__ __launch_bounds__(WG) void k_st_lary(const uint64_t* __restrict__ prev,
+                                                uint64_t* __restrict__ cur, int64_t nb,
+                                                int64_t s, int l) {
+  const int64_t b = (int64_t)blockIdx.x * WG + threadIdx.x;
+  if (b >= nb) return;
+  const int64_t avail = (nb - 1 - b) / s + 1;  // terms with b + j s < nb
+  const int cnt = avail < l ? (int)avail : l;
+  uint64_t m = prev[b];
+#pragma unroll 8
+  for (int j = 1; j < cnt; ++j) m = umin64(m, prev[b + j * s]);
+  cur[b] = m;
+}
+
 }  // namespace
+
+int lary_levels(int64_t nb, int lg) {
+  if (nb <= 3) return 1;
+  int t = 0;  // floor(log2(nb - 2)): the largest inner span is nb - 2 blocks
+  while ((int64_t)2 << t <= nb - 2) ++t;
+  return t / lg + 1;
+}
+
+hipError_t launch_sparse_table_lary(uint64_t* st, int64_t nb, int lg, hipStream_t stream) {
+  const int levels = lary_levels(nb, lg);
+  const int64_t grid = (nb + WG - 1) / WG;
+  for (int i = 1; i < levels; ++i) {
+    const int64_t s = 1ll << ((i - 1) * lg);
+    RMQ_TRY(launch(k_st_lary, dim3((unsigned)grid), dim3(WG), 0, stream,
+                   static_cast<const uint64_t*>(st + (size_t)(i - 1) * nb),
+                   st + (size_t)i * nb, nb, s, 1 << lg));
+  }
+  return hipSuccess;
+}
 
 int st_round_j0(int r) { return round_shape(r).j0; }
 

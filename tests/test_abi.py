@@ -62,6 +62,28 @@ def test_table_levels():
         [1, 1, 1, 2, 2, 3, 4, 10, 11]
 
 
+def test_table_levels_over_powers_of_l():
+    # Section 3.1 over powers of l = 2^a: level i spans l^i blocks, and the
+    # levels needed are those with l^i <= nb - 2 (the widest inner span)
+    for a in (1, 2, 3, 4, 5):
+        for nb in (1, 2, 3, 4, 5, 6, 17, 18, 19, 33, 34, 257, 258, 1025, 1026, 4099, 1 << 20,
+                   (1 << 25) + 3):
+            exp = 1
+            while nb > 3 and (1 << (exp * a)) <= nb - 2:
+                exp += 1
+            assert rmq.table_levels(nb, a) == exp, (nb, a)
+    assert rmq.table_levels(1 << 20, 4) == 5 and rmq.table_levels(18, 4) == 2
+    L = rmq.lib()
+    assert L.rmq_table_levels_ary(10, 6) == 0 and L.rmq_table_levels_ary(0, 2) == 0
+    assert L.rmq_table_levels_ary(1000, 0) == L.rmq_table_levels(1000)
+    # the table over powers of 16 takes a quarter of the doubling table's levels
+    n, q = 10 ** 8, 10 ** 7
+    two = rmq.workspace_bytes(n, q, "full", 32)
+    sixteen = rmq.workspace_bytes(n, q, "full", 32, arity_log2=4)
+    nb = -(-n // 32)
+    assert two - sixteen == 8 * nb * (rmq.table_levels(nb) - rmq.table_levels(nb, 4))
+
+
 def test_invalid_arguments_rejected_on_host():
     L = rmq.lib()
     fake = ctypes.c_void_p(256)  # never dereferenced: rejected before any device work
@@ -80,6 +102,12 @@ def test_invalid_arguments_rejected_on_host():
     o.block_size = 0
     o.path = 7
     assert L.rmq_query_batch_ex(fake, 10, fake, fake, 1, out, None, ctypes.byref(o)) == 1
+    o.path = 0
+    for a in (-1, 6):  # table arity l = 2^a outside 2..32
+        o.table_arity_log2 = a
+        assert L.rmq_query_batch_ex(fake, 10, fake, fake, 1, out, None, ctypes.byref(o)) == 1
+        h = ctypes.c_void_p()
+        assert L.rmq_build(fake, 10, ctypes.byref(o), None, ctypes.byref(h)) == 1
     assert L.rmq_index_bytes(0, 1024) == 0 and L.rmq_index_bytes(100, 1000) == 0
     assert L.rmq_workspace_bytes(10, -1, None) == 0
 
