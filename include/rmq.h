@@ -112,8 +112,14 @@ typedef struct rmq_options {
                                  blocks, there are floor(log2(nb - 2) /
                                  log2(l)) + 1 levels for nb > 3 blocks (1
                                  otherwise), and a query reads at most l of
-                                 them.  Both methods and the resident index;
-                                 not the batched calls (RMQ_ERR_INVALID_ARG). */
+                                 them.  Level i >= 1 is stored by residue
+                                 class mod s = l^i: block b's entry is at
+                                 r * floor(nb / s) + min(r, nb mod s) + b / s
+                                 with r = b mod s, so the windows one query
+                                 reads at a level are adjacent.  Both methods,
+                                 the resident index and the LCA front-end;
+                                 the batched and served calls keep the
+                                 doubling table. */
 } rmq_options;
 
 /* A human-readable name for a status code (static storage). */
@@ -196,7 +202,8 @@ rmq_status rmq_index_info(rmq_index idx, int64_t *n, int32_t *block_size, int64_
 
 /* Copy of the index's Sparse Table (level-major, levels x num_blocks uint64
  * keys; level 0 = block minima; level i spans 2^i blocks, or l^i for a table
- * over powers of l) into device memory `st`, on `stream`. */
+ * over powers of l, whose levels i >= 1 are in residue-class order -- see
+ * rmq_options.table_arity_log2) into device memory `st`, on `stream`. */
 rmq_status rmq_index_copy_table(rmq_index idx, uint64_t *st, void *stream);
 
 /* Device bytes of a resident index for (n, k): 8 * nb * levels with

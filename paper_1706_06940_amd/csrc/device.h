@@ -18,6 +18,18 @@ __device__ __forceinline__ uint32_t key_pos(uint64_t k) { return (uint32_t)k; }
 
 __device__ __forceinline__ uint64_t umin64(uint64_t a, uint64_t b) { return a < b ? a : b; }
 
+// Where block b's entry sits in a level of the table over powers of l whose
+// windows span s = 2^sh blocks: levels are stored by residue class (b mod s
+// first, then b / s), so the windows b, b + s, b + 2s, ... that a query or the
+// next level's build reads are adjacent.  Classes r < nb mod s hold one more
+// entry than the others; the map is a permutation of [0, nb).  sh = 0 is the
+// identity (level 0, the block minima).
+__host__ __device__ __forceinline__ int64_t lary_addr(int64_t b, int64_t nb, int sh) {
+  const int64_t m = (1ll << sh) - 1;
+  const int64_t r = b & m, rem = nb & m;
+  return r * (nb >> sh) + (r < rem ? r : rem) + (b >> sh);
+}
+
 // ---- DPP moves of a 64-bit value (gfx9 DPP control codes) ------------------
 enum : int {
   DPP_QUAD_XOR1 = 0xB1,        // quad_perm [1,0,3,2]

@@ -85,6 +85,7 @@ hipError_t launch_blockmin_keys(const uint64_t* S, int64_t m, int kshift, uint64
 hipError_t launch_sparse_table(uint64_t* st, int64_t nb, int levels, hipStream_t stream);
 // l-ary table (Section 3.1), l = 2^lg >= 4: level i holds the minima over
 // l^i blocks (truncated at nb); levels = lary_levels(nb, lg).  Level 0 given.
+// Levels i >= 1 are stored by residue class mod l^i (lary_addr in device.h).
 int lary_levels(int64_t nb, int lg);
 hipError_t launch_sparse_table_lary(uint64_t* st, int64_t nb, int lg, hipStream_t stream);
 int64_t blockmin_grid(int64_t n, int kshift, int elems_per_lane_load);

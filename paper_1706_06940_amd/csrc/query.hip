@@ -273,15 +273,17 @@ __device__ __forceinline__ void query_core(const Src& src, int64_t src_len, int6
           best = umin64(lev[bl + 1], lev[br - (1ll << t)]);
         } else {
           // l-ary table (Section 3.1), l = 2^lg: level i holds windows of
-          // l^i blocks; whole windows from the left, then one ending at the
-          // last inner block -- at most l of them
-          const int i = t / lg;
-          const int64_t span = 1ll << (i * lg);
-          const uint64_t* lev = st + (size_t)i * nb;
-          const int64_t whole = inner / span;
+          // s = l^i blocks; whole windows from the left, then one ending at
+          // the last inner block -- at most l of them.  The whole windows
+          // share a residue class mod s, so they are adjacent entries.
+          const int sh = (t / lg) * lg;
+          const uint64_t* lev = st + (size_t)(t / lg) * nb;
+          const int64_t whole = inner >> sh;
+          const uint64_t* w = lev + lary_addr(bl + 1, nb, sh);
 #pragma unroll 8
-          for (int64_t j = 0; j < whole; ++j) best = umin64(best, lev[bl + 1 + j * span]);
-          if (whole * span < inner) best = umin64(best, lev[br - span]);
+          for (int64_t j = 0; j < whole; ++j) best = umin64(best, w[j]);
+          if (inner & ((1ll << sh) - 1))
+            best = umin64(best, lev[lary_addr(br - (1ll << sh), nb, sh)]);
         }
       }
       kr = st[br];

@@ -136,23 +136,95 @@ __global__ __launch_bounds__(WG) void k_st_multi(const ArrayDesc* __restrict__ i
   st_tile(d.st, d.nb, j0, t, R, col_tiles, blockIdx.x - tile_prefix[j], lds);
 }
 
+// Division of a < 2^31 by a divisor fixed for the launch, d >= 1: with
+// e = ceil(log2 d) and m = ceil(2^(31+e) / d) < 2^32, floor(a / d) =
+// (a * m) >> (31 + e) (the round-up method of Granlund and Montgomery).
+struct Divisor {
+  uint32_t d, m;
+  int shift;
+};
+Divisor make_divisor(uint32_t d) {
+  int e = 0;
+  while ((1ull << e) < d) ++e;
+  const unsigned __int128 num = (unsigned __int128)1 << (31 + e);
+  return Divisor{d, (uint32_t)((num + d - 1) / d), 31 + e};
+}
+__device__ __forceinline__ uint32_t div_by(uint32_t a, const Divisor& v) {
+  return (uint32_t)(((uint64_t)a * v.m) >> v.shift);
+}
+
+// Block b of the a-th stored entry of a level whose windows span 2^sh blocks:
+// b = p * 2^sh + r for the p-th entry of class r; the first nb mod 2^sh
+// classes (`long_cls.d` = base + 1 entries each) come before the others
+// (`short_cls.d` = base entries each).  Also the class length.
+__device__ __forceinline__ int64_t lary_block(uint32_t a, uint32_t nb, int sh,
+                                              const Divisor& long_cls, const Divisor& short_cls,
+                                              uint32_t* p_out = nullptr,
+                                              uint32_t* len_out = nullptr) {
+  const uint32_t rem = nb & ((1u << sh) - 1), big = rem * long_cls.d;
+  uint32_t r, p, len;
+  if (a < big) {
+    r = div_by(a, long_cls);
+    p = a - r * long_cls.d;
+    len = long_cls.d;
+  } else {
+    const uint32_t c = div_by(a - big, short_cls);
+    r = rem + c;
+    p = a - big - c * short_cls.d;
+    len = short_cls.d;
+  }
+  if (p_out) *p_out = p;
+  if (len_out) *len_out = len;
+  return ((int64_t)p << sh) + r;
+}
+
+constexpr int LARY_TILE = 1024;  // entries of level i-1 per workgroup
+
 // One level of the table over powers of l = 2^lg (Section 3.1): level i at
-// block b is the min of level i-1 at b, b + s, ..., b + (l-1)s with
-// s = l^(i-1), entries past the last block left out (truncated spans, as in
-// the doubling table).  Consecutive threads take consecutive b, so each of
-// the l reads is a coalesced row; rows that neighbouring workgroups share
-// come from L2.
+// block b is the min of level i-1 at b, b + s', ..., b + (l-1)s' with
+// s' = l^(i-1), entries past the last block left out (truncated spans, as in
+// the doubling table).  Level i-1 is stored by residue class mod s'
+// (lary_addr), so these terms are l adjacent entries of one class: a window
+// of width l sliding along the class, cut at the class's end.  A workgroup
+// stages LARY_TILE consecutive entries of level i-1 plus the l - 1 after
+// them in LDS (each entry read once from HBM) and makes the window minimum
+// starting at each of its entries, written to block b's place in level i
+// (within a wave: l classes of level i, adjacent positions in each).
 __global__ __launch_bounds__(WG) void k_st_lary(const uint64_t* __restrict__ prev,
-                                                uint64_t* __restrict__ cur, int64_t nb,
-                                                int64_t s, int l) {
-  const int64_t b = (int64_t)blockIdx.x * WG + threadIdx.x;
-  if (b >= nb) return;
-  const int64_t avail = (nb - 1 - b) / s + 1;  // terms with b + j s < nb
-  const int cnt = avail < l ? (int)avail : l;
-  uint64_t m = prev[b];
+                                                uint64_t* __restrict__ cur, uint32_t nb, int sh,
+                                                int lg, Divisor long_cls, Divisor short_cls) {
+  __shared__ uint64_t tile[LARY_TILE + 32];
+  constexpr int LOADS = (LARY_TILE + 32 + WG - 1) / WG;
+  const int l = 1 << lg;
+  const int psh = sh - lg;
+  const int64_t x0 = (int64_t)blockIdx.x * LARY_TILE;
+  uint64_t v[LOADS];
+#pragma unroll
+  for (int u = 0; u < LOADS; ++u) {
+    const int64_t x = x0 + u * WG + threadIdx.x;
+    v[u] = prev[x < (int64_t)nb ? x : 0];
+    if (x >= (int64_t)nb) v[u] = KEY_NONE;
+  }
+#pragma unroll
+  for (int u = 0; u < LOADS; ++u) {
+    const int idx = u * WG + threadIdx.x;
+    if (idx < LARY_TILE + l - 1) tile[idx] = v[u];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < LARY_TILE / WG; ++u) {
+    const int idx = u * WG + threadIdx.x;
+    const int64_t x = x0 + idx;
+    if (x >= (int64_t)nb) break;
+    // entry x of level i-1: block b, p-th of its class, class length len
+    uint32_t p, len;
+    const int64_t b = lary_block((uint32_t)x, nb, psh, long_cls, short_cls, &p, &len);
+    const int cnt = (int)(len - p) < l ? (int)(len - p) : l;  // terms inside the class
+    uint64_t m = tile[idx];
 #pragma unroll 8
-  for (int j = 1; j < cnt; ++j) m = umin64(m, prev[b + j * s]);
-  cur[b] = m;
+    for (int j = 1; j < cnt; ++j) m = umin64(m, tile[idx + j]);
+    cur[lary_addr(b, nb, sh)] = m;
+  }
 }
 
 }  // namespace
@@ -166,12 +238,15 @@ int lary_levels(int64_t nb, int lg) {
 
 hipError_t launch_sparse_table_lary(uint64_t* st, int64_t nb, int lg, hipStream_t stream) {
   const int levels = lary_levels(nb, lg);
-  const int64_t grid = (nb + WG - 1) / WG;
+  if (nb >= ((int64_t)1 << 31)) return hipErrorInvalidValue;  // 32-bit index math
+  const int64_t grid = (nb + LARY_TILE - 1) / LARY_TILE;
   for (int i = 1; i < levels; ++i) {
-    const int64_t s = 1ll << ((i - 1) * lg);
+    // classes of level i-1 (mod l^(i-1)): base or base + 1 entries, base >= 1
+    const uint32_t base = (uint32_t)(nb >> ((i - 1) * lg));
     RMQ_TRY(launch(k_st_lary, dim3((unsigned)grid), dim3(WG), 0, stream,
                    static_cast<const uint64_t*>(st + (size_t)(i - 1) * nb),
-                   st + (size_t)i * nb, nb, s, 1 << lg));
+                   st + (size_t)i * nb, (uint32_t)nb, i * lg, lg, make_divisor(base + 1),
+                   make_divisor(base)));
   }
   return hipSuccess;
 }
