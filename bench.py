@@ -69,6 +69,8 @@ def main() -> int:
                     help="skip the LCA front-end measurement (5e8-node tree)")
     ap.add_argument("--no-skewed", action="store_true",
                     help="skip the n = 1e9 skewed-query measurement")
+    ap.add_argument("--no-lary", action="store_true",
+                    help="skip the table-over-powers-of-l measurement")
     ap.add_argument("--no-resident", action="store_true",
                     help="skip the resident-index query-only measurement")
     ap.add_argument("--blockmin-sweep", default="",
@@ -287,6 +289,7 @@ def main() -> int:
     torch.cuda.empty_cache()
     skewed = None if args.no_skewed else bench_skewed(d)
     lca = None if args.no_lca else bench_lca(d)
+    lary = None if args.no_lary else bench_lary(d)
     batched = None if args.no_batched else bench_batched(d)
     served = None if args.no_served else bench_served(d, args.served_requests)
 
@@ -302,7 +305,7 @@ def main() -> int:
                    "block_size": {p: k_used[p] for p in paths},
                    "parallelism": "single GPU"},
         "roofline": roofline, "cpu_baseline": cpu, "breakdown": breakdown,
-        "resident": resident, "skewed": skewed, "lca": lca,
+        "resident": resident, "skewed": skewed, "lca": lca, "lary": lary,
         "batched": batched, "served": served,
     }
     print(json.dumps(line), flush=True)
@@ -389,6 +392,49 @@ def bench_skewed(d, reps=5):
     torch.cuda.empty_cache()
     return {"workload": "n=1e9 int32 uniform in [0,2^31), q=1e7: 5e6 short ranges (length "
                         "uniform in [1,1024]) and 5e6 uniform long ranges, shuffled",
+            "results": res}
+
+
+def bench_lary(d, reps=5):
+    """The block table over powers of l = 2^a instead of 2 (Section 3.1's
+    generalisation) against the doubling table (a = 1) on the plain method:
+    n = 1e8 uniform int32, q = 1e7 uniform queries, small blocks (where the
+    table is large).  Whole offline jobs and resident-index queries (mean of
+    `reps`), and the table's bytes."""
+    import torch
+
+    import paper_1706_06940_amd as rmq
+    import workloads as W
+
+    n, q = 10 ** 8, 10 ** 7
+    seed = W.BASE_SEED + 5
+    A = W.uniform_int31_torch(n, seed, 0, device=d)
+    L, R = W.uniform_queries_torch(n, q, seed, 1, device=d)
+    out = torch.empty(q, dtype=torch.int32, device=d)
+    stream = torch.cuda.current_stream(d)
+    res = {}
+    for k in (32, 256):
+        ref = None
+        for a in (1, 2, 4, 5):
+            ws = torch.empty(rmq.workspace_bytes(n, q, "full", k, arity_log2=a),
+                             dtype=torch.uint8, device=d)
+            job = lambda: rmq.query_batch(A, L, R, path="full", block_size=k, arity_log2=a,
+                                          out=out, workspace=ws)
+            job_ms = time_runs(job, stream, warmup=1, reps=reps)
+            got = out.clone()
+            ref = got if ref is None else ref
+            idx = rmq.Index(A, k, arity_log2=a)
+            q_ms = time_runs(lambda: idx.query(L, R, out=out), stream, warmup=1, reps=reps)
+            res[f"k={k}/l={2 ** a}"] = {
+                "levels": idx.levels, "table_bytes": idx.bytes, "job_ms": round(job_ms, 4),
+                "index_query_ms": round(q_ms, 4),
+                "same_answers_as_doubling": bool(torch.equal(got, ref))}
+            del idx, ws
+            print(f"[bench] lary k={k} l={2 ** a}: job {job_ms:.3f} ms, index query "
+                  f"{q_ms:.3f} ms", file=sys.stderr, flush=True)
+    del A, L, R, out
+    torch.cuda.empty_cache()
+    return {"workload": "n=1e8 int32 uniform in [0,2^31), q=1e7 uniform queries, plain method",
             "results": res}
 
 
