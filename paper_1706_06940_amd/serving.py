@@ -50,6 +50,14 @@ class _Spec(ctypes.Structure):
                 ("out", ctypes.c_void_p), ("t_arrival", ctypes.c_double)]
 
 
+# rmq_request_spec as a numpy record (same offsets as _Spec), so that a whole
+# schedule's arrival times are set in one vector operation
+_SPEC_DTYPE = np.dtype([("table_id", "<i4"), ("reserved", "<i4"), ("L", "<u8"), ("R", "<u8"),
+                        ("q", "<i8"), ("out", "<u8"), ("t_arrival", "<f8")])
+assert _SPEC_DTYPE.itemsize == ctypes.sizeof(_Spec) and all(
+    _SPEC_DTYPE.fields[f][1] == getattr(_Spec, f).offset for f, _ in _Spec._fields_)
+
+
 _SIGS_DONE = False
 
 
@@ -112,22 +120,30 @@ class Server:
         self._keep[t.value] = (L, R, out)
         return t.value
 
-    def submit_schedule(self, requests, arrivals) -> list:
-        """requests: list of (table, L, R, out); arrivals: server-clock times."""
+    def submit_schedule(self, requests, arrivals, lead_s: float = 1e-3):
+        """requests: list of (table, L, R, out); arrivals: server-clock times.
+        The request table is built first; if that took the schedule's start
+        closer than lead_s to now, the whole schedule is shifted later by the
+        same amount (gaps unchanged), so that no request is submitted behind
+        its arrival time because of this set-up.  Returns the tickets and the
+        arrival times used."""
         n = len(requests)
-        specs = (_Spec * max(n, 1))()
-        for i, ((tab, L, R, out), ta) in enumerate(zip(requests, arrivals)):
+        specs = np.zeros(max(n, 1), dtype=_SPEC_DTYPE)
+        for i, (tab, L, R, out) in enumerate(requests):
             L, R, out = _host_i32(L, "L"), _host_i32(R, "R"), _host_i32(out, "out")
-            specs[i] = _Spec(int(tab), 0, L.ctypes.data, R.ctypes.data, L.shape[0],
-                             out.ctypes.data, float(ta))
-        tickets = (ctypes.c_uint64 * max(n, 1))()
+            specs[i] = (int(tab), 0, L.ctypes.data, R.ctypes.data, L.shape[0], out.ctypes.data, 0.0)
+        arr = np.array(arrivals, dtype=np.float64)
+        if n:
+            arr += max(0.0, clock() + lead_s - float(arr.min()))
+            specs["t_arrival"][:n] = arr
+        tickets = np.zeros(max(n, 1), dtype=np.uint64)
         _check("rmq_server_submit_schedule",
-               _lib().rmq_server_submit_schedule(self.handle, n, specs, tickets))
-        out = []
-        for i in range(n):
-            self._keep[tickets[i]] = requests[i]
-            out.append(int(tickets[i]))
-        return out
+               _lib().rmq_server_submit_schedule(self.handle, n, specs.ctypes.data,
+                                                 tickets.ctypes.data))
+        out = [int(t) for t in tickets[:n]]
+        for t, r in zip(out, requests):
+            self._keep[t] = r
+        return out, arr
 
     def wait(self, ticket: int) -> dict:
         info = _Info()
@@ -175,27 +191,33 @@ class RunResult:
     queries: int
     makespan_s: float
     mean_batch_requests: float
+    queued_s: np.ndarray = None  # arrival -> launch of the request's batch
 
     def summary(self) -> dict:
         lat = self.latencies_s
-        return {"requests": int(lat.shape[0]), "queries": int(self.queries),
-                "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 4),
-                "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 4),
-                "mean_ms": round(float(lat.mean()) * 1e3, 4),
-                "queries_per_s": round(self.queries / self.makespan_s, 1),
-                "mean_requests_per_batch": round(self.mean_batch_requests, 2)}
+        out = {"requests": int(lat.shape[0]), "queries": int(self.queries),
+               "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 4),
+               "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 4),
+               "max_ms": round(float(lat.max()) * 1e3, 4),
+               "mean_ms": round(float(lat.mean()) * 1e3, 4),
+               "queries_per_s": round(self.queries / self.makespan_s, 1),
+               "mean_requests_per_batch": round(self.mean_batch_requests, 2)}
+        if self.queued_s is not None:
+            out["queued_p99_ms"] = round(float(np.percentile(self.queued_s, 99)) * 1e3, 4)
+        return out
 
 
 def run_schedule(server: Server, requests, arrivals) -> RunResult:
     """Submit each request at its arrival time, wait for all; latency =
-    completion - arrival."""
-    tickets = server.submit_schedule(requests, arrivals)
+    completion - arrival (the schedule shifted as a whole past the set-up of
+    its request table, see Server.submit_schedule)."""
+    tickets, arr = server.submit_schedule(requests, arrivals)
     infos = [server.wait(t) for t in tickets]
     done = np.array([i["t_done"] for i in infos])
-    arr = np.asarray(arrivals, dtype=np.float64)
+    launch = np.array([i["t_launch"] for i in infos])
     q = sum(int(r[1].shape[0]) for r in requests)
     return RunResult(done - arr, q, float(done.max() - arr.min()),
-                     float(np.mean([i["batch_requests"] for i in infos])))
+                     float(np.mean([i["batch_requests"] for i in infos])), launch - arr)
 
 
 def make_requests(ns, count: int, q_lo: float, q_hi: float, seed: int):
