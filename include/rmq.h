@@ -120,6 +120,17 @@ typedef struct rmq_options {
                                  the resident index and the LCA front-end;
                                  the batched and served calls keep the
                                  doubling table. */
+    int32_t no_query_records; /* nonzero: do not build query records.  By
+                                 default a doubling table of nb blocks and L
+                                 levels also gets, when 32 * nb * L bytes <=
+                                 32 MiB, two records per block: for every
+                                 level t, the block's minimum paired with the
+                                 window of 2^t blocks starting just after it,
+                                 and paired with the window ending just
+                                 before it (16-byte pairs).  A query then
+                                 reads each end block's key and the window
+                                 beside it with one 16-byte load instead of
+                                 two 8-byte ones.  Same answers either way. */
 } rmq_options;
 
 /* A human-readable name for a status code (static storage). */
@@ -196,7 +207,9 @@ rmq_status rmq_query_index_ex(rmq_index idx, const int32_t *L, const int32_t *R,
 rmq_status rmq_index_free(rmq_index idx);
 
 /* Facts about an index (any output pointer may be NULL).  bytes counts the
- * table and, for a two-level index, the k1-block minima (8 * ceil(n / k1)). */
+ * device memory the index holds: the table, for a two-level index the
+ * k1-block minima (8 * ceil(n / k1)), and its query records if it has them
+ * (rmq_options.no_query_records). */
 rmq_status rmq_index_info(rmq_index idx, int64_t *n, int32_t *block_size, int64_t *num_blocks,
                           int32_t *levels, size_t *bytes);
 
@@ -214,6 +227,10 @@ size_t rmq_index_bytes(int64_t n, int32_t block_size);
 
 /* Number of Sparse Table levels for nb blocks (see rmq_index_bytes). */
 int32_t rmq_table_levels(int64_t num_blocks);
+
+/* Bytes of the query records built beside a doubling table of nb blocks
+ * (see rmq_options.no_query_records); 0 when none are built. */
+size_t rmq_query_record_bytes(int64_t num_blocks);
 
 /* Levels of the table over powers of l = 2^table_arity_log2 (Section 3.1;
  * see rmq_options.table_arity_log2) for nb blocks; 0 on invalid arguments.

@@ -50,6 +50,7 @@ class _Options(ctypes.Structure):
         ("timer", ctypes.c_void_p),
         ("sub_block_size", ctypes.c_int32),
         ("table_arity_log2", ctypes.c_int32),
+        ("no_query_records", ctypes.c_int32),
     ]
 
 
@@ -91,6 +92,7 @@ def lib() -> ctypes.CDLL:
         "rmq_index_bytes": ([i64, i32], sz),
         "rmq_table_levels": ([i64], i32),
         "rmq_table_levels_ary": ([i64, i32], i32),
+        "rmq_query_record_bytes": ([i64], sz),
         "rmq_block_minima": ([v, i64, i32, v, v], i32),
         "rmq_block_minima_keys": ([v, i64, i32, v, v], i32),
         "rmq_sparse_table_build": ([v, i64, i32, v], i32),
@@ -164,8 +166,9 @@ class Timer:
 
 def _options(block_size=0, path="auto", bad_count=None, stats=None, workspace=None,
              timer: Optional[Timer] = None, sub_block_size: int = 0,
-             arity_log2: int = 0) -> _Options:
+             arity_log2: int = 0, records: bool = True) -> _Options:
     o = _Options()
+    o.no_query_records = 0 if records else 1
     o.block_size = int(block_size)
     o.sub_block_size = int(sub_block_size)
     o.table_arity_log2 = int(arity_log2)
@@ -234,13 +237,20 @@ def default_block(n: int, q: int, path: str) -> int:
 
 
 def workspace_bytes(n: int, q: int, path="auto", block_size: int = 0,
-                    sub_block_size: int = 0, arity_log2: int = 0) -> int:
-    o = _options(block_size, path, sub_block_size=sub_block_size, arity_log2=arity_log2)
+                    sub_block_size: int = 0, arity_log2: int = 0, records: bool = True) -> int:
+    o = _options(block_size, path, sub_block_size=sub_block_size, arity_log2=arity_log2,
+                 records=records)
     return int(lib().rmq_workspace_bytes(n, q, ctypes.byref(o)))
 
 
 def index_bytes(n: int, block_size: int) -> int:
     return int(lib().rmq_index_bytes(n, block_size))
+
+
+def query_record_bytes(num_blocks: int) -> int:
+    """Bytes of the query records kept beside a doubling table of
+    num_blocks blocks (0 if none)."""
+    return int(lib().rmq_query_record_bytes(num_blocks))
 
 
 def table_levels(num_blocks: int, arity_log2: int = 0) -> int:
@@ -254,7 +264,7 @@ def table_levels(num_blocks: int, arity_log2: int = 0) -> int:
 def query_batch(A: torch.Tensor, L: torch.Tensor, R: torch.Tensor, *, path="auto",
                 block_size: int = 0, sub_block_size: int = 0, arity_log2: int = 0,
                 out: Optional[torch.Tensor] = None, bad_count=None, stats=None, workspace=None,
-                timer: Optional[Timer] = None, stream=None) -> torch.Tensor:
+                timer: Optional[Timer] = None, stream=None, records: bool = True) -> torch.Tensor:
     """Answer all queries of one offline batch (Section 1); returns int32 out.
     sub_block_size > 0 selects two block levels (Section 3.3) on the plain
     method; arity_log2 in 2..5 builds the block table over powers of
@@ -265,7 +275,7 @@ def query_batch(A: torch.Tensor, L: torch.Tensor, R: torch.Tensor, *, path="auto
     if out is None:
         out = torch.empty(q, dtype=torch.int32, device=A.device)
     o = _options(block_size, path, bad_count, stats, workspace, timer, sub_block_size,
-                 arity_log2)
+                 arity_log2, records)
     st = lib().rmq_query_batch_ex(_dev_i32(A, "A"), n, _dev_i32(L, "L") if q else None,
                                   _dev_i32(R, "R") if q else None, q,
                                   _dev_i32(out, "out") if q else None,
@@ -281,9 +291,10 @@ class Index:
     3.1).  Keeps a reference to A, which partial-block scans read."""
 
     def __init__(self, A: torch.Tensor, block_size: int = 0, stream=None,
-                 sub_block_size: int = 0, arity_log2: int = 0):
+                 sub_block_size: int = 0, arity_log2: int = 0, records: bool = True):
         h = ctypes.c_void_p()
-        o = _options(block_size, "full", sub_block_size=sub_block_size, arity_log2=arity_log2)
+        o = _options(block_size, "full", sub_block_size=sub_block_size, arity_log2=arity_log2,
+                     records=records)
         _check("rmq_build", lib().rmq_build(_dev_i32(A, "A"), A.numel(), ctypes.byref(o),
                                             _stream(A.device, stream), ctypes.byref(h)))
         self.handle = h
@@ -397,9 +408,10 @@ class LCA:
     RMQ index over its depths, built on the device."""
 
     def __init__(self, parent: torch.Tensor, block_size: int = 0, sub_block_size: int = 0,
-                 stream=None, arity_log2: int = 0):
+                 stream=None, arity_log2: int = 0, records: bool = True):
         h = ctypes.c_void_p()
-        o = _options(block_size, "full", sub_block_size=sub_block_size, arity_log2=arity_log2)
+        o = _options(block_size, "full", sub_block_size=sub_block_size, arity_log2=arity_log2,
+                     records=records)
         _check("rmq_lca_build", lib().rmq_lca_build(_dev_i32(parent, "parent"), parent.numel(),
                                                     ctypes.byref(o),
                                                     _stream(parent.device, stream),

@@ -74,7 +74,17 @@ struct Plan {
   int kshift;
   int k1shift;  // two block levels (Section 3.3): k1 = 2^k1shift; -1 = one level
   int lg;       // table over powers of l = 2^lg (Section 3.1); 1 = doubling
+  bool records;  // query records allowed (opt->no_query_records == 0)
 };
+
+// Query records (see launch_records) for a doubling table of nb blocks and
+// `levels` levels: whether they are built (not for another arity, nor above
+// kMaxRecordBytes), and their bytes.
+constexpr size_t kMaxRecordBytes = 32u << 20;
+size_t records_bytes(int64_t nb, int levels) { return sizeof(uint64_t) * 4 * (size_t)nb * levels; }
+bool records_built(int64_t nb, int levels, int lg, bool allowed) {
+  return allowed && lg <= 1 && records_bytes(nb, levels) <= kMaxRecordBytes;
+}
 
 // opt->table_arity_log2 as lg (0 and 1 both mean doubling); -1 if invalid.
 int arity_lg(const rmq_options* opt) {
@@ -105,6 +115,7 @@ rmq_status make_plan(int64_t n, int64_t q, const rmq_options* opt, Plan* p) {
   p->k1shift = -1;
   p->lg = arity_lg(opt);
   if (p->lg < 0) return RMQ_ERR_INVALID_ARG;
+  p->records = !(opt && opt->no_query_records);
   if (k1 != 0) {
     // two block levels: the plain method with k1 < k
     if (!is_pow2_block(k1) || path == RMQ_PATH_CONTRACTED) return RMQ_ERR_INVALID_ARG;
@@ -133,33 +144,38 @@ rmq_status make_plan(int64_t n, int64_t q, const rmq_options* opt, Plan* p) {
 struct FullLayout {
   int64_t nb, nb1;
   int levels;
-  size_t off_st, off_sub, bytes;
+  bool rec;  // query records built
+  size_t off_st, off_sub, off_rec, bytes;
 };
 
 // The table, then (two block levels) the k1-block minima.
-FullLayout full_layout(int64_t n, int64_t k, int k1shift, int lg) {
+FullLayout full_layout(int64_t n, int64_t k, int k1shift, int lg, bool records) {
   FullLayout f{};
   f.nb = num_blocks(n, k);
   f.levels = table_levels(f.nb, lg);
+  f.rec = records_built(f.nb, f.levels, lg, records);
   f.off_st = 0;
   f.off_sub = align_up(sizeof(uint64_t) * (size_t)f.nb * (size_t)f.levels);
   f.nb1 = k1shift >= 0 ? num_blocks(n, 1ll << k1shift) : 0;
-  f.bytes = f.off_sub + align_up(sizeof(uint64_t) * (size_t)f.nb1);
+  f.off_rec = f.off_sub + align_up(sizeof(uint64_t) * (size_t)f.nb1);
+  f.bytes = f.off_rec + (f.rec ? align_up(records_bytes(f.nb, f.levels)) : 0);
   return f;
 }
 
 struct ConLayout {
   int64_t M, m, nb;
   int levels;
-  size_t off_E, off_sort, off_lr, off_aq, off_tiles, off_st, bytes;
+  bool rec;  // query records built
+  size_t off_E, off_sort, off_lr, off_aq, off_tiles, off_st, off_rec, bytes;
 };
 
-ConLayout con_layout(int64_t n, int64_t q, int64_t k, int lg) {
+ConLayout con_layout(int64_t n, int64_t q, int64_t k, int lg, bool records) {
   ConLayout c{};
   c.M = 2 * q;
   c.m = c.M - 1;
   c.nb = num_blocks(c.m, k);
   c.levels = table_levels(c.nb, lg);
+  c.rec = records_built(c.nb, c.levels, lg, records);
   size_t o = 0;
   c.off_E = o;
   o = align_up(o + sizeof(uint64_t) * (size_t)c.M);
@@ -173,13 +189,15 @@ ConLayout con_layout(int64_t n, int64_t q, int64_t k, int lg) {
   o = align_up(o + contract_tile_start_bytes(n));
   c.off_st = o;
   o = align_up(o + sizeof(uint64_t) * (size_t)c.nb * (size_t)c.levels);
+  c.off_rec = o;
+  o = align_up(o + (c.rec ? records_bytes(c.nb, c.levels) : 0));
   c.bytes = o;
   return c;
 }
 
 size_t plan_bytes(int64_t n, int64_t q, const Plan& p) {
-  if (p.path == RMQ_PATH_FULL) return full_layout(n, p.k, p.k1shift, p.lg).bytes;
-  return con_layout(n, q, p.k, p.lg).bytes;
+  if (p.path == RMQ_PATH_FULL) return full_layout(n, p.k, p.k1shift, p.lg, p.records).bytes;
+  return con_layout(n, q, p.k, p.lg, p.records).bytes;
 }
 
 std::once_flag g_pool_once[64];
@@ -240,9 +258,10 @@ rmq_status run_full(const int32_t* A, int64_t n, const int32_t* L, const int32_t
   rmq_timer* t = opt ? opt->timer : nullptr;
   ClockGuard guard;
   if (t) t->ran[0] = false;  // no sort stage on this path
-  const FullLayout f = full_layout(n, p.k, p.k1shift, p.lg);
+  const FullLayout f = full_layout(n, p.k, p.k1shift, p.lg, p.records);
   uint64_t* st = reinterpret_cast<uint64_t*>(ws + f.off_st);
   uint64_t* sub = reinterpret_cast<uint64_t*>(ws + f.off_sub);
+  uint64_t* rec = f.rec ? reinterpret_cast<uint64_t*>(ws + f.off_rec) : nullptr;
   const bool two = p.k1shift >= 0;
   stage_begin(t, 1);
   hipError_t e;
@@ -257,14 +276,16 @@ rmq_status run_full(const int32_t* A, int64_t n, const int32_t* L, const int32_t
   stage_end(t, 1, s);
   stage_begin(t, 2);
   e = build_table(st, f.nb, f.levels, p.lg, s);
+  if (e == hipSuccess && rec) e = launch_records(st, f.nb, f.levels, rec, s);
   if (e != hipSuccess) return from_hip(e);
   stage_end(t, 2, s);
   stage_begin(t, 3);
   int64_t* bad = opt ? opt->bad_count : nullptr;
   uint64_t* stats = opt ? opt->stats : nullptr;
   e = two ? launch_query_full2(A, n, p.kshift, st, f.nb, sub, p.k1shift, L, R, q, out, bad, stats,
-                               s, p.lg)
-          : launch_query_full(A, n, p.kshift, st, f.nb, L, R, q, out, bad, stats, s, p.lg);
+                               s, p.lg, rec, f.levels)
+          : launch_query_full(A, n, p.kshift, st, f.nb, L, R, q, out, bad, stats, s, p.lg, rec,
+                              f.levels);
   if (e != hipSuccess) return from_hip(e);
   stage_end(t, 3, s);
   return RMQ_OK;
@@ -274,8 +295,9 @@ rmq_status run_contracted(const int32_t* A, int64_t n, const int32_t* L, const i
                           int64_t q, int32_t* out, hipStream_t s, const rmq_options* opt,
                           const Plan& p, char* ws) {
   rmq_timer* t = opt ? opt->timer : nullptr;
-  const ConLayout c = con_layout(n, q, p.k, p.lg);
+  const ConLayout c = con_layout(n, q, p.k, p.lg, p.records);
   uint64_t* E = reinterpret_cast<uint64_t*>(ws + c.off_E);
+  uint64_t* rec = c.rec ? reinterpret_cast<uint64_t*>(ws + c.off_rec) : nullptr;
   int32_t* LR = reinterpret_cast<int32_t*>(ws + c.off_lr);
   uint64_t* aq = reinterpret_cast<uint64_t*>(ws + c.off_aq);
   int32_t* tiles = reinterpret_cast<int32_t*>(ws + c.off_tiles);
@@ -295,12 +317,13 @@ rmq_status run_contracted(const int32_t* A, int64_t n, const int32_t* L, const i
   e = launch_blockmin_keys(aq, c.m, p.kshift, st, s);
   if (e != hipSuccess) return from_hip(e);
   e = build_table(st, c.nb, c.levels, p.lg, s);
+  if (e == hipSuccess && rec) e = launch_records(st, c.nb, c.levels, rec, s);
   if (e != hipSuccess) return from_hip(e);
   stage_end(t, 2, s);
   stage_begin(t, 3);
   e = launch_query_contracted(aq, c.m, n, p.kshift, st, c.nb, L, R, LR, q, out,
                               opt ? opt->bad_count : nullptr, opt ? opt->stats : nullptr, s,
-                              p.lg);
+                              p.lg, rec, c.levels);
   if (e != hipSuccess) return from_hip(e);
   stage_end(t, 3, s);
   return RMQ_OK;
@@ -327,6 +350,12 @@ const char* rmq_version(void) { return "rmq-gfx950 1.0"; }
 int32_t rmq_table_levels(int64_t nb) {
   if (nb <= 3) return 1;
   return ilog2_i64(nb - 2) + 1;
+}
+
+size_t rmq_query_record_bytes(int64_t nb) {
+  if (nb < 1 || nb > RMQ_MAX_N) return 0;
+  const int lv = rmq_table_levels(nb);
+  return records_built(nb, lv, 1, true) ? records_bytes(nb, lv) : 0;
 }
 
 int32_t rmq_table_levels_ary(int64_t nb, int32_t table_arity_log2) {
@@ -466,8 +495,12 @@ rmq_status rmq_build(const int32_t* A, int64_t n, const rmq_options* opt, void* 
   ix->levels = table_levels(ix->nb, lg);
   ix->k1shift = k1 != 0 ? ilog2_i64(k1) : -1;
   ix->nb1 = k1 != 0 ? num_blocks(n, k1) : 0;
+  const bool with_rec = records_built(ix->nb, ix->levels, lg, !(opt && opt->no_query_records));
   const size_t table_bytes = sizeof(uint64_t) * (size_t)ix->nb * (size_t)ix->levels;
-  ix->bytes = table_bytes + sizeof(uint64_t) * (size_t)ix->nb1;
+  const size_t sub_bytes = sizeof(uint64_t) * (size_t)ix->nb1;
+  // the records start on a 256-byte boundary, so that each is whole lines
+  const size_t off_rec = align_up(table_bytes + sub_bytes);
+  ix->bytes = with_rec ? off_rec + records_bytes(ix->nb, ix->levels) : table_bytes + sub_bytes;
   void* mem = nullptr;
   hipError_t e = hipMalloc(&mem, ix->bytes);
   if (e != hipSuccess) {
@@ -476,6 +509,7 @@ rmq_status rmq_build(const int32_t* A, int64_t n, const rmq_options* opt, void* 
   }
   ix->st = static_cast<uint64_t*>(mem);
   ix->sub = k1 != 0 ? ix->st + (size_t)ix->nb * (size_t)ix->levels : nullptr;
+  ix->rec = with_rec ? reinterpret_cast<uint64_t*>(static_cast<char*>(mem) + off_rec) : nullptr;
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (ix->sub) {
     // Section 3.3: k1-block minima, then the k-block minima from them
@@ -486,6 +520,7 @@ rmq_status rmq_build(const int32_t* A, int64_t n, const rmq_options* opt, void* 
     e = launch_blockmin_i32(A, n, ix->kshift, ix->st, s);
   }
   if (e == hipSuccess) e = build_table(ix->st, ix->nb, ix->levels, ix->lg, s);
+  if (e == hipSuccess && ix->rec) e = launch_records(ix->st, ix->nb, ix->levels, ix->rec, s);
   if (e != hipSuccess) {
     hipFree(mem);
     free(ix);
@@ -507,9 +542,10 @@ rmq_status rmq_query_index_ex(rmq_index idx, const int32_t* L, const int32_t* R,
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e =
       idx->sub ? launch_query_full2(idx->A, idx->n, idx->kshift, idx->st, idx->nb, idx->sub,
-                                    idx->k1shift, L, R, q, out, bad, stats, s, idx->lg)
+                                    idx->k1shift, L, R, q, out, bad, stats, s, idx->lg, idx->rec,
+                                    idx->levels)
                : launch_query_full(idx->A, idx->n, idx->kshift, idx->st, idx->nb, L, R, q, out,
-                                   bad, stats, s, idx->lg);
+                                   bad, stats, s, idx->lg, idx->rec, idx->levels);
   return from_hip(e);
 }
 
@@ -759,6 +795,7 @@ rmq_status rmq_batch_create(const rmq_batch_item* items, int32_t count, rmq_batc
       delete b;
       return st;
     }
+    b->plans[i].records = false;  // the batched kernels read the level-major table
     b->ws_off[i] = off;
     off = align_up(off + plan_bytes(items[i].n, items[i].q, b->plans[i]));
     if (b->plans[i].path == RMQ_PATH_FULL) b->full_items.push_back(i);
@@ -773,9 +810,9 @@ rmq_status rmq_batch_create(const rmq_batch_item* items, int32_t count, rmq_batc
   for (int c = 0; c < cnt; ++c) {
     const int i = b->full_items[c];
     const rmq_batch_item& it = items[i];
-    const FullLayout f = full_layout(it.n, b->plans[i].k, -1, 1);
+    const FullLayout f = full_layout(it.n, b->plans[i].k, -1, 1, false);
     desc[c] = ArrayDesc{it.A, it.n, b->plans[i].kshift, f.levels, f.nb, nullptr,
-                        it.L, it.R, it.q, it.out, 1};
+                        it.L, it.R, it.q, it.out, 1, nullptr, 0};
     wg[c + 1] = wg[c] + blockmin_grid(it.n, b->plans[i].kshift, 4);
     qp[c + 1] = qp[c] + it.q;
     const int rounds = st_rounds(f.levels);

@@ -129,8 +129,8 @@ __global__ __launch_bounds__(WG) void k_contract(const int32_t* __restrict__ A, 
 #pragma unroll
     for (int k = 0; k < KREG; ++k) {
       if (k >= rounds) break;
-      const int32_t up = __shfl_up(ep[k], 1);
-      const int32_t wrap = k == 0 ? before_lo : __shfl(ep[k - 1], 63);
+      const int32_t up = (int32_t)dpp_u32_id<DPP_WAVE_SHR1>((uint32_t)ep[k], 0u);
+      const int32_t wrap = k == 0 ? before_lo : __builtin_amdgcn_readlane(ep[k - 1], 63);
       epv[k] = lane == 0 ? wrap : up;
     }
   }
@@ -207,18 +207,8 @@ __global__ __launch_bounds__(WG) void k_contract(const int32_t* __restrict__ A, 
     }
     // ---- runs across lanes: segmented inclusive min-scan of lane totals
     // (keys of value and offset, so equal values keep the leftmost) ----
-    uint64_t v = make_key(cv, co);
-    bool f = hb != 0;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const uint64_t vu = __shfl_up(v, d);
-      const int fu = __shfl_up((int)f, d);
-      if (lane >= d) {
-        if (!f) v = umin64(v, vu);
-        f = f || fu;
-      }
-    }
-    const uint64_t carry = __shfl_up(v, 1);  // lane 0: no run comes in
+    const uint64_t v = seg_scan_min_u64(make_key(cv, co), hb != 0);
+    const uint64_t carry = dpp_u64_id<DPP_WAVE_SHR1>(v, KEY_NONE);  // lane 0: no run comes in
     const int first = hb ? __builtin_ctz(hb) : EPL;
     const int32_t kv = (int32_t)((uint32_t)(carry >> 32) ^ 0x80000000u);
     const uint32_t ko = (uint32_t)carry;

@@ -50,6 +50,59 @@ __device__ __forceinline__ uint64_t dpp_u64(uint64_t v) {
   return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
 }
 
+// DPP move whose lanes without a source (outside the row for row shifts,
+// lane 0 for the wave shift, rows masked off) read `ident` instead.
+enum : int {
+  DPP_ROW_SHR1 = 0x111,  // lane i <- i-1 within each row of 16
+  DPP_ROW_SHR2 = 0x112,
+  DPP_ROW_SHR4 = 0x114,
+  DPP_ROW_SHR8 = 0x118,
+  DPP_WAVE_SHR1 = 0x138,  // lane i <- i-1 across the wave
+};
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ uint32_t dpp_u32_id(uint32_t v, uint32_t ident) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)ident, (int)v, CTRL, ROW_MASK, 0xF, false);
+}
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ uint64_t dpp_u64_id(uint64_t v, uint64_t ident) {
+  const uint32_t lo = dpp_u32_id<CTRL, ROW_MASK>((uint32_t)v, (uint32_t)ident);
+  const uint32_t hi = dpp_u32_id<CTRL, ROW_MASK>((uint32_t)(v >> 32), (uint32_t)(ident >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Inclusive segmented min-scan over the wave: lane l ends with the min of v
+// over lanes s..l, s the last lane <= l with a set flag (lane 0 if none).
+// Row shifts 1, 2, 4, 8 scan each row of 16; broadcasts of lanes 15 and 31
+// join the rows.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ void seg_min_step(uint64_t& v, uint32_t& f) {
+  const uint64_t vu = dpp_u64_id<CTRL, ROW_MASK>(v, KEY_NONE);
+  const uint32_t fu = dpp_u32_id<CTRL, ROW_MASK>(f, 0u);
+  v = f ? v : umin64(v, vu);
+  f |= fu;
+}
+__device__ __forceinline__ uint64_t seg_scan_min_u64(uint64_t v, bool head) {
+  uint32_t f = head ? 1u : 0u;
+  seg_min_step<DPP_ROW_SHR1, 0xF>(v, f);
+  seg_min_step<DPP_ROW_SHR2, 0xF>(v, f);
+  seg_min_step<DPP_ROW_SHR4, 0xF>(v, f);
+  seg_min_step<DPP_ROW_SHR8, 0xF>(v, f);
+  seg_min_step<DPP_ROW_BCAST15, 0xA>(v, f);
+  seg_min_step<DPP_ROW_BCAST31, 0xC>(v, f);
+  return v;
+}
+
+// Inclusive prefix sum over the wave (same DPP pattern).
+__device__ __forceinline__ uint32_t wave_inclusive_add_u32(uint32_t x) {
+  x += dpp_u32_id<DPP_ROW_SHR1, 0xF>(x, 0u);
+  x += dpp_u32_id<DPP_ROW_SHR2, 0xF>(x, 0u);
+  x += dpp_u32_id<DPP_ROW_SHR4, 0xF>(x, 0u);
+  x += dpp_u32_id<DPP_ROW_SHR8, 0xF>(x, 0u);
+  x += dpp_u32_id<DPP_ROW_BCAST15, 0xA>(x, 0u);
+  x += dpp_u32_id<DPP_ROW_BCAST31, 0xC>(x, 0u);
+  return x;
+}
+
 // Min over aligned groups of G lanes (G = 1..64, power of two).  Afterwards
 // the LAST lane of each group (lane % G == G-1) holds the group's minimum
 // (for G <= 16 every lane of the group does).

@@ -16,5 +16,6 @@ struct rmq_index_s {
   uint64_t* sub;     // two block levels (Section 3.3): k1-block minima, else null
   int k1shift;       // k1 = 2^k1shift when sub is set
   int64_t nb1;       // number of k1-blocks
-  size_t bytes;      // table + k1-block minima
+  uint64_t* rec;     // query records of the doubling table, or null
+  size_t bytes;      // table + k1-block minima + query records
 };

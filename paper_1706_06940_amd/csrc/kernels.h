@@ -67,6 +67,8 @@ struct ArrayDesc {
   int64_t q;
   int32_t* out;
   int32_t lg;  // table arity l = 2^lg (1: doubling)
+  const uint64_t* rec;  // query records of the doubling table, or null
+  int32_t rlev;         // levels of the records' table
 };
 
 // Sparse Table rounds: round r builds levels j0(r)+1 .. j0(r)+t; j0 = 0,
@@ -88,6 +90,13 @@ hipError_t launch_sparse_table(uint64_t* st, int64_t nb, int levels, hipStream_t
 // Levels i >= 1 are stored by residue class mod l^i (lary_addr in device.h).
 int lary_levels(int64_t nb, int lg);
 hipError_t launch_sparse_table_lary(uint64_t* st, int64_t nb, int lg, hipStream_t stream);
+// Query records of a doubling table (levels x nb, level-major), pairs of
+// keys on 16-byte boundaries: forward pair (b, t) at rec + 2 (b levels + t)
+// holds st[0][b] and st[t][b + 1]; backward pair (b, t) at
+// rec + 2 ((nb + b) levels + t) holds st[0][b] and st[t][b - 2^t]; a pair
+// without a window holds the min identity there.  4 nb levels keys in all.
+hipError_t launch_records(const uint64_t* st, int64_t nb, int levels, uint64_t* rec,
+                          hipStream_t stream);
 int64_t blockmin_grid(int64_t n, int kshift, int elems_per_lane_load);
 // Batched forms: one launch per phase for all arrays of a batch.  The
 // prefix tables (count + 1 entries, starting at 0) give each array's first
@@ -109,18 +118,20 @@ hipError_t launch_query_segments(const ArrayDesc* tables, const int64_t* seg_pre
 hipError_t launch_query_full(const int32_t* A, int64_t n, int kshift, const uint64_t* st,
                              int64_t nb, const int32_t* L, const int32_t* R, int64_t q,
                              int32_t* out, int64_t* bad_count, uint64_t* stats,
-                             hipStream_t stream, int lg = 1);
+                             hipStream_t stream, int lg = 1, const uint64_t* rec = nullptr,
+                             int rlev = 0);
 // LCA queries (Section 1) over the depth array D of an Euler tour.
 hipError_t launch_query_lca(const int32_t* D, int64_t len, int kshift, const uint64_t* st,
                             int64_t nb, const uint64_t* sub, int k1shift, const int32_t* first,
                             const int32_t* node, int64_t N, const int32_t* U, const int32_t* V,
                             int64_t q, int32_t* out, int64_t* bad_count, hipStream_t stream,
-                            int lg = 1);
+                            int lg = 1, const uint64_t* rec = nullptr, int rlev = 0);
 // Two block levels (Section 3.3): sub holds the minima of the 2^k1shift-blocks.
 hipError_t launch_query_full2(const int32_t* A, int64_t n, int kshift, const uint64_t* st,
                               int64_t nb, const uint64_t* sub, int k1shift, const int32_t* L,
                               const int32_t* R, int64_t q, int32_t* out, int64_t* bad_count,
-                              uint64_t* stats, hipStream_t stream, int lg = 1);
+                              uint64_t* stats, hipStream_t stream, int lg = 1,
+                              const uint64_t* rec = nullptr, int rlev = 0);
 
 // ---- contracted path (Section 3.1) ----
 // Device LSD radix sort of the 2q endpoints by (position, tag).  The sorted
@@ -154,6 +165,6 @@ hipError_t launch_query_contracted(const uint64_t* aq, int64_t m, int64_t n, int
                                    const uint64_t* st, int64_t nb, const int32_t* L,
                                    const int32_t* R, const int32_t* LR, int64_t q, int32_t* out,
                                    int64_t* bad_count, uint64_t* stats, hipStream_t stream,
-                                   int lg = 1);
+                                   int lg = 1, const uint64_t* rec = nullptr, int rlev = 0);
 
 }  // namespace rmq

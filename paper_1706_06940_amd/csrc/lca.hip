@@ -387,6 +387,7 @@ rmq_status rmq_lca_build(const int32_t* parent, int64_t num_nodes, const rmq_opt
       o.block_size = opt->block_size;
       o.sub_block_size = opt->sub_block_size;
       o.table_arity_log2 = opt->table_arity_log2;
+      o.no_query_records = opt->no_query_records;
     }
     st = rmq_build(h->depth, len, &o, stream, &h->idx);
   }
@@ -409,7 +410,8 @@ rmq_status rmq_lca_query(rmq_lca h, const int32_t* u, const int32_t* v, int64_t 
   return status_of(launch_query_lca(h->depth, ix->n, ix->kshift, ix->st, ix->nb, ix->sub,
                                     ix->k1shift, h->first, h->node, h->N, u, v, q, out,
                                     opt ? opt->bad_count : nullptr,
-                                    static_cast<hipStream_t>(stream), ix->lg));
+                                    static_cast<hipStream_t>(stream), ix->lg, ix->rec,
+                                    ix->levels));
 }
 
 rmq_status rmq_lca_copy_tour(rmq_lca h, int32_t* depth, int32_t* node, int32_t* first,

@@ -244,7 +244,8 @@ __device__ __forceinline__ void query_core(const Src& src, int64_t src_len, int6
                                            int64_t ri, bool live, int32_t* outp,
                                            unsigned long long* __restrict__ bad_count,
                                            unsigned long long* __restrict__ stats,
-                                           int lg = 1) {
+                                           int lg = 1, const uint64_t* __restrict__ rec = nullptr,
+                                           int rlev = 0) {
   const int lane = lane_id();
   const bool ok = live && 0 <= l && l <= r && r < n && 0 <= li && li <= ri && ri < src_len;
 
@@ -254,7 +255,16 @@ __device__ __forceinline__ void query_core(const Src& src, int64_t src_len, int6
 
   if (ok) {
     const int64_t bl = li >> kshift, br = ri >> kshift;
-    const uint64_t kl = st[bl];
+    const int64_t inner = br - bl - 1;
+    const int t = inner > 0 ? ilog2_u64((uint64_t)inner) : 0;
+    // query records (doubling table): one 16-byte load per end gives the
+    // end block's key and the window of 2^t blocks beside it
+    v2u64 pl = {KEY_NONE, KEY_NONE}, pr = {KEY_NONE, KEY_NONE};
+    if (rec) {
+      pl = *reinterpret_cast<const v2u64*>(rec + 2 * (bl * rlev + t));
+      if (bl != br) pr = *reinterpret_cast<const v2u64*>(rec + 2 * ((nb + br) * rlev + t));
+    }
+    const uint64_t kl = rec ? pl.x : st[bl];
     if (bl == br) {
       const int64_t p = src.pos_of(kl);
       if (l <= p && p <= r) {
@@ -265,12 +275,10 @@ __device__ __forceinline__ void query_core(const Src& src, int64_t src_len, int6
         hiL = ri;
       }
     } else {
-      const int64_t inner = br - bl - 1;
       if (inner > 0) {
-        const int t = ilog2_u64((uint64_t)inner);
         if (lg <= 1) {  // doubling (Section 2): two overlapping windows
           const uint64_t* lev = st + (size_t)t * nb;
-          best = umin64(lev[bl + 1], lev[br - (1ll << t)]);
+          best = rec ? umin64(pl.y, pr.y) : umin64(lev[bl + 1], lev[br - (1ll << t)]);
         } else {
           // l-ary table (Section 3.1), l = 2^lg: level i holds windows of
           // s = l^i blocks; whole windows from the left, then one ending at
@@ -286,7 +294,7 @@ __device__ __forceinline__ void query_core(const Src& src, int64_t src_len, int6
             best = umin64(best, lev[lary_addr(br - (1ll << sh), nb, sh)]);
         }
       }
-      kr = st[br];
+      kr = rec ? pr.x : st[br];
       if ((int64_t)src.pos_of(kl) >= l) {
         best = umin64(best, kl);
       } else if (kl < best) {
@@ -382,7 +390,8 @@ __global__ __launch_bounds__(WG) void k_query(Src src, int64_t src_len, int64_t 
                                               const int32_t* __restrict__ LR, int64_t q,
                                               int32_t* __restrict__ out,
                                               unsigned long long* __restrict__ bad_count,
-                                              unsigned long long* __restrict__ stats, int lg) {
+                                              unsigned long long* __restrict__ stats, int lg,
+                                              const uint64_t* __restrict__ rec, int rlev) {
   const int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
   const bool live = i < q;
   int64_t l = 0, r = -1, li = 0, ri = -1;
@@ -399,7 +408,7 @@ __global__ __launch_bounds__(WG) void k_query(Src src, int64_t src_len, int64_t 
     }
   }
   query_core(src, src_len, n, kshift, st, nb, l, r, li, ri, live, out + (live ? i : 0),
-             bad_count, stats, lg);
+             bad_count, stats, lg, rec, rlev);
 }
 
 // Every query of a batch of tables (plain path): global query g belongs to
@@ -420,7 +429,7 @@ __global__ __launch_bounds__(WG) void k_query_multi(const ArrayDesc* __restrict_
     r = d.R[i];
   }
   query_core(SrcA{d.A, d.n}, d.n, d.n, d.kshift, d.st, d.nb, l, r, l, r, live, d.out + i,
-             bad_count, stats, d.lg);
+             bad_count, stats, d.lg, d.rec, d.rlev);
 }
 
 // A coalesced batch of requests (serving): queries g in
@@ -442,7 +451,7 @@ __global__ __launch_bounds__(WG) void k_query_segments(const ArrayDesc* __restri
     r = R[g];
   }
   query_core(SrcA{d.A, d.n}, d.n, d.n, d.kshift, d.st, d.nb, l, r, l, r, live,
-             out + (live ? g : 0), nullptr, nullptr, d.lg);
+             out + (live ? g : 0), nullptr, nullptr, d.lg, d.rec, d.rlev);
 }
 
 // Lowest common ancestors (Section 1): query i is the pair (U[i], V[i]) of
@@ -457,7 +466,8 @@ __global__ __launch_bounds__(WG) void k_query_lca(Src src, int64_t len, int kshi
                                                   const int32_t* __restrict__ V, int64_t q,
                                                   int32_t* __restrict__ out,
                                                   unsigned long long* __restrict__ bad_count,
-                                                  int lg) {
+                                                  int lg, const uint64_t* __restrict__ rec,
+                                                  int rlev) {
   const int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
   const bool live = i < q;
   int64_t l = -1, r = -1;  // an invalid node leaves l < 0: answered -1
@@ -470,7 +480,7 @@ __global__ __launch_bounds__(WG) void k_query_lca(Src src, int64_t len, int kshi
     }
   }
   query_core(src, len, len, kshift, st, nb, l, r, l, r, live, out + (live ? i : 0), bad_count,
-             nullptr, lg);
+             nullptr, lg, rec, rlev);
   if (live) {
     const int32_t p = out[i];
     out[i] = p >= 0 ? node[p] : -1;
@@ -493,26 +503,27 @@ hipError_t launch_query_segments(const ArrayDesc* tables, const int64_t* seg_pre
 hipError_t launch_query_full(const int32_t* A, int64_t n, int kshift, const uint64_t* st,
                              int64_t nb, const int32_t* L, const int32_t* R, int64_t q,
                              int32_t* out, int64_t* bad_count, uint64_t* stats,
-                             hipStream_t stream, int lg) {
+                             hipStream_t stream, int lg, const uint64_t* rec, int rlev) {
   if (q <= 0) return hipSuccess;
   const int64_t grid = (q + WG - 1) / WG;
   RMQ_TRY(launch(k_query<SrcA>, dim3((unsigned)grid), dim3(WG), 0, stream, SrcA{A, n}, n, n,
                  kshift, st, nb, L, R, static_cast<const int32_t*>(nullptr), q, out,
-                 (unsigned long long*)bad_count, (unsigned long long*)stats, lg));
+                 (unsigned long long*)bad_count, (unsigned long long*)stats, lg, rec, rlev));
   return hipGetLastError();
 }
 
 hipError_t launch_query_full2(const int32_t* A, int64_t n, int kshift, const uint64_t* st,
                               int64_t nb, const uint64_t* sub, int k1shift, const int32_t* L,
                               const int32_t* R, int64_t q, int32_t* out, int64_t* bad_count,
-                              uint64_t* stats, hipStream_t stream, int lg) {
+                              uint64_t* stats, hipStream_t stream, int lg, const uint64_t* rec,
+                              int rlev) {
   if (q <= 0) return hipSuccess;
   const int64_t grid = (q + WG - 1) / WG;
   const int64_t nsub = (n + (1ll << k1shift) - 1) >> k1shift;
   RMQ_TRY(launch(k_query<SrcA2>, dim3((unsigned)grid), dim3(WG), 0, stream,
                  SrcA2{SrcA{A, n}, sub, nsub, k1shift}, n, n, kshift, st, nb, L, R,
                  static_cast<const int32_t*>(nullptr), q, out, (unsigned long long*)bad_count,
-                 (unsigned long long*)stats, lg));
+                 (unsigned long long*)stats, lg, rec, rlev));
   return hipGetLastError();
 }
 
@@ -520,18 +531,18 @@ hipError_t launch_query_lca(const int32_t* D, int64_t len, int kshift, const uin
                             int64_t nb, const uint64_t* sub, int k1shift, const int32_t* first,
                             const int32_t* node, int64_t N, const int32_t* U, const int32_t* V,
                             int64_t q, int32_t* out, int64_t* bad_count, hipStream_t stream,
-                            int lg) {
+                            int lg, const uint64_t* rec, int rlev) {
   if (q <= 0) return hipSuccess;
   const int64_t grid = (q + WG - 1) / WG;
   if (sub) {
     const int64_t nsub = (len + (1ll << k1shift) - 1) >> k1shift;
     RMQ_TRY(launch(k_query_lca<SrcA2>, dim3((unsigned)grid), dim3(WG), 0, stream,
                    SrcA2{SrcA{D, len}, sub, nsub, k1shift}, len, kshift, st, nb, first, node, N,
-                   U, V, q, out, (unsigned long long*)bad_count, lg));
+                   U, V, q, out, (unsigned long long*)bad_count, lg, rec, rlev));
   } else {
     RMQ_TRY(launch(k_query_lca<SrcA>, dim3((unsigned)grid), dim3(WG), 0, stream, SrcA{D, len},
                    len, kshift, st, nb, first, node, N, U, V, q, out,
-                   (unsigned long long*)bad_count, lg));
+                   (unsigned long long*)bad_count, lg, rec, rlev));
   }
   return hipSuccess;
 }
@@ -540,12 +551,12 @@ hipError_t launch_query_contracted(const uint64_t* aq, int64_t m, int64_t n, int
                                    const uint64_t* st, int64_t nb, const int32_t* L,
                                    const int32_t* R, const int32_t* LR, int64_t q, int32_t* out,
                                    int64_t* bad_count, uint64_t* stats, hipStream_t stream,
-                                   int lg) {
+                                   int lg, const uint64_t* rec, int rlev) {
   if (q <= 0) return hipSuccess;
   const int64_t grid = (q + WG - 1) / WG;
   RMQ_TRY(launch(k_query<SrcKeys>, dim3((unsigned)grid), dim3(WG), 0, stream, SrcKeys{aq, m}, m,
                  n, kshift, st, nb, L, R, LR, q, out, (unsigned long long*)bad_count,
-                 (unsigned long long*)stats, lg));
+                 (unsigned long long*)stats, lg, rec, rlev));
   return hipGetLastError();
 }
 

@@ -207,12 +207,7 @@ __global__ __launch_bounds__(WG) void k_os_hist(const uint64_t* __restrict__ ite
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* tmp,
                                                          uint32_t& excl) {
   const int lane = lane_id(), wave = threadIdx.x >> 6;
-  uint32_t x = v;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const uint32_t y = __shfl_up(x, d);
-    if (lane >= d) x += y;
-  }
+  const uint32_t x = wave_inclusive_add_u32(v);
   if (lane == 63) tmp[wave] = x;
   __syncthreads();
   uint32_t off = 0, total = 0;

@@ -312,7 +312,7 @@ rmq_status rmq_server_add_array(rmq_server S, const int32_t* A, int64_t n, int32
     return from_hip(e);
   }
   const ArrayDesc d{ix->A, ix->n, ix->kshift, ix->levels, ix->nb, ix->st,
-                    nullptr, nullptr, 0, nullptr, ix->lg};
+                    nullptr, nullptr, 0, nullptr, ix->lg, ix->rec, ix->levels};
   std::lock_guard<std::mutex> lk(S->mu);
   const int32_t id = (int32_t)S->tables.size();
   e = hipMemcpy(S->d_tables + id, &d, sizeof(ArrayDesc), hipMemcpyHostToDevice);

@@ -227,7 +227,36 @@ __global__ __launch_bounds__(WG) void k_st_lary(const uint64_t* __restrict__ pre
   }
 }
 
+// Query records: one thread per key, in record order (coalesced writes);
+// the table reads are gathers from a table small enough for L2.
+__global__ __launch_bounds__(WG) void k_records(const uint64_t* __restrict__ st, int64_t nb,
+                                                int levels, uint64_t* __restrict__ rec) {
+  const int64_t e = (int64_t)blockIdx.x * WG + threadIdx.x;
+  if (e >= 4 * nb * levels) return;
+  const int64_t pair = e >> 1;
+  const int64_t rb = pair / levels;  // record: forward 0 .. nb-1, backward nb .. 2nb-1
+  const int t = (int)(pair - rb * levels);
+  const bool fwd = rb < nb;
+  const int64_t b = fwd ? rb : rb - nb;
+  uint64_t v = KEY_NONE;
+  if ((e & 1) == 0) {
+    v = st[b];
+  } else {
+    const int64_t x = fwd ? b + 1 : b - (1ll << t);  // window start
+    if (fwd ? x < nb : x >= 0) v = st[(size_t)t * nb + x];
+  }
+  rec[e] = v;
+}
+
 }  // namespace
+
+hipError_t launch_records(const uint64_t* st, int64_t nb, int levels, uint64_t* rec,
+                          hipStream_t stream) {
+  const int64_t total = 4 * nb * levels;
+  RMQ_TRY(launch(k_records, dim3((unsigned)((total + WG - 1) / WG)), dim3(WG), 0, stream, st, nb,
+                 levels, rec));
+  return hipSuccess;
+}
 
 int lary_levels(int64_t nb, int lg) {
   if (nb <= 3) return 1;

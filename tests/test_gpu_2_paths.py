@@ -133,7 +133,11 @@ def test_resident_index(orc):
     A = W.uniform_int31(n, 91)
     At = dev(A, d)
     idx = rmq.Index(At, block_size=2048)
-    assert idx.bytes == rmq.index_bytes(n, 2048)
+    nb = -(-n // 2048)
+    # the table (Table 2's footprint), then the query records on a 256-byte boundary
+    assert rmq.query_record_bytes(nb) > 0
+    assert idx.bytes == -(-rmq.index_bytes(n, 2048) // 256) * 256 + rmq.query_record_bytes(nb)
+    assert rmq.Index(At, block_size=2048, records=False).bytes == rmq.index_bytes(n, 2048)
     for seed in range(3):
         L, R = W.uniform_queries(n, 10_000, 100 + seed)
         got = host(idx.query(dev(L, d), dev(R, d)))
