@@ -123,7 +123,7 @@ typedef struct rmq_options {
     int32_t no_query_records; /* nonzero: do not build query records.  By
                                  default a doubling table of nb blocks and L
                                  levels also gets, when 32 * nb * L bytes <=
-                                 32 MiB, two records per block: for every
+                                 8 MiB, two records per block: for every
                                  level t, the block's minimum paired with the
                                  window of 2^t blocks starting just after it,
                                  and paired with the window ending just

@@ -80,7 +80,7 @@ struct Plan {
 // Query records (see launch_records) for a doubling table of nb blocks and
 // `levels` levels: whether they are built (not for another arity, nor above
 // kMaxRecordBytes), and their bytes.
-constexpr size_t kMaxRecordBytes = 32u << 20;
+constexpr size_t kMaxRecordBytes = 8u << 20;  // measured: larger records lose to L2 misses
 size_t records_bytes(int64_t nb, int levels) { return sizeof(uint64_t) * 4 * (size_t)nb * levels; }
 bool records_built(int64_t nb, int levels, int lg, bool allowed) {
   return allowed && lg <= 1 && records_bytes(nb, levels) <= kMaxRecordBytes;

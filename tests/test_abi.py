@@ -86,18 +86,18 @@ def test_table_levels_over_powers_of_l():
 
 def test_query_record_bytes():
     # two records per block, one 16-byte pair per level, while they take at
-    # most 32 MiB
-    for nb in (1, 2, 3, 4, 100, 32_768, 65_536, 65_537, 10 ** 6):
+    # most 8 MiB
+    for nb in (1, 2, 3, 4, 100, 16_384, 17_476, 17_477, 32_768, 10 ** 6):
         exp = 2 * nb * rmq.table_levels(nb) * 16
-        assert rmq.query_record_bytes(nb) == (exp if exp <= 32 << 20 else 0), nb
-    assert rmq.query_record_bytes(24_415) == 2 * 24_415 * 15 * 16  # n = 1e8, k = 4096
-    assert rmq.query_record_bytes(65_536) == 32 << 20 and rmq.query_record_bytes(65_537) == 0
-    assert rmq.query_record_bytes(97_657) == 0 and rmq.query_record_bytes(0) == 0
+        assert rmq.query_record_bytes(nb) == (exp if exp <= 8 << 20 else 0), nb
+    assert rmq.query_record_bytes(12_208) == 2 * 12_208 * 14 * 16  # n = 1e8, k = 8192
+    assert rmq.query_record_bytes(17_476) > 0 and rmq.query_record_bytes(17_477) == 0
+    assert rmq.query_record_bytes(24_415) == 0 and rmq.query_record_bytes(0) == 0
     # the offline workspace holds them unless asked not to
     n, q = 10 ** 8, 10 ** 7
-    nb = -(-n // 4096)
-    on = rmq.workspace_bytes(n, q, "full", 4096)
-    off = rmq.workspace_bytes(n, q, "full", 4096, records=False)
+    nb = -(-n // 8192)
+    on = rmq.workspace_bytes(n, q, "full", 8192)
+    off = rmq.workspace_bytes(n, q, "full", 8192, records=False)
     assert off < on <= off + rmq.query_record_bytes(nb) + 512
 
 

@@ -3,7 +3,7 @@ the window of 2^t blocks that starts just after it (forward record) or ends
 just before it (backward record), for every level t, so that a query reads
 each end block and the window beside it in one 16-byte load.  Answers with
 records, without them and from the oracle agree bit for bit on every path
-that reads them, including the edge of the record rule (32 MiB)."""
+that reads them, including the edge of the record rule (8 MiB)."""
 import numpy as np
 import pytest
 import torch
@@ -22,11 +22,11 @@ def both(At, Lt, Rt, **kw):
 
 
 @pytest.mark.parametrize("n,k", [(1, 16), (33, 16), (48, 16), (64, 16), (1000, 16), (4099, 64),
-                                 (524_300, 16), (1 << 20, 32), (1 << 20, 16),
-                                 (1_048_577, 16), (4_194_400, 64), (1_000_003, 1 << 20)])
+                                 (262_144, 16), (279_616, 16), (279_617, 16),
+                                 (1 << 20, 16), (4_194_400, 64), (1_000_003, 1 << 20)])
 def test_full_families(orc, n, k):
-    """nb from 1 to 65,538 blocks: records up to 65,536 blocks (16 levels,
-    exactly 32 MiB), none above."""
+    """nb from 1 to 65,538 blocks: records up to 17,476 blocks (15 levels,
+    8 MiB), none above."""
     d = need_gpu()
     q = 3000 if n > 64 else 300
     for aname, A in list(arrays(n, n + k))[:5]:
@@ -75,9 +75,9 @@ def test_index_two_level_lca_and_serving_agree(orc):
     exp = reference(orc, A, L, R)
     Lt, Rt = dev(L, d), dev(R, d)
     for kw in (dict(block_size=1024), dict(block_size=4096, sub_block_size=256),
-               dict(block_size=64)):
+               dict(block_size=256)):
         on, off = rmq.Index(At, records=True, **kw), rmq.Index(At, records=False, **kw)
-        assert on.bytes > off.bytes  # records kept up to 65,536 blocks (here <= 46,876)
+        assert on.bytes > off.bytes  # records kept up to 17,476 blocks (here <= 11,719)
         assert np.array_equal(host(on.query(Lt, Rt)), exp), kw
         assert np.array_equal(host(off.query(Lt, Rt)), exp), kw
         assert torch.equal(on.table(), off.table())
