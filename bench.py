@@ -207,6 +207,22 @@ def main() -> int:
                     "launches": len(blockmin),
                     "traffic_source": os.path.relpath(TRAFFIC_PROFILE, ROOT)}
 
+    # the part's achievable read rate for this pass: the same loads over the
+    # same A, keeping nothing (25 launches timed by their own events)
+    if roofline is not None:
+        sink = torch.zeros(1, dtype=torch.int32, device=d)
+        stream = torch.cuda.current_stream(d)
+        rmq.read_probe(A, sink, reps=2)
+        t_pr = rmq.Timer()
+        rmq.read_probe(A, sink, reps=25, timer=t_pr)  # back to back, launch-attached events
+        probe_ms = t_pr.read()[1] / 25
+        probe_gbs = 16 * (n // 4) / (probe_ms / 1e3) / 1e9  # 4 floor(n/4) int32 read
+        roofline["read_ceiling"] = {
+            "achieved": round(probe_gbs, 1), "frac": round(probe_gbs / HBM_PEAK_GBS, 4),
+            "kernel_over_ceiling": round(roofline["achieved"] / probe_gbs, 4),
+            "how": "rmq_read_probe: the block-minima loads over the same A with nothing kept, "
+                   "mean of 25 back-to-back launches"}
+
     # the same block-minima launches after a 1 GB write that evicts A from the
     # L2s and the MALL (the paper's cache flush before every repetition)
     if roofline is not None and not args.no_flushed:

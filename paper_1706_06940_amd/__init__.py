@@ -93,6 +93,7 @@ def lib() -> ctypes.CDLL:
         "rmq_table_levels": ([i64], i32),
         "rmq_table_levels_ary": ([i64, i32], i32),
         "rmq_query_record_bytes": ([i64], sz),
+        "rmq_read_probe": ([v, i64, v, i32, v, v], i32),
         "rmq_block_minima": ([v, i64, i32, v, v], i32),
         "rmq_block_minima_keys": ([v, i64, i32, v, v], i32),
         "rmq_sparse_table_build": ([v, i64, i32, v], i32),
@@ -251,6 +252,18 @@ def query_record_bytes(num_blocks: int) -> int:
     """Bytes of the query records kept beside a doubling table of
     num_blocks blocks (0 if none)."""
     return int(lib().rmq_query_record_bytes(num_blocks))
+
+
+def read_probe(A: torch.Tensor, sink: torch.Tensor, reps: int = 1, stream=None,
+               timer: Optional[Timer] = None) -> None:
+    """reps streaming reads of A with the block-minima pass's loads, back to
+    back (a measurement aid: their time is the achievable read rate of that
+    pass); with a timer, its stage 1 spans them."""
+    if sink.dtype != torch.int32 or not sink.is_cuda:
+        raise TypeError("sink must be a CUDA int32 tensor")
+    _check("rmq_read_probe", lib().rmq_read_probe(_dev_i32(A, "A"), A.numel(), sink.data_ptr(),
+                                                  int(reps), _stream(A.device, stream),
+                                                  timer.handle if timer is not None else None))
 
 
 def table_levels(num_blocks: int, arity_log2: int = 0) -> int:

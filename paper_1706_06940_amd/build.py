@@ -27,6 +27,7 @@ SOURCES = [
     "capi.hip",
     "server.hip",
     "lca.hip",
+    "probe.hip",
 ]
 
 ARCH = "gfx950"
