@@ -551,9 +551,13 @@ def bench_served(d, n_req):
     out = {"workload": (f"64 resident arrays, n log-uniform in [1e6,1e8] (total {int(ns.sum())}); "
                         f"{n_req} requests, q log-uniform in [1,1e5], uniform queries")}
     for name, cfg in (("coalesced", dict(num_streams=4, max_requests_per_batch=4096,
-                                         hbm_budget_bytes=4 * 12 * (1 << 21) + (1 << 20))),
+                                         budget_bytes=4 * 12 * (1 << 21) + (1 << 20))),
+                      ("coalesced_copying", dict(num_streams=4, max_requests_per_batch=4096,
+                                                 budget_bytes=4 * 12 * (1 << 21) + (1 << 20),
+                                                 copy_queries=True)),
                       ("per_request", dict(num_streams=1, max_requests_per_batch=1,
-                                           hbm_budget_bytes=12 * (1 << 21) + (1 << 20)))):
+                                           budget_bytes=12 * (1 << 21) + (1 << 20),
+                                           copy_queries=True))):
         with serving.Server(max_tables=64, **cfg) as srv:
             for A in arrays:
                 srv.add_array(A)

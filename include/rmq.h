@@ -373,19 +373,29 @@ rmq_status rmq_batch_free(rmq_batch b);
  * (Section 3.2's index, built once per array) and answers query requests as
  * they arrive.  Requests wait in a queue; a dispatcher thread packs whatever
  * is pending into the next free slot -- a stream with its own pinned staging
- * and device query buffers -- while their queries fit the slot (admission by
- * HBM footprint: the slots' device buffers are carved from hbm_budget_bytes),
- * and answers the whole coalesced batch with one query launch over the
- * resident tables; requests that arrive meanwhile go to the next slot, so
+ * buffer (and device query buffers with RMQ_SERVER_COPY_QUERIES) -- while
+ * their queries fit the slot (admission by footprint: the slots' buffers are
+ * carved from budget_bytes), and answers the whole coalesced batch with one
+ * query launch over the resident tables, which reads the queries from the
+ * staging buffer and writes the answers there (or, copying, from and to the
+ * device buffers); requests that arrive meanwhile go to the next slot, so
  * batches overlap on the device.  A completion thread copies each request's
  * answers to its output buffer.  All threads are native; the calls below are
  * thread-safe. */
+#define RMQ_SERVER_COPY_QUERIES 1  /* flags: queries and answers through device
+                                      buffers (one H2D and one D2H copy per
+                                      batch) instead of being read and written
+                                      in the pinned staging buffers by the
+                                      query kernel itself (the default)       */
 typedef struct rmq_server_config {
     int32_t num_streams;             /* slots in flight, 1..16                    */
     int32_t max_tables;              /* resident arrays the server can hold       */
     int32_t max_requests_per_batch;  /* requests coalesced into one launch        */
-    int32_t reserved;
-    size_t hbm_budget_bytes;         /* device bytes for in-flight query buffers  */
+    int32_t flags;                   /* 0 or RMQ_SERVER_COPY_QUERIES              */
+    size_t budget_bytes;             /* bytes of in-flight query buffers, split
+                                        over the slots (12 B a query + segment
+                                        tables): pinned host memory, plus as
+                                        much device memory with the copy flag */
 } rmq_server_config;
 
 typedef struct rmq_server_stats {

@@ -176,6 +176,22 @@ __device__ __forceinline__ int find_item(const int64_t* __restrict__ prefix, int
   return lo;
 }
 
+// find_item for every lane of a wave whose lanes hold consecutive x (a
+// wave's share of a concatenated list): one search for the wave's first x
+// with wave-uniform values (scalar loads), then each lane steps forward past
+// the few boundaries inside the wave.  x_first: the wave's first x, clamped to
+// [0, prefix[count]).
+__device__ __forceinline__ int find_item_wave(const int64_t* __restrict__ prefix, int count,
+                                              int64_t x_first, int64_t x) {
+  const uint64_t u = (uint64_t)x_first;
+  const int64_t xf = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(
+                                    (int)(uint32_t)(u >> 32)) << 32) |
+                               (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u));
+  int j = find_item(prefix, count, xf);
+  while (j + 1 < count && prefix[j + 1] <= x) ++j;
+  return j;
+}
+
 // Floor log2 for x >= 1.
 __device__ __forceinline__ int ilog2_u64(uint64_t x) { return 63 - __clzll(x); }
 

@@ -419,8 +419,10 @@ __global__ __launch_bounds__(WG) void k_query_multi(const ArrayDesc* __restrict_
                                                     unsigned long long* __restrict__ bad_count,
                                                     unsigned long long* __restrict__ stats) {
   const int64_t g = (int64_t)blockIdx.x * WG + threadIdx.x;
-  const bool live = g < q_prefix[count];
-  const int j = live ? find_item(q_prefix, count, g) : 0;
+  const int64_t total = q_prefix[count];
+  const bool live = g < total;
+  const int64_t gw = (int64_t)blockIdx.x * WG + (threadIdx.x & ~63);  // the wave's first query
+  const int j = find_item_wave(q_prefix, count, gw < total ? gw : total - 1, live ? g : gw);
   const ArrayDesc& d = items[j];
   const int64_t i = live ? g - q_prefix[j] : 0;
   int64_t l = 0, r = -1;
@@ -442,8 +444,10 @@ __global__ __launch_bounds__(WG) void k_query_segments(const ArrayDesc* __restri
                                                        const int32_t* __restrict__ R,
                                                        int32_t* __restrict__ out) {
   const int64_t g = (int64_t)blockIdx.x * WG + threadIdx.x;
-  const bool live = g < seg_prefix[nseg];
-  const int sg = live ? find_item(seg_prefix, nseg, g) : 0;
+  const int64_t total = seg_prefix[nseg];
+  const bool live = g < total;
+  const int64_t gw = (int64_t)blockIdx.x * WG + (threadIdx.x & ~63);  // the wave's first query
+  const int sg = find_item_wave(seg_prefix, nseg, gw < total ? gw : total - 1, live ? g : gw);
   const ArrayDesc& d = tables[seg_table[sg]];
   int64_t l = 0, r = -1;
   if (live) {

@@ -3,15 +3,19 @@
 //
 // Requests (array id, q queries in host memory) are queued by rmq_server_submit.
 // A dispatcher thread takes whatever is pending whenever a slot -- a stream
-// with its own pinned staging buffer and device query buffers -- is free,
-// packs the requests FIFO into it while their queries fit the slot's device
-// capacity (admission by HBM footprint: the slots' buffers are sized from the
-// configured byte budget), and enqueues one H2D copy, one query launch over
-// the coalesced batch (each request's queries address its own resident
-// table) and one D2H copy.  Requests arriving meanwhile form the next batch on
-// the next free slot, so batches overlap on the device.  A completion thread
-// polls the slots' events, copies each request's answers to its output
-// buffer and stamps its completion time.
+// with its own pinned staging buffer (and, in the copying mode, device query
+// buffers) -- is free, packs the requests FIFO into it while their queries fit
+// the slot's capacity (admission by footprint: the slots' buffers are sized
+// from the configured byte budget), and enqueues one query launch over the
+// coalesced batch (each request's queries address its own resident table).
+// By default that kernel reads the queries from the pinned staging buffer and
+// writes the answers there itself; with RMQ_SERVER_COPY_QUERIES they go
+// through device buffers with one H2D and one D2H copy.  (The copy engines
+// were measured to stall now and then for several ms at moderate load, a
+// whole p99 by themselves, while reading in place did not.)  Requests
+// arriving meanwhile form the next batch on the next free slot, so batches
+// overlap on the device.  A completion thread polls the slots' events, copies
+// each request's answers to its output buffer and stamps its completion time.
 #include <math.h>
 #include <string.h>
 
@@ -119,6 +123,17 @@ hipError_t launch_slot(rmq_server_s* S, int si) {
     off += r->q;
   }
   hp[nseg] = off;
+  if (!sl.d) {
+    // in place: the kernel reads the queries from the pinned staging buffer
+    // and writes the answers there
+    const int32_t* hq = reinterpret_cast<const int32_t*>(sl.h);
+    RMQ_TRY(launch_query_segments(S->d_tables,
+                                  reinterpret_cast<const int64_t*>(sl.h + S->off_prefix),
+                                  reinterpret_cast<const int32_t*>(sl.h + S->off_table), nseg, hq,
+                                  hq + total, reinterpret_cast<int32_t*>(sl.h + S->off_out), total,
+                                  sl.stream));
+    return hipEventRecord(sl.done, sl.stream);
+  }
   const size_t seg_bytes = sizeof(int64_t) * (size_t)(nseg + 1);
   RMQ_TRY(hipMemcpyAsync(sl.d, sl.h, 2 * sizeof(int32_t) * (size_t)total, hipMemcpyHostToDevice,
                          sl.stream));
@@ -256,7 +271,8 @@ extern "C" {
 
 rmq_status rmq_server_create(const rmq_server_config* cfg, rmq_server* out) {
   if (!cfg || !out || cfg->num_streams < 1 || cfg->num_streams > 16 || cfg->max_tables < 1 ||
-      cfg->max_requests_per_batch < 1 || cfg->hbm_budget_bytes < 4096)
+      cfg->max_requests_per_batch < 1 || cfg->budget_bytes < 4096 ||
+      (cfg->flags & ~RMQ_SERVER_COPY_QUERIES) != 0)
     return RMQ_ERR_INVALID_ARG;
   rmq_server_s* S = new (std::nothrow) rmq_server_s();
   if (!S) return RMQ_ERR_OUT_OF_MEMORY;
@@ -264,7 +280,7 @@ rmq_status rmq_server_create(const rmq_server_config* cfg, rmq_server* out) {
   hipGetDevice(&S->device);
   S->max_reqs = cfg->max_requests_per_batch;
   // per slot: L, R, out (12 bytes a query) + segment tables, from the budget
-  const size_t per_slot = cfg->hbm_budget_bytes / (size_t)cfg->num_streams;
+  const size_t per_slot = cfg->budget_bytes / (size_t)cfg->num_streams;
   const size_t seg_bytes = align_up(sizeof(int64_t) * (size_t)(S->max_reqs + 1)) +
                            align_up(sizeof(int32_t) * (size_t)S->max_reqs);
   if (per_slot <= seg_bytes + 3 * kAlign) {
@@ -282,7 +298,8 @@ rmq_status rmq_server_create(const rmq_server_config* cfg, rmq_server* out) {
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&sl.h), S->slot_bytes, 0);
-    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&sl.d), S->slot_bytes);
+    if (e == hipSuccess && (cfg->flags & RMQ_SERVER_COPY_QUERIES))
+      e = hipMalloc(reinterpret_cast<void**>(&sl.d), S->slot_bytes);
   }
   if (e != hipSuccess) {
     free_slots(S);

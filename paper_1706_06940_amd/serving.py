@@ -25,10 +25,13 @@ from . import _check, _dev_i32, lib
 _i32p = ctypes.POINTER(ctypes.c_int32)
 
 
+COPY_QUERIES = 1  # queries and answers through device buffers and the copy engines
+
+
 class _Config(ctypes.Structure):
     _fields_ = [("num_streams", ctypes.c_int32), ("max_tables", ctypes.c_int32),
-                ("max_requests_per_batch", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("hbm_budget_bytes", ctypes.c_size_t)]
+                ("max_requests_per_batch", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("budget_bytes", ctypes.c_size_t)]
 
 
 class _Stats(ctypes.Structure):
@@ -96,8 +99,10 @@ def _host_i32(a: np.ndarray, name: str) -> np.ndarray:
 
 class Server:
     def __init__(self, num_streams: int = 3, max_tables: int = 64,
-                 max_requests_per_batch: int = 1024, hbm_budget_bytes: int = 256 << 20):
-        cfg = _Config(num_streams, max_tables, max_requests_per_batch, 0, hbm_budget_bytes)
+                 max_requests_per_batch: int = 1024, budget_bytes: int = 256 << 20,
+                 copy_queries: bool = False):
+        cfg = _Config(num_streams, max_tables, max_requests_per_batch,
+                      COPY_QUERIES if copy_queries else 0, budget_bytes)
         h = ctypes.c_void_p()
         _check("rmq_server_create", _lib().rmq_server_create(ctypes.byref(cfg), ctypes.byref(h)))
         self.handle = h

@@ -25,11 +25,12 @@ def check(orc, arrays, reqs):
         assert np.array_equal(out, reference(orc, arrays[tab], L, R)), (tab, L.shape[0])
 
 
-def test_burst_is_coalesced_and_exact(orc):
+@pytest.mark.parametrize("copy", [False, True])
+def test_burst_is_coalesced_and_exact(orc, copy):
     d = need_gpu()
-    say("serve_burst")
+    say("serve_burst", copy)
     arrays = arrays_for(8, 3)
-    with serving.Server(num_streams=3, max_tables=16) as srv:
+    with serving.Server(num_streams=3, max_tables=16, copy_queries=copy) as srv:
         for A in arrays:
             srv.add_array(dev(A, d))
         reqs = serving.make_requests([a.shape[0] for a in arrays], 300, 1, 5e3, 5)
@@ -42,11 +43,12 @@ def test_burst_is_coalesced_and_exact(orc):
         assert np.all(res.latencies_s > 0)
 
 
-def test_alone_equals_in_mix(orc):
+@pytest.mark.parametrize("copy", [False, True])
+def test_alone_equals_in_mix(orc, copy):
     d = need_gpu()
-    say("serve_alone_vs_mix")
+    say("serve_alone_vs_mix", copy)
     arrays = arrays_for(6, 11)
-    with serving.Server(num_streams=4, max_tables=8) as srv:
+    with serving.Server(num_streams=4, max_tables=8, copy_queries=copy) as srv:
         for A in arrays:
             srv.add_array(dev(A, d))
         ns = [a.shape[0] for a in arrays]
@@ -75,7 +77,8 @@ def test_plain_per_request_server_agrees(orc):
     arrays = arrays_for(4, 23)
     ns = [a.shape[0] for a in arrays]
     reqs = serving.make_requests(ns, 60, 1, 3e3, 29)
-    with serving.Server(num_streams=1, max_requests_per_batch=1, max_tables=4) as srv:
+    with serving.Server(num_streams=1, max_requests_per_batch=1, max_tables=4,
+                        copy_queries=True) as srv:
         for A in arrays:
             srv.add_array(dev(A, d))
         serving.run_schedule(srv, reqs, [serving.clock()] * len(reqs))
@@ -84,13 +87,14 @@ def test_plain_per_request_server_agrees(orc):
     check(orc, arrays, reqs)
 
 
-def test_admission_and_invalid_queries(orc):
+@pytest.mark.parametrize("copy", [False, True])
+def test_admission_and_invalid_queries(orc, copy):
     d = need_gpu()
-    say("serve_admission")
+    say("serve_admission", copy)
     arrays = arrays_for(2, 31, 1e4, 2e4)
-    # a small HBM budget: each slot holds only a few thousand queries
+    # a small budget: each slot holds only a few thousand queries
     with serving.Server(num_streams=2, max_tables=2, max_requests_per_batch=64,
-                        hbm_budget_bytes=2 * (3 * 4 * 3000 + 8192)) as srv:
+                        budget_bytes=2 * (3 * 4 * 3000 + 8192), copy_queries=copy) as srv:
         for A in arrays:
             srv.add_array(dev(A, d))
         cap = srv.stats()["slot_capacity"]
