@@ -107,21 +107,26 @@ def main() -> int:
     rmq.load_plan_table()
 
     def k_for(p, q):
+        """(block size, sub-block size) of the batch; sub-block size > 0 is a
+        two-level plan (Section 3.3) chosen by the autotuner."""
         if p == "full":
             if args.k_full:
-                return args.k_full
-            k, path = rmq.plan(n, q)
-            return k if path == "full" else rmq.default_block(n, q, "full")
-        return args.k_con or rmq.default_block(n, q, "contracted")
+                return args.k_full, 0
+            k, path, k1 = rmq.plan_ex(n, q)
+            return (k, k1) if path == "full" else (rmq.default_block(n, q, "full"), 0)
+        return args.k_con or rmq.default_block(n, q, "contracted"), 0
 
-    k_used = {p: {q: k_for(p, q) for q in qs} for p in ("full", "contracted")}
+    plans = {p: {q: k_for(p, q) for q in qs} for p in ("full", "contracted")}
+    k_used = {p: {q: plans[p][q][0] for q in qs} for p in plans}
+    k1_used = {p: {q: plans[p][q][1] for q in qs} for p in plans}
     torch.cuda.synchronize()
 
     def step(timers=None):
         for p in paths:
             for j, q in enumerate(qs):
                 L, R = batches[j]
-                rmq.query_batch(A, L, R, path=p, block_size=k_used[p][q], out=outs[j],
+                rmq.query_batch(A, L, R, path=p, block_size=k_used[p][q],
+                                sub_block_size=k1_used[p][q], out=outs[j],
                                 timer=timers[(p, j)] if timers else None)
 
     if args.copy_calibration:
@@ -151,7 +156,8 @@ def main() -> int:
         for p in paths:
             for j, q in enumerate(qs):
                 L, R = batches[j]
-                got = rmq.query_batch(A, L, R, path=p, block_size=k_used[p][q]).cpu().numpy()
+                got = rmq.query_batch(A, L, R, path=p, block_size=k_used[p][q],
+                                      sub_block_size=k1_used[p][q]).cpu().numpy()
                 exp = orc.rmq_sparse_table(A_h, batches_h[j][0], batches_h[j][1], 32)
                 if not np.array_equal(got, exp):
                     print(f"[bench] MISMATCH path={p} q={q}", file=sys.stderr, flush=True)
@@ -184,10 +190,12 @@ def main() -> int:
             stages = [statistics.median(st[i] for st, _ in per) for i in range(4)]
             breakdown[f"{p}/q={q}"] = {
                 "ms": round(tot, 4), "queries_per_s": round(q / (tot / 1e3), 1),
-                "block_size": k_used[p][q],
+                "block_size": k_used[p][q], "sub_block_size": k1_used[p][q],
                 "stage_ms": {name: round(v, 4) for name, v in zip(rmq.STAGE_NAMES, stages)}}
             if p == "full":
-                blockmin += [(k_used[p][q], st[1]) for st, _ in per]
+                # the pass over A takes the k1-block minima under two levels
+                kb = k1_used[p][q] or k_used[p][q]
+                blockmin += [(kb, st[1]) for st, _ in per]
     roofline = None
     if blockmin:
         # algorithmic bytes of one launch: A once + one 8-byte key per block
@@ -233,10 +241,11 @@ def main() -> int:
             L, R = batches[j]
             for _ in range(args.flushed_reps):
                 scratch.fill_(j)
-                rmq.query_batch(A, L, R, path="full", block_size=k_used["full"][q], out=outs[j],
-                                timer=t_fl)
+                rmq.query_batch(A, L, R, path="full", block_size=k_used["full"][q],
+                                sub_block_size=k1_used["full"][q], out=outs[j], timer=t_fl)
                 ms_fl.append(t_fl.read()[0][1])
-                bytes_fl.append(4 * n + 8 * (-(-n // k_used["full"][q])))
+                kb = k1_used["full"][q] or k_used["full"][q]
+                bytes_fl.append(4 * n + 8 * (-(-n // kb)))
         del scratch
         med = statistics.median(b / (m / 1e3) / 1e9 for b, m in zip(bytes_fl, ms_fl))
         roofline["flushed"] = {"achieved": round(med, 1), "frac": round(med / HBM_PEAK_GBS, 4),
@@ -247,11 +256,11 @@ def main() -> int:
     # structure kept in HBM between batches)
     resident = None
     if not args.no_resident and "full" in paths:
-        k_res = k_used["full"][max(qs)]
+        k_res, k1_res = k_used["full"][max(qs)], k1_used["full"][max(qs)]
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         e0.record(stream)
-        idx = rmq.Index(A, k_res)
+        idx = rmq.Index(A, k_res, sub_block_size=k1_res)
         e1.record(stream)
         torch.cuda.synchronize()
         build_ms = e0.elapsed_time(e1)
@@ -267,7 +276,7 @@ def main() -> int:
                 if r >= 2:
                     reps.append(e0.elapsed_time(e1))
             q_ms[str(q)] = round(statistics.median(reps), 4)
-        resident = {"block_size": k_res, "index_bytes": idx.bytes, "build_ms": round(build_ms, 4),
+        resident = {"block_size": k_res, "sub_block_size": k1_res, "index_bytes": idx.bytes, "build_ms": round(build_ms, 4),
                     "query_ms": q_ms,
                     "queries_per_s": {q: round(int(q) / (ms / 1e3), 1) for q, ms in q_ms.items()}}
         del idx
@@ -319,6 +328,7 @@ def main() -> int:
                                 f"{' and '.join(paths)} method(s)"),
                    "n": n, "q": qs, "paths": paths,
                    "block_size": {p: k_used[p] for p in paths},
+                   "sub_block_size": {p: k1_used[p] for p in paths},
                    "parallelism": "single GPU"},
         "roofline": roofline, "cpu_baseline": cpu, "breakdown": breakdown,
         "resident": resident, "skewed": skewed, "lca": lca, "lary": lary,

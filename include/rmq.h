@@ -160,9 +160,15 @@ rmq_status rmq_query_batch_ex(const int32_t *A, int64_t n, const int32_t *L, con
 size_t rmq_workspace_bytes(int64_t n, int64_t q, const rmq_options *opt);
 
 /* The planner's choice of block size and path for (n, q) -- the automated
- * selection of k that Section 5 leaves as future work.  Either output
- * pointer may be NULL. */
+ * selection of k that Section 5 leaves as future work -- among one-level
+ * plans (what batches use).  Either output pointer may be NULL. */
 rmq_status rmq_plan(int64_t n, int64_t q, int32_t *block_size, int32_t *path);
+
+/* The plan a call with path AUTO and no block sizes takes: as rmq_plan, but
+ * the measured table may also choose two block levels (Section 3.3), given
+ * as *sub_block_size > 0 (0: one level).  Any output pointer may be NULL. */
+rmq_status rmq_plan_ex(int64_t n, int64_t q, int32_t *block_size, int32_t *path,
+                       int32_t *sub_block_size);
 
 /* Measured plans for the planner: for a call with path AUTO, rmq_plan picks
  * the entry nearest to (n, q) in (log2 n, log2 q) and uses its block size and
@@ -171,7 +177,11 @@ rmq_status rmq_plan(int64_t n, int64_t q, int32_t *block_size, int32_t *path);
 typedef struct rmq_plan_entry {
     int64_t n, q;
     int32_t block_size;
-    int32_t path;          /* RMQ_PATH_FULL or RMQ_PATH_CONTRACTED */
+    int32_t path;                 /* RMQ_PATH_FULL or RMQ_PATH_CONTRACTED          */
+    int32_t sub_block_size;       /* > 0: two block levels (FULL only), k1 < k     */
+    int32_t one_level_block_size; /* with two levels: the best one-level k, used
+                                     where two levels are not offered (batches);
+                                     0 = block_size                              */
 } rmq_plan_entry;
 rmq_status rmq_planner_set_table(const rmq_plan_entry *entries, int32_t count);
 

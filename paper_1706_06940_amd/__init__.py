@@ -76,6 +76,8 @@ def lib() -> ctypes.CDLL:
         "rmq_query_batch_ex": ([v, i64, v, v, i64, v, v, opt], i32),
         "rmq_workspace_bytes": ([i64, i64, opt], sz),
         "rmq_plan": ([i64, i64, ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
+        "rmq_plan_ex": ([i64, i64, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                         ctypes.POINTER(i32)], i32),
         "rmq_default_block": ([i64, i64, i32], i32),
         "rmq_build": ([v, i64, opt, v, ctypes.POINTER(v)], i32),
         "rmq_query_index": ([v, v, v, i64, v, v], i32),
@@ -187,7 +189,8 @@ def _options(block_size=0, path="auto", bad_count=None, stats=None, workspace=No
 
 class _PlanEntry(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("q", ctypes.c_int64), ("block_size", ctypes.c_int32),
-                ("path", ctypes.c_int32)]
+                ("path", ctypes.c_int32), ("sub_block_size", ctypes.c_int32),
+                ("one_level_block_size", ctypes.c_int32)]
 
 
 class _BatchItem(ctypes.Structure):
@@ -197,12 +200,17 @@ class _BatchItem(ctypes.Structure):
 
 
 def set_plan_table(entries) -> None:
-    """Install measured plans: iterable of (n, q, block_size, path name).
-    An empty iterable restores the built-in rule."""
+    """Install measured plans: iterable of (n, q, block_size, path name) or
+    (n, q, block_size, path name, sub_block_size, one_level_block_size); a
+    sub_block_size > 0 is a two-level plan (Section 3.3).  An empty iterable
+    restores the built-in rule."""
     entries = list(entries)
     arr = (_PlanEntry * max(len(entries), 1))()
-    for i, (n, q, k, p) in enumerate(entries):
-        arr[i] = _PlanEntry(int(n), int(q), int(k), PATHS[p] if isinstance(p, str) else int(p))
+    for i, e in enumerate(entries):
+        n, q, k, p = e[:4]
+        k1, k_one = (e[4], e[5]) if len(e) > 4 else (0, 0)
+        arr[i] = _PlanEntry(int(n), int(q), int(k), PATHS[p] if isinstance(p, str) else int(p),
+                            int(k1), int(k_one))
     _check("rmq_planner_set_table", lib().rmq_planner_set_table(arr, len(entries)))
 
 
@@ -217,7 +225,8 @@ def load_plan_table(path: str = TUNE_TABLE) -> bool:
         return False
     with open(path) as f:
         data = json.load(f)
-    set_plan_table((e["n"], e["q"], e["block_size"], e["path"]) for e in data["entries"])
+    set_plan_table((e["n"], e["q"], e["block_size"], e["path"], e.get("sub_block_size", 0),
+                    e.get("one_level_block_size", 0)) for e in data["entries"])
     return True
 
 
@@ -226,10 +235,20 @@ def version() -> str:
 
 
 def plan(n: int, q: int):
-    """(block_size, path name) the planner picks for (n, q)."""
+    """(block_size, path name) the planner picks for (n, q) among one-level
+    plans."""
     k, p = ctypes.c_int32(), ctypes.c_int32()
     _check("rmq_plan", lib().rmq_plan(n, q, ctypes.byref(k), ctypes.byref(p)))
     return k.value, {v: k_ for k_, v in PATHS.items()}[p.value]
+
+
+def plan_ex(n: int, q: int):
+    """(block_size, path name, sub_block_size) of a path="auto" call without
+    block sizes; sub_block_size > 0 means two block levels."""
+    k, p, k1 = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check("rmq_plan_ex", lib().rmq_plan_ex(n, q, ctypes.byref(k), ctypes.byref(p),
+                                            ctypes.byref(k1)))
+    return k.value, {v: k_ for k_, v in PATHS.items()}[p.value], k1.value
 
 
 def default_block(n: int, q: int, path: str) -> int:

@@ -105,7 +105,8 @@ int32_t default_block_two_level(int64_t n, int32_t k1) {
   return (int32_t)k;
 }
 
-rmq_status make_plan(int64_t n, int64_t q, const rmq_options* opt, Plan* p) {
+rmq_status make_plan(int64_t n, int64_t q, const rmq_options* opt, Plan* p,
+                     bool allow_two_level = true) {
   int32_t path = opt ? opt->path : RMQ_PATH_AUTO;
   int32_t k = opt ? opt->block_size : 0;
   const int32_t k1 = opt ? opt->sub_block_size : 0;
@@ -128,8 +129,19 @@ rmq_status make_plan(int64_t n, int64_t q, const rmq_options* opt, Plan* p) {
     return RMQ_OK;
   }
   if (path == RMQ_PATH_AUTO) {
-    int32_t pk = 0, pp = 0;
-    rmq_plan(n, q, &pk, &pp);
+    int32_t pk = 0, pp = 0, pk1 = 0;
+    if (k == 0 && allow_two_level) {
+      rmq_plan_ex(n, q, &pk, &pp, &pk1);
+      if (pk1 > 0 && pp == RMQ_PATH_FULL && pk1 < pk) {  // two block levels (Section 3.3)
+        p->path = RMQ_PATH_FULL;
+        p->k = pk;
+        p->kshift = ilog2_i64(pk);
+        p->k1shift = ilog2_i64(pk1);
+        return RMQ_OK;
+      }
+    } else {
+      rmq_plan(n, q, &pk, &pp);
+    }
     path = pp;
     if (k == 0) k = pk;
   }
@@ -205,6 +217,23 @@ std::once_flag g_pool_once[64];
 std::mutex g_table_mu;
 std::vector<rmq_plan_entry> g_table;  // measured plans, see rmq_planner_set_table
 
+// The measured entry nearest to (n, q) in (log2 n, log2 q); the caller holds
+// g_table_mu and has checked that the table is not empty.
+const rmq_plan_entry& nearest_entry(int64_t n, int64_t q) {
+  const double ln = log2((double)n), lq = log2((double)(q > 0 ? q : 1));
+  const rmq_plan_entry* best = &g_table[0];
+  double bd = -1;
+  for (const rmq_plan_entry& e : g_table) {
+    const double dn = log2((double)e.n) - ln, dq = log2((double)e.q) - lq;
+    const double d = dn * dn + dq * dq;
+    if (bd < 0 || d < bd) {
+      best = &e;
+      bd = d;
+    }
+  }
+  return *best;
+}
+
 // Keep freed stream-ordered memory cached in the device pool, so that
 // per-call scratch costs no device allocation after the first call.
 void prepare_pool() {
@@ -263,19 +292,17 @@ rmq_status run_full(const int32_t* A, int64_t n, const int32_t* L, const int32_t
   uint64_t* sub = reinterpret_cast<uint64_t*>(ws + f.off_sub);
   uint64_t* rec = f.rec ? reinterpret_cast<uint64_t*>(ws + f.off_rec) : nullptr;
   const bool two = p.k1shift >= 0;
+  // stage 1 is the one pass over A; with two levels (Section 3.3) it takes
+  // the k1-block minima, and the k-block minima are taken from those in
+  // stage 2 with the table
   stage_begin(t, 1);
-  hipError_t e;
-  if (two) {
-    // Section 3.3: minima of the k1-blocks, then of the k-blocks from them
-    e = launch_blockmin_i32(A, n, p.k1shift, sub, s);
-    if (e == hipSuccess) e = launch_blockmin_keys(sub, f.nb1, p.kshift - p.k1shift, st, s);
-  } else {
-    e = launch_blockmin_i32(A, n, p.kshift, st, s);
-  }
+  hipError_t e = two ? launch_blockmin_i32(A, n, p.k1shift, sub, s)
+                     : launch_blockmin_i32(A, n, p.kshift, st, s);
   if (e != hipSuccess) return from_hip(e);
   stage_end(t, 1, s);
   stage_begin(t, 2);
-  e = build_table(st, f.nb, f.levels, p.lg, s);
+  if (two) e = launch_blockmin_keys(sub, f.nb1, p.kshift - p.k1shift, st, s);
+  if (e == hipSuccess) e = build_table(st, f.nb, f.levels, p.lg, s);
   if (e == hipSuccess && rec) e = launch_records(st, f.nb, f.levels, rec, s);
   if (e != hipSuccess) return from_hip(e);
   stage_end(t, 2, s);
@@ -376,31 +403,33 @@ rmq_status rmq_planner_set_table(const rmq_plan_entry* entries, int32_t count) {
     if (e.n < 1 || e.q < 1 || !is_pow2_block(e.block_size) ||
         (e.path != RMQ_PATH_FULL && e.path != RMQ_PATH_CONTRACTED))
       return RMQ_ERR_INVALID_ARG;
+    if (e.sub_block_size != 0 && (e.path != RMQ_PATH_FULL || !is_pow2_block(e.sub_block_size) ||
+                                  e.sub_block_size >= e.block_size))
+      return RMQ_ERR_INVALID_ARG;
+    if (e.one_level_block_size != 0 && !is_pow2_block(e.one_level_block_size))
+      return RMQ_ERR_INVALID_ARG;
   }
   std::lock_guard<std::mutex> lock(g_table_mu);
   g_table.assign(entries, entries + count);
   return RMQ_OK;
 }
 
-rmq_status rmq_plan(int64_t n, int64_t q, int32_t* block_size, int32_t* path) {
+rmq_status rmq_plan_ex(int64_t n, int64_t q, int32_t* block_size, int32_t* path,
+                       int32_t* sub_block_size) {
   if (n < 1 || n > RMQ_MAX_N || q < 0 || q > RMQ_MAX_Q) return RMQ_ERR_INVALID_ARG;
+  if (sub_block_size) *sub_block_size = 0;
   {
     // measured table: the entry nearest in (log2 n, log2 q)
     std::lock_guard<std::mutex> lock(g_table_mu);
     if (!g_table.empty()) {
-      const double ln = log2((double)n), lq = log2((double)(q > 0 ? q : 1));
-      const rmq_plan_entry* best = nullptr;
-      double bd = 0;
-      for (const rmq_plan_entry& e : g_table) {
-        const double dn = log2((double)e.n) - ln, dq = log2((double)e.q) - lq;
-        const double d = dn * dn + dq * dq;
-        if (!best || d < bd) {
-          best = &e;
-          bd = d;
-        }
-      }
-      if (block_size) *block_size = best->block_size;
+      const rmq_plan_entry* best = &nearest_entry(n, q);
+      // a two-level plan needs k1 < k <= the array (else one level)
+      const bool two = best->sub_block_size > 0 && best->block_size <= n;
+      if (block_size)
+        *block_size = two || best->one_level_block_size == 0 ? best->block_size
+                                                             : best->one_level_block_size;
       if (path) *path = best->path;
+      if (sub_block_size && two) *sub_block_size = best->sub_block_size;
       return RMQ_OK;
     }
   }
@@ -410,6 +439,21 @@ rmq_status rmq_plan(int64_t n, int64_t q, int32_t* block_size, int32_t* path) {
   // the cheaper choice for every batch whose endpoints span A.
   if (block_size) *block_size = default_block_full(n);
   if (path) *path = RMQ_PATH_FULL;
+  return RMQ_OK;
+}
+
+rmq_status rmq_plan(int64_t n, int64_t q, int32_t* block_size, int32_t* path) {
+  int32_t k = 0, p = 0, k1 = 0;
+  const rmq_status st = rmq_plan_ex(n, q, &k, &p, &k1);
+  if (st != RMQ_OK) return st;
+  if (k1 > 0) {
+    // the one-level choice of the same entry
+    std::lock_guard<std::mutex> lock(g_table_mu);
+    const rmq_plan_entry& best = nearest_entry(n, q);
+    k = best.one_level_block_size ? best.one_level_block_size : best.block_size;
+  }
+  if (block_size) *block_size = k;
+  if (path) *path = p;
   return RMQ_OK;
 }
 
@@ -808,7 +852,8 @@ rmq_status rmq_batch_create(const rmq_batch_item* items, int32_t count, rmq_batc
     rmq_options o{};
     o.block_size = items[i].block_size;
     o.path = items[i].path;
-    rmq_status st = make_plan(items[i].n, items[i].q, &o, &b->plans[i]);
+    // one block level: the batched kernels read one level
+    rmq_status st = make_plan(items[i].n, items[i].q, &o, &b->plans[i], false);
     if (st != RMQ_OK) {
       delete b;
       return st;

@@ -161,3 +161,25 @@ def test_plan_table_roundtrip():
         rmq.set_plan_table([])
     k, p = rmq.plan(10 ** 6, 10)
     assert p == "full" and k == rmq.default_block(10 ** 6, 10, "full")
+
+
+def test_plan_table_two_levels():
+    """A two-level entry (Section 3.3) is what path="auto" takes; rmq_plan
+    (and batches) get the entry's one-level block size instead."""
+    rmq.set_plan_table([(10 ** 8, 10 ** 7, 65536, "full", 1024, 8192),
+                        (10 ** 8, 10 ** 3, 4096, "full")])
+    try:
+        assert rmq.plan_ex(10 ** 8, 10 ** 7) == (65536, "full", 1024)
+        assert rmq.plan(10 ** 8, 10 ** 7) == (8192, "full")
+        assert rmq.plan_ex(10 ** 8, 10 ** 3) == (4096, "full", 0)
+        # an array smaller than the entry's k: one level
+        assert rmq.plan_ex(30_000, 10 ** 7) == (8192, "full", 0)
+        # the workspace of an auto call follows the two-level plan
+        two = rmq.workspace_bytes(10 ** 8, 10 ** 7, "auto")
+        assert two == rmq.workspace_bytes(10 ** 8, 10 ** 7, "full", 65536, 1024)
+        for bad in ((10, 10, 1024, "full", 2048, 0), (10, 10, 1024, "contracted", 256, 0),
+                    (10, 10, 1024, "full", 100, 0), (10, 10, 1024, "full", 256, 1000)):
+            with pytest.raises(rmq.RMQError):
+                rmq.set_plan_table([bad])
+    finally:
+        rmq.set_plan_table([])
