@@ -73,6 +73,10 @@ def main() -> int:
                     help="skip the table-over-powers-of-l measurement")
     ap.add_argument("--no-resident", action="store_true",
                     help="skip the resident-index query-only measurement")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the small-instance measurement (n = 2^20, q = 1024)")
+    ap.add_argument("--no-permutation", action="store_true",
+                    help="skip the paper's permutation workload at n = 1e8")
     ap.add_argument("--blockmin-sweep", default="",
                     help="counter-profiling mode: after --copy-calibration, one block-minima "
                          "launch per listed block size on the n-element array, then exit")
@@ -312,6 +316,8 @@ def main() -> int:
 
     del A, batches, outs
     torch.cuda.empty_cache()
+    small = None if args.no_small else bench_small(d)
+    permutation = None if args.no_permutation else bench_permutation(d, qs)
     skewed = None if args.no_skewed else bench_skewed(d)
     lca = None if args.no_lca else bench_lca(d)
     lary = None if args.no_lary else bench_lary(d)
@@ -331,7 +337,8 @@ def main() -> int:
                    "sub_block_size": {p: k1_used[p] for p in paths},
                    "parallelism": "single GPU"},
         "roofline": roofline, "cpu_baseline": cpu, "breakdown": breakdown,
-        "resident": resident, "skewed": skewed, "lca": lca, "lary": lary,
+        "resident": resident, "small": small, "permutation": permutation,
+        "skewed": skewed, "lca": lca, "lary": lary,
         "batched": batched, "served": served,
     }
     print(json.dumps(line), flush=True)
@@ -372,6 +379,96 @@ def time_runs(fn, stream, warmup=2, reps=5):
     e1.record(stream)
     stream.synchronize()
     return e0.elapsed_time(e1) / reps
+
+
+def bench_small(d, warm_reps=20, flushed_reps=7):
+    """The small instance: n = 2^20 uniform int32 (4 MiB, which stays in the
+    L2s and the MALL between calls), q = 1024 uniform swapped queries; both
+    methods over block sizes 256 .. 16384.  Warm: mean of back-to-back whole
+    jobs.  Flushed: median of jobs each after writing 1 GiB of scratch.  Not a
+    bandwidth point: A is cache-resident when warm."""
+    import torch
+
+    import paper_1706_06940_amd as rmq
+    import workloads as W
+
+    n, q = 1 << 20, 1024
+    seed = W.BASE_SEED + 0
+    A = torch.from_numpy(W.uniform_int31(n, seed)).to(d)
+    L_h, R_h = W.uniform_queries(n, q, seed, 1)
+    L, R = torch.from_numpy(L_h).to(d), torch.from_numpy(R_h).to(d)
+    out = torch.empty(q, dtype=torch.int32, device=d)
+    stream = torch.cuda.current_stream(d)
+    scratch = torch.empty(1 << 28, dtype=torch.int32, device=d)
+    t = rmq.Timer()
+    res, ref = {}, None
+    for path in ("full", "contracted"):
+        for k in (256, 1024, 4096, 16384):
+            run = lambda tm=None: rmq.query_batch(A, L, R, path=path, block_size=k, out=out,
+                                                  timer=tm)
+            run()
+            torch.cuda.synchronize()
+            if ref is None:
+                ref = out.clone()
+            same = bool(torch.equal(out, ref))
+            warm = time_runs(run, stream, warmup=2, reps=warm_reps)
+            fl = []
+            for r in range(flushed_reps):
+                scratch.fill_(r)
+                run(t)
+                fl.append(t.read()[1])
+            flushed = statistics.median(fl)
+            res[f"{path}/k={k}"] = {"warm_ms": round(warm, 4), "flushed_ms": round(flushed, 4),
+                                    "warm_queries_per_s": round(q / (warm / 1e3), 1),
+                                    "flushed_queries_per_s": round(q / (flushed / 1e3), 1),
+                                    "same_answers_as_first": same}
+    del A, scratch
+    torch.cuda.empty_cache()
+    return {"workload": "n=2^20 int32 uniform in [0,2^31), q=1024 uniform swapped queries",
+            "results": res}
+
+
+def bench_permutation(d, qs, reps=5):
+    """The paper's own array workload: 1..n after n/2 random pair swaps (no
+    ties), n = 1e8, with uniform swapped queries over the same q sweep; both
+    methods with the planner's block sizes; whole offline jobs (mean of
+    `reps`)."""
+    import torch
+
+    import paper_1706_06940_amd as rmq
+    import workloads as W
+
+    n = 10 ** 8
+    seed = W.BASE_SEED + 6
+    t0 = time.time()
+    A = torch.from_numpy(W.paper_permutation(n, seed)).to(d)
+    print(f"[bench] permutation of {n} drawn in {time.time() - t0:.1f}s", file=sys.stderr,
+          flush=True)
+    stream = torch.cuda.current_stream(d)
+    res = {}
+    for j, q in enumerate(qs):
+        L_h, R_h = W.uniform_queries(n, q, seed, 10 + 2 * j)
+        L, R = torch.from_numpy(L_h).to(d), torch.from_numpy(R_h).to(d)
+        k, path_f, k1 = rmq.plan_ex(n, q)
+        if path_f != "full":
+            k, k1 = rmq.default_block(n, q, "full"), 0
+        outs = {}
+        for path in ("full", "contracted"):
+            kk = k if path == "full" else rmq.default_block(n, q, "contracted")
+            kk1 = k1 if path == "full" else 0
+            out = torch.empty(q, dtype=torch.int32, device=d)
+            run = lambda: rmq.query_batch(A, L, R, path=path, block_size=kk, sub_block_size=kk1,
+                                          out=out)
+            ms = time_runs(run, stream, warmup=2, reps=reps)
+            outs[path] = out
+            res[f"{path}/q={q}"] = {"ms": round(ms, 4), "queries_per_s": round(q / (ms / 1e3), 1),
+                                    "block_size": kk, "sub_block_size": kk1}
+        res[f"full/q={q}"]["same_answers_as_contracted"] = bool(
+            torch.equal(outs["full"], outs["contracted"]))
+    del A
+    torch.cuda.empty_cache()
+    return {"workload": "n=1e8: 1..n after n/2 uniform pair swaps (the paper's array), "
+                        f"q={qs} uniform swapped queries", "results": res}
 
 
 def bench_skewed(d, reps=5):
