@@ -26,7 +26,10 @@
  * queries (extra space is counted apart from A and Q, as in Section 4).  It
  * owns rmq_index objects and, when no workspace is passed, the per-call
  * scratch, which it takes from the device's stream-ordered pool
- * (hipMallocAsync) and returns on the same stream.
+ * (hipMallocAsync) and returns on the same stream.  That scratch is as large
+ * as the largest any earlier call on the device needed (so calls of mixed
+ * sizes reuse one pool block), and the pool keeps freed memory cached; a
+ * caller that must bound device memory passes its own workspace.
  *
  * Streams: `stream` is a hipStream_t passed as void* (NULL = the null
  * stream).  Every call only enqueues work on it and returns; results are

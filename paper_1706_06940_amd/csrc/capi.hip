@@ -4,6 +4,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <atomic>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -235,10 +236,11 @@ const rmq_plan_entry& nearest_entry(int64_t n, int64_t q) {
 }
 
 // Keep freed stream-ordered memory cached in the device pool, so that
-// per-call scratch costs no device allocation after the first call.
-void prepare_pool() {
+// per-call scratch costs no device allocation after the first call.  Returns
+// the device, or -1.
+int prepare_pool() {
   int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return -1;
   std::call_once(g_pool_once[dev], [dev] {
     hipMemPool_t pool;
     if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
@@ -246,6 +248,22 @@ void prepare_pool() {
       hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
     }
   });
+  return dev;
+}
+
+// Size of the per-call scratch taken from the pool: the largest any call on
+// the device has needed so far, so that jobs of different sizes all ask for
+// the same block.  With each job's exact size, a sweep alternating small and
+// large jobs (both methods over q = 1e3 .. 1e7 at n = 1e8) took 3.42 instead
+// of 2.72 ms per 10 jobs.
+std::atomic<size_t> g_scratch_size[64];
+size_t pool_request(int dev, size_t need) {
+  if (dev < 0) return need;
+  size_t cur = g_scratch_size[dev].load(std::memory_order_relaxed);
+  while (cur < need &&
+         !g_scratch_size[dev].compare_exchange_weak(cur, need, std::memory_order_relaxed)) {
+  }
+  return cur > need ? cur : need;
 }
 
 // Stage i of a timed call: kernels launched until stage_end carry the
@@ -491,9 +509,9 @@ rmq_status rmq_query_batch_ex(const int32_t* A, int64_t n, const int32_t* L, con
     if (opt->workspace_bytes < need) return RMQ_ERR_WORKSPACE_SMALL;
     ws = static_cast<char*>(opt->workspace);
   } else {
-    prepare_pool();
+    const int dev = prepare_pool();
     void* w = nullptr;
-    hipError_t e = hipMallocAsync(&w, need, s);
+    hipError_t e = hipMallocAsync(&w, pool_request(dev, need), s);
     if (e != hipSuccess) return from_hip(e);
     ws = static_cast<char*>(w);
     own = true;
