@@ -10,7 +10,8 @@
 //   k_os_clear  -- clears digit totals, tickets and the first status words;
 //   k_os_hist   -- one read of the input: digit totals of every pass at once
 //                  (per workgroup in LDS, then global atomics);
-//   k_os_pass   -- per pass, one workgroup per 4096-item tile, tiles taken in
+//   k_os_pass   -- per pass, one workgroup per tile of 1024, 2048 or 4096
+//                  items (by list length), tiles taken in
 //                  order from an atomic ticket.  The tile ranks its items
 //                  stably (one wave ballot per digit bit gives the lanes that
 //                  share a digit), publishes its per-digit counts at once,
@@ -44,8 +45,12 @@ namespace rmq {
 namespace {
 
 constexpr int WG = 256;
-constexpr int ROUNDS = 16;
-constexpr int TILE = WG * ROUNDS;  // items per tile
+// Items per thread of a tile (a tile is WG * ROUNDS items), chosen by the
+// list length N: small lists take small tiles so that more workgroups share
+// them, long ones large tiles (fewer look-back steps, longer digit runs).
+// Measured sort times of the 2q endpoints at n = 1e8: 4 items per thread is
+// fastest up to q = 3e4, 8 at q = 1e5, 16 from q = 3e5.
+int rounds_for(int64_t N) { return N < 100000 ? 4 : (N < 400000 ? 8 : 16); }
 constexpr int RADIX_BITS = 8;
 constexpr int RADIX = 1 << RADIX_BITS;
 constexpr int NXCD = 8;
@@ -68,6 +73,7 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t num_tiles) {
 }
 int64_t xcd_grid(int64_t num_tiles) { return ((num_tiles + NXCD - 1) / NXCD) * NXCD; }
 
+template <int ROUNDS>
 __device__ __forceinline__ int64_t item_index(int64_t tile0, int wave, int round, int lane) {
   return tile0 + (int64_t)wave * (64 * ROUNDS) + round * 64 + lane;
 }
@@ -168,12 +174,13 @@ __global__ __launch_bounds__(WG) void k_os_clear(uint32_t* __restrict__ hist,
 
 // Digit totals of every pass: per-workgroup counts in LDS over per_group
 // tiles, then one global atomic add per digit.
-template <int MODE>
+template <int MODE, int ROUNDS>
 __global__ __launch_bounds__(WG) void k_os_hist(const uint64_t* __restrict__ items_in,
                                                 const int32_t* __restrict__ L,
                                                 const int32_t* __restrict__ R, int64_t N,
                                                 int64_t n, Digits dg, int per_group,
                                                 uint32_t* __restrict__ hist) {
+  constexpr int TILE = WG * ROUNDS;
   __shared__ uint32_t h[MAX_PASSES][RADIX];
   const int lane = lane_id(), wave = threadIdx.x >> 6;
 #pragma unroll
@@ -185,13 +192,13 @@ __global__ __launch_bounds__(WG) void k_os_hist(const uint64_t* __restrict__ ite
     uint64_t it[ROUNDS];
 #pragma unroll
     for (int rd = 0; rd < ROUNDS; ++rd)
-      it[rd] = load_raw<MODE>(items_in, L, R, N, item_index(tile0, wave, rd, lane));
+      it[rd] = load_raw<MODE>(items_in, L, R, N, item_index<ROUNDS>(tile0, wave, rd, lane));
 #pragma unroll
     for (int rd = 0; rd < ROUNDS; ++rd)
-      it[rd] = finish_item<MODE>(it[rd], n, item_index(tile0, wave, rd, lane));
+      it[rd] = finish_item<MODE>(it[rd], n, item_index<ROUNDS>(tile0, wave, rd, lane));
 #pragma unroll
     for (int rd = 0; rd < ROUNDS; ++rd) {
-      if (item_index(tile0, wave, rd, lane) < N)
+      if (item_index<ROUNDS>(tile0, wave, rd, lane) < N)
         for (int p = 0; p < dg.passes; ++p)
           atomicAdd(&h[p][digit_of(it[rd], dg.shift[p], (1u << dg.bits[p]) - 1u)], 1u);
     }
@@ -221,7 +228,7 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* t
   return total;
 }
 
-template <int MODE>
+template <int MODE, int ROUNDS>
 __global__ __launch_bounds__(WG) void k_os_pass(const uint64_t* __restrict__ items_in,
                                                 const int32_t* __restrict__ L,
                                                 const int32_t* __restrict__ R, int64_t N,
@@ -231,6 +238,7 @@ __global__ __launch_bounds__(WG) void k_os_pass(const uint64_t* __restrict__ ite
                                                 uint32_t* ticket, uint32_t* abort_word,
                                                 uint64_t* __restrict__ items_out,
                                                 int32_t* __restrict__ LR) {
+  constexpr int TILE = WG * ROUNDS;
   __shared__ uint32_t wave_cnt[WG / 64][RADIX];
   __shared__ uint32_t local_start[RADIX];
   __shared__ uint32_t global_start[RADIX];
@@ -417,6 +425,7 @@ int bit_length(uint64_t x) {
 struct SortLayout {
   int64_t N, num_tiles, hist_groups;
   int hist_per_group;
+  int rounds;  // items per thread of a tile
   size_t off_items, off_status0, off_status1, off_hist, off_tickets, off_abort, bytes;
 };
 
@@ -426,7 +435,9 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 SortLayout sort_layout_items(int64_t N) {
   SortLayout s{};
   s.N = N;
-  s.num_tiles = (s.N + TILE - 1) / TILE;
+  s.rounds = rounds_for(N);
+  const int64_t tile = (int64_t)WG * s.rounds;
+  s.num_tiles = (s.N + tile - 1) / tile;
   s.hist_per_group = hist_tiles(s.num_tiles);
   s.hist_groups = (s.num_tiles + s.hist_per_group - 1) / s.hist_per_group;
   size_t o = 0;
@@ -472,13 +483,13 @@ hipError_t clear(const SortLayout& lay, const SortBufs& b, hipStream_t stream) {
 
 // A whole sort: clear, histograms of every pass, then the passes.  Passes
 // alternate between the scratch buffer and `out` so the last lands in `out`.
-template <int MODE>
-hipError_t onesweep(const uint64_t* src, const int32_t* L, const int32_t* R, int64_t N, int64_t n,
-                    const Digits& dg, const SortLayout& lay, const SortBufs& b, uint64_t* out,
-                    int32_t* LR, hipStream_t stream) {
+template <int MODE, int ROUNDS>
+hipError_t onesweep_r(const uint64_t* src, const int32_t* L, const int32_t* R, int64_t N,
+                      int64_t n, const Digits& dg, const SortLayout& lay, const SortBufs& b,
+                      uint64_t* out, int32_t* LR, hipStream_t stream) {
   RMQ_TRY(clear(lay, b, stream));
-  RMQ_TRY(launch(k_os_hist<MODE>, dim3((unsigned)lay.hist_groups), dim3(WG), 0, stream, src, L, R,
-                 N, n, dg, lay.hist_per_group, b.hist));
+  RMQ_TRY(launch(k_os_hist<MODE, ROUNDS>, dim3((unsigned)lay.hist_groups), dim3(WG), 0, stream,
+                 src, L, R, N, n, dg, lay.hist_per_group, b.hist));
   const uint64_t* in = src;
   for (int p = 0; p < dg.passes; ++p) {
     const bool to_out = ((dg.passes - 1 - p) % 2) == 0;
@@ -488,15 +499,42 @@ hipError_t onesweep(const uint64_t* src, const int32_t* L, const int32_t* R, int
     int32_t* lr = p + 1 < dg.passes ? nullptr : LR;
     const dim3 grid((unsigned)lay.num_tiles), block(WG);
     if (p == 0)
-      RMQ_TRY(launch(k_os_pass<MODE>, grid, block, 0, stream, in, L, R, N, n, dg.shift[p],
-                     dg.bits[p], b.hist + p * RADIX, st, st_next, b.tickets + p, b.abort_word,
-                     dst, lr));
+      RMQ_TRY(launch(k_os_pass<MODE, ROUNDS>, grid, block, 0, stream, in, L, R, N, n,
+                     dg.shift[p], dg.bits[p], b.hist + p * RADIX, st, st_next, b.tickets + p,
+                     b.abort_word, dst, lr));
     else
-      RMQ_TRY(launch(k_os_pass<ITEMS>, grid, block, 0, stream, in, L, R, N, n, dg.shift[p],
-                     dg.bits[p], b.hist + p * RADIX, st, st_next, b.tickets + p, b.abort_word,
-                     dst, lr));
+      RMQ_TRY(launch(k_os_pass<ITEMS, ROUNDS>, grid, block, 0, stream, in, L, R, N, n,
+                     dg.shift[p], dg.bits[p], b.hist + p * RADIX, st, st_next, b.tickets + p,
+                     b.abort_word, dst, lr));
     in = dst;
   }
+  return hipSuccess;
+}
+
+template <int MODE>
+hipError_t onesweep(const uint64_t* src, const int32_t* L, const int32_t* R, int64_t N, int64_t n,
+                    const Digits& dg, const SortLayout& lay, const SortBufs& b, uint64_t* out,
+                    int32_t* LR, hipStream_t stream) {
+  switch (lay.rounds) {
+    case 4: return onesweep_r<MODE, 4>(src, L, R, N, n, dg, lay, b, out, LR, stream);
+    case 8: return onesweep_r<MODE, 8>(src, L, R, N, n, dg, lay, b, out, LR, stream);
+    default: return onesweep_r<MODE, 16>(src, L, R, N, n, dg, lay, b, out, LR, stream);
+  }
+}
+
+// One sweep on the top bits of the tag (the stand-alone remap's bucketing).
+template <int ROUNDS>
+hipError_t tag_sweep(const uint64_t* E, const SortLayout& lay, const SortBufs& b,
+                     const Digits& dg, uint64_t* sorted, hipStream_t stream) {
+  RMQ_TRY(clear(lay, b, stream));
+  RMQ_TRY(launch(k_os_hist<E_TAGS, ROUNDS>, dim3((unsigned)lay.hist_groups), dim3(WG), 0, stream,
+                 E, static_cast<const int32_t*>(nullptr), static_cast<const int32_t*>(nullptr),
+                 lay.N, (int64_t)0, dg, lay.hist_per_group, b.hist));
+  RMQ_TRY(launch(k_os_pass<E_TAGS, ROUNDS>, dim3((unsigned)lay.num_tiles), dim3(WG), 0, stream, E,
+                 static_cast<const int32_t*>(nullptr), static_cast<const int32_t*>(nullptr),
+                 lay.N, (int64_t)0, dg.shift[0], dg.bits[0], b.hist, b.status[0],
+                 static_cast<uint64_t*>(nullptr), b.tickets, b.abort_word, sorted,
+                 static_cast<int32_t*>(nullptr)));
   return hipSuccess;
 }
 
@@ -545,15 +583,11 @@ hipError_t launch_remap(const uint64_t* E, int64_t q, int32_t* LR, void* ws, siz
   dg.shift[0] = tbits - top;
   dg.bits[0] = top;
   uint64_t* sorted = b.items;
-  RMQ_TRY(clear(lay, b, stream));
-  RMQ_TRY(launch(k_os_hist<E_TAGS>, dim3((unsigned)lay.hist_groups), dim3(WG), 0, stream, E,
-                 static_cast<const int32_t*>(nullptr), static_cast<const int32_t*>(nullptr),
-                 lay.N, (int64_t)0, dg, lay.hist_per_group, b.hist));
-  RMQ_TRY(launch(k_os_pass<E_TAGS>, dim3((unsigned)lay.num_tiles), dim3(WG), 0, stream, E,
-                 static_cast<const int32_t*>(nullptr), static_cast<const int32_t*>(nullptr),
-                 lay.N, (int64_t)0, dg.shift[0], dg.bits[0], b.hist, b.status[0],
-                 static_cast<uint64_t*>(nullptr), b.tickets, b.abort_word, sorted,
-                 static_cast<int32_t*>(nullptr)));
+  switch (lay.rounds) {
+    case 4: RMQ_TRY(tag_sweep<4>(E, lay, b, dg, sorted, stream)); break;
+    case 8: RMQ_TRY(tag_sweep<8>(E, lay, b, dg, sorted, stream)); break;
+    default: RMQ_TRY(tag_sweep<16>(E, lay, b, dg, sorted, stream)); break;
+  }
   const int64_t chunks = (lay.N + 4 * WG - 1) / (4 * WG);
   RMQ_TRY(launch(k_remap_apply, dim3((unsigned)xcd_grid(chunks)), dim3(WG), 0, stream, sorted,
                  lay.N, LR, chunks));

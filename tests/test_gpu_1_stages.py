@@ -85,7 +85,11 @@ def test_sparse_table_all_levels_small(orc):
 
 
 @pytest.mark.parametrize("n,q", [(1, 1), (10, 7), (1000, 1), (5000, 300), (1 << 20, 1024),
-                                 (1_000_003, 40_000), (100_000, 1 << 17)])
+                                 (1_000_003, 40_000), (100_000, 1 << 17),
+                                 # either side of the tile-size changes at 2q = 1e5 and 4e5
+                                 (1_000_003, 49_999), (1_000_003, 50_000),
+                                 (3_000_017, 199_999), (3_000_017, 200_000),
+                                 (3_000_017, 250_001)])
 def test_sort_endpoints(orc, n, q):
     d = need_gpu()
     say("sort_endpoints", n, q)
