@@ -196,8 +196,8 @@ ConLayout con_layout(int64_t n, int64_t q, int64_t k, int lg, bool records) {
   o = align_up(o + sort_workspace_bytes(q));
   c.off_lr = o;
   o = align_up(o + sizeof(int32_t) * (size_t)c.M);
-  c.off_aq = o;
-  o = align_up(o + sizeof(uint64_t) * (size_t)c.m);
+  c.off_aq = o;  // before the contraction also the remap's pair scratch (2q items)
+  o = align_up(o + sizeof(uint64_t) * (size_t)c.M);
   c.off_tiles = o;
   o = align_up(o + contract_tile_start_bytes(n));
   c.off_st = o;
@@ -351,7 +351,7 @@ rmq_status run_contracted(const int32_t* A, int64_t n, const int32_t* L, const i
   stage_begin(t, 0);
   // the sort's last pass writes the remap as well
   hipError_t e =
-      launch_sort_endpoints(L, R, q, n, E, LR, ws + c.off_sort, sort_workspace_bytes(q), s);
+      launch_sort_endpoints(L, R, q, n, E, LR, aq, ws + c.off_sort, sort_workspace_bytes(q), s);
   if (e != hipSuccess) return from_hip(e);
   stage_end(t, 0, s);
   stage_begin(t, 1);
@@ -706,7 +706,7 @@ rmq_status rmq_sort_endpoints(const int32_t* L, const int32_t* R, int64_t q, int
   hipStream_t s = static_cast<hipStream_t>(stream);
   const size_t sort_b = align_up(sort_workspace_bytes(q));
   uint64_t* E = reinterpret_cast<uint64_t*>(static_cast<char*>(workspace) + sort_b);
-  hipError_t e = launch_sort_endpoints(L, R, q, n, E, nullptr, workspace, sort_b, s);
+  hipError_t e = launch_sort_endpoints(L, R, q, n, E, nullptr, nullptr, workspace, sort_b, s);
   if (e == hipSuccess) e = launch_unpack_endpoints(E, q, pos, tag, s);
   return from_hip(e);
 }

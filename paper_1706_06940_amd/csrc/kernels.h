@@ -139,11 +139,12 @@ hipError_t launch_query_full2(const int32_t* A, int64_t n, int kshift, const uin
 // ---- contracted path (Section 3.1) ----
 // Device LSD radix sort of the 2q endpoints by (position, tag).  The sorted
 // list E holds (position << 32) | tag per slot.  With LR non-null the last
-// pass also writes the remap (as launch_remap does).
+// pass also writes the remap (as launch_remap does); pair_scratch, when
+// given, is 2q 8-byte items through which long sorts stage the remap.
 size_t sort_workspace_bytes(int64_t q);
 hipError_t launch_sort_endpoints(const int32_t* L, const int32_t* R, int64_t q, int64_t n,
-                                 uint64_t* E, int32_t* LR, void* ws, size_t ws_bytes,
-                                 hipStream_t stream);
+                                 uint64_t* E, int32_t* LR, uint64_t* pair_scratch, void* ws,
+                                 size_t ws_bytes, hipStream_t stream);
 // Remap: LR[2i] = Lc[i], LR[2i+1] = Rc[i] from the sorted list; uses the
 // sort's workspace.
 hipError_t launch_remap(const uint64_t* E, int64_t q, int32_t* LR, void* ws, size_t ws_bytes,

@@ -32,7 +32,11 @@
 //
 // Remap: slot s of the sorted list holding tag t gives Lc[t/2] = s (t even)
 // or Rc[t/2] = s - 1 (t odd).  Inside the whole pipeline the last sort pass
-// writes these 2q scattered 4-byte stores itself, as it places each item.
+// writes these 2q scattered 4-byte stores itself, as it places each item;
+// for long lists (2q >= 2^22) it instead writes each tile's (tag, slot)
+// pairs grouped by window of 32768 tags, and k_remap_windows assembles each
+// window of LR in LDS and writes it out whole (a scattered 4-byte store
+// costs a partial write to HBM once LR outgrows the L2s).
 // The stand-alone remap (from a given sorted list) instead orders the
 // (tag, slot) pairs by the top bits of the tag with one more sweep and then
 // writes window by window, each window of the interleaved LR array while it
@@ -228,16 +232,30 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* t
   return total;
 }
 
-template <int MODE, int ROUNDS>
-__global__ __launch_bounds__(WG) void k_os_pass(const uint64_t* __restrict__ items_in,
-                                                const int32_t* __restrict__ L,
-                                                const int32_t* __restrict__ R, int64_t N,
-                                                int64_t n, int shift, int bits,
-                                                const uint32_t* __restrict__ hist,
-                                                uint64_t* status, uint64_t* status_next,
-                                                uint32_t* ticket, uint32_t* abort_word,
-                                                uint64_t* __restrict__ items_out,
-                                                int32_t* __restrict__ LR) {
+// The remap through LR windows (the last pass of long endpoint sorts): tags
+// fall into windows of 2^WIN_SHIFT consecutive tags (128 KiB of LR); the
+// last pass writes each tile's (tag << 32 | slot) pairs grouped by window
+// into the tile's own range of a pair buffer, with the window offsets in a
+// row of `pre`, and k_remap_windows then builds each window of LR in LDS
+// and writes it out whole.
+constexpr int WIN_SHIFT = 15;
+constexpr int WIN = 1 << WIN_SHIFT;
+constexpr int MAX_WINDOWS = 1024;       // windows of one sort (LDS counters of the pass)
+constexpr int WIN_MAX_TILES = 6144;     // tiles whose runs a window workgroup keeps in LDS
+constexpr int64_t WIN_MIN_N = 1 << 22;  // shorter lists keep the scattered stores
+
+// One pass over a tile (see the top of this file).  WINDOWS: the last pass
+// of a long endpoint sort, which also writes the tile's remap pairs.
+template <int MODE, int ROUNDS, bool WINDOWS>
+__device__ __forceinline__ void os_pass(const uint64_t* __restrict__ items_in,
+                                        const int32_t* __restrict__ L,
+                                        const int32_t* __restrict__ R, int64_t N, int64_t n,
+                                        int shift, int bits, const uint32_t* __restrict__ hist,
+                                        uint64_t* status, uint64_t* status_next,
+                                        uint32_t* ticket, uint32_t* abort_word,
+                                        uint64_t* __restrict__ items_out,
+                                        int32_t* __restrict__ LR, uint64_t* __restrict__ pairs,
+                                        uint16_t* __restrict__ pre, int nwin) {
   constexpr int TILE = WG * ROUNDS;
   __shared__ uint32_t wave_cnt[WG / 64][RADIX];
   __shared__ uint32_t local_start[RADIX];
@@ -245,12 +263,17 @@ __global__ __launch_bounds__(WG) void k_os_pass(const uint64_t* __restrict__ ite
   __shared__ uint32_t tmp[WG / 64];
   __shared__ uint64_t s_item[TILE];
   __shared__ uint32_t s_tile;
+  __shared__ uint32_t s_wcnt[WINDOWS ? MAX_WINDOWS : 1];  // pairs per window, then offsets
 
   const int lane = lane_id(), wave = threadIdx.x >> 6;
   const uint32_t total = hist[threadIdx.x];  // in flight with the ticket
   if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
 #pragma unroll
   for (int w = 0; w < WG / 64; ++w) wave_cnt[w][threadIdx.x] = 0;
+  if (WINDOWS) {
+#pragma unroll
+    for (int i = 0; i < MAX_WINDOWS / WG; ++i) s_wcnt[i * WG + threadIdx.x] = 0;
+  }
   // digit offsets of this pass: exclusive scan of the digit totals
   uint32_t digit_base;
   block_exclusive_scan(total, tmp, digit_base);
@@ -365,18 +388,195 @@ __global__ __launch_bounds__(WG) void k_os_pass(const uint64_t* __restrict__ ite
   __syncthreads();
 
   const int64_t tile_n = N - tile0 < TILE ? N - tile0 : TILE;
-  for (int t = threadIdx.x; t < tile_n; t += WG) {
+  if (!WINDOWS) {
+    for (int t = threadIdx.x; t < tile_n; t += WG) {
+      const uint64_t x = s_item[t];
+      const uint32_t dd = digit_of(x, shift, mask);
+      const uint32_t dst = global_start[dd] + (uint32_t)t - local_start[dd];
+      if ((int64_t)dst < N) {  // always true for consistent counts
+        items_out[dst] = x;
+        // last pass of the endpoint sort: the remap, LR[tag] = slot (minus
+        // one for a right end), written here directly
+        const uint32_t g = (uint32_t)x;
+        if (LR && (int64_t)g < N) LR[g] = (g & 1u) ? (int32_t)dst - 1 : (int32_t)dst;
+      }
+    }
+    return;
+  }
+  // ---- WINDOWS: the items as above, and each item's (tag, slot) pair
+  // ranked inside its window by an LDS counter ----
+  uint64_t pr[ROUNDS];     // (tag << 32) | slot
+  uint32_t pr_at[ROUNDS];  // rank inside the window; TILE = not placed
+#pragma unroll
+  for (int i = 0; i < ROUNDS; ++i) {
+    const int t = i * WG + threadIdx.x;
+    pr[i] = 0;
+    pr_at[i] = TILE;
+    if (t >= tile_n) continue;
     const uint64_t x = s_item[t];
     const uint32_t dd = digit_of(x, shift, mask);
     const uint32_t dst = global_start[dd] + (uint32_t)t - local_start[dd];
-    if ((int64_t)dst < N) {  // always true for consistent counts
-      items_out[dst] = x;
-      // last pass of the endpoint sort: the remap, LR[tag] = slot (minus
-      // one for a right end), written here directly
-      const uint32_t g = (uint32_t)x;
-      if (LR && (int64_t)g < N) LR[g] = (g & 1u) ? (int32_t)dst - 1 : (int32_t)dst;
+    if ((int64_t)dst >= N) continue;  // never, for consistent counts
+    items_out[dst] = x;
+    const uint32_t g = (uint32_t)x;
+    const uint32_t w = min(g >> WIN_SHIFT, (uint32_t)nwin - 1u);
+    pr[i] = ((uint64_t)g << 32) | dst;
+    pr_at[i] = atomicAdd(&s_wcnt[w], 1u);
+  }
+  __syncthreads();  // counts final; s_item free again
+  // window offsets inside the tile: thread u scans windows 4u .. 4u + 3
+  constexpr int WPT = MAX_WINDOWS / WG;
+  uint32_t c[WPT], sum = 0;
+#pragma unroll
+  for (int k = 0; k < WPT; ++k) {
+    c[k] = s_wcnt[threadIdx.x * WPT + k];
+    sum += c[k];
+  }
+  uint32_t off;
+  block_exclusive_scan(sum, tmp, off);
+  // start of window w's run in this tile: pre[w * num_tiles + tile], window
+  // by window, so that a window's workgroup reads one contiguous column
+  // (column nwin: the end of the last run)
+  const int64_t num_tiles = (N + TILE - 1) / TILE;
+#pragma unroll
+  for (int k = 0; k < WPT; ++k) {
+    const int w = threadIdx.x * WPT + k;
+    if (w <= nwin) pre[w * num_tiles + tile] = (uint16_t)off;
+    s_wcnt[w] = off;
+    off += c[k];
+  }
+  if (threadIdx.x == WG - 1 && nwin == MAX_WINDOWS) pre[nwin * num_tiles + tile] = (uint16_t)off;
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < ROUNDS; ++i) {
+    if (pr_at[i] >= (uint32_t)TILE) continue;
+    const uint32_t w = min((uint32_t)(pr[i] >> 32) >> WIN_SHIFT, (uint32_t)nwin - 1u);
+    const uint32_t at = s_wcnt[w] + pr_at[i];
+    if (at < (uint32_t)TILE) s_item[at] = pr[i];  // always true
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < ROUNDS; ++i) {
+    const int t = i * WG + threadIdx.x;
+    if (t < tile_n) pairs[tile0 + t] = s_item[t];
+  }
+}
+
+template <int MODE, int ROUNDS>
+__global__ __launch_bounds__(WG) void k_os_pass(const uint64_t* __restrict__ items_in,
+                                                const int32_t* __restrict__ L,
+                                                const int32_t* __restrict__ R, int64_t N,
+                                                int64_t n, int shift, int bits,
+                                                const uint32_t* __restrict__ hist,
+                                                uint64_t* status, uint64_t* status_next,
+                                                uint32_t* ticket, uint32_t* abort_word,
+                                                uint64_t* __restrict__ items_out,
+                                                int32_t* __restrict__ LR) {
+  os_pass<MODE, ROUNDS, false>(items_in, L, R, N, n, shift, bits, hist, status, status_next,
+                               ticket, abort_word, items_out, LR, nullptr, nullptr, 1);
+}
+
+// The last pass of a long endpoint sort (4096-item tiles), remap through
+// LR windows.  Its own kernel, so that the registers the pairs take do not
+// lower the occupancy of the other passes.
+template <int MODE>
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) void k_os_pass_windows(
+    const uint64_t* __restrict__ items_in, const int32_t* __restrict__ L,
+    const int32_t* __restrict__ R, int64_t N, int64_t n, int shift, int bits,
+    const uint32_t* __restrict__ hist, uint64_t* status, uint32_t* ticket, uint32_t* abort_word,
+    uint64_t* __restrict__ items_out, uint64_t* __restrict__ pairs, uint16_t* __restrict__ pre,
+    int nwin) {
+  os_pass<MODE, 16, true>(items_in, L, R, N, n, shift, bits, hist, status, nullptr, ticket,
+                          abort_word, items_out, nullptr, pairs, pre, nwin);
+}
+
+// LR window w (tags [w * WIN, (w + 1) * WIN)) from the pairs of every tile:
+// tile j's run for the window is pairs[j * 4096 + pre[w][j] .. j * 4096 +
+// pre[w + 1][j]).  The runs' bounds (two contiguous columns of pre) go to
+// LDS first; then each wave takes 64 / lpt tiles per load, lpt lanes per
+// tile (lpt: a power of two near the mean run length), U such loads in
+// flight per lane, and writes the entries into the LDS image of the window;
+// the image is written to LR with coalesced stores.  Every tag of the
+// window occurs in exactly one pair, so the image is complete.
+// (At 2q = 2e7 it fetches 1.25x the pair bytes from HBM; with the windows
+// spread over the XCDs it fetched 3.6x.)
+constexpr int AWG = 1024;  // threads of a window workgroup
+constexpr int WIN_TILE = 4096;
+__global__ __launch_bounds__(AWG) void k_remap_windows(const uint64_t* __restrict__ pairs,
+                                                       const uint16_t* __restrict__ pre,
+                                                       int64_t num_tiles, int nwin, int lpt_shift,
+                                                       int64_t N, int32_t* __restrict__ LR) {
+  __shared__ int32_t win[WIN];
+  __shared__ uint32_t runs[WIN_MAX_TILES];  // start | end << 16
+  // XCD x takes the x-th contiguous range of windows: neighbouring windows
+  // run together on one XCD and share, in its L2, the cache lines where
+  // their runs meet
+  const int64_t wx = xcd_tile(nwin);
+  if (wx < 0) return;  // whole workgroup
+  const int w = (int)wx;
+  const int64_t wbase = (int64_t)w << WIN_SHIFT;
+  {
+    constexpr int PER = (WIN_MAX_TILES + AWG - 1) / AWG;
+    const uint16_t* c0 = pre + (int64_t)w * num_tiles;
+    const uint16_t* c1 = c0 + num_tiles;
+    uint32_t r[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int64_t j = threadIdx.x + (int64_t)k * AWG;
+      r[k] = j < num_tiles ? (uint32_t)c0[j] | ((uint32_t)c1[j] << 16) : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int64_t j = threadIdx.x + (int64_t)k * AWG;
+      if (j < num_tiles) runs[j] = r[k];
     }
   }
+  __syncthreads();
+  const int lane = lane_id(), wave = threadIdx.x >> 6;
+  const int lpt = 1 << lpt_shift;                   // lanes per tile
+  const int sub = lane & (lpt - 1), tj = lane >> lpt_shift;
+  const int64_t per_load = 64 >> lpt_shift;         // tiles per wave load
+  auto put = [&](uint64_t x) {
+    const uint32_t t = (uint32_t)(x >> 32), slot = (uint32_t)x;
+    const int64_t at = (int64_t)t - wbase;
+    if (at >= 0 && at < WIN) win[at] = (t & 1u) ? (int32_t)slot - 1 : (int32_t)slot;
+  };
+  constexpr int U = 8;
+  const int64_t stride = (AWG / 64) * per_load;     // tiles per round of the block's waves
+  for (int64_t j0 = wave * per_load; j0 < num_tiles; j0 += stride * U) {
+    uint64_t v[U];
+    uint32_t se[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t j = j0 + (int64_t)u * stride + tj;
+      se[u] = j < num_tiles ? runs[j] : 0u;
+      const uint32_t s0 = se[u] & 0xFFFFu, e0 = se[u] >> 16;
+      v[u] = s0 + sub < e0 ? pairs[j * WIN_TILE + s0 + sub] : ~0ull;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (v[u] != ~0ull) put(v[u]);
+    // runs longer than lpt (about a quarter of them): their next lpt
+    // entries, all of the round's loads at once
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t j = j0 + (int64_t)u * stride + tj;
+      const uint32_t s0 = se[u] & 0xFFFFu, e0 = se[u] >> 16;
+      v[u] = s0 + lpt + sub < e0 ? pairs[j * WIN_TILE + s0 + lpt + sub] : ~0ull;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (v[u] != ~0ull) put(v[u]);
+    // runs longer than 2 lpt (rare)
+    for (int u = 0; u < U; ++u) {
+      const int64_t j = j0 + (int64_t)u * stride + tj;
+      const uint32_t s0 = se[u] & 0xFFFFu, e0 = se[u] >> 16;
+      for (uint32_t i = s0 + 2 * lpt + sub; i < e0; i += lpt) put(pairs[j * WIN_TILE + i]);
+    }
+  }
+  __syncthreads();
+  const int64_t len = N - wbase < WIN ? N - wbase : WIN;
+  for (int64_t i = threadIdx.x; i < len; i += AWG) LR[wbase + i] = win[i];
 }
 
 // Remap writes from (tag, slot) items ordered by the top bits of the tag.
@@ -426,7 +626,8 @@ struct SortLayout {
   int64_t N, num_tiles, hist_groups;
   int hist_per_group;
   int rounds;  // items per thread of a tile
-  size_t off_items, off_status0, off_status1, off_hist, off_tickets, off_abort, bytes;
+  int nwin;    // LR windows of the remap, 0 = scattered remap stores
+  size_t off_items, off_status0, off_status1, off_hist, off_tickets, off_abort, off_pre, bytes;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -452,6 +653,12 @@ SortLayout sort_layout_items(int64_t N) {
   s.off_hist = take(sizeof(uint32_t) * (size_t)MAX_PASSES * RADIX);
   s.off_tickets = take(sizeof(uint32_t) * MAX_PASSES);
   s.off_abort = take(sizeof(uint32_t));
+  const int64_t nwin = (N + WIN - 1) / WIN;
+  s.nwin = N >= WIN_MIN_N && s.rounds == 16 && s.num_tiles <= WIN_MAX_TILES &&
+                   nwin <= MAX_WINDOWS
+               ? (int)nwin
+               : 0;
+  s.off_pre = take(sizeof(uint16_t) * (size_t)(s.nwin + 1) * (size_t)s.num_tiles);
   s.bytes = o;
   return s;
 }
@@ -460,6 +667,7 @@ struct SortBufs {
   uint64_t* items;
   uint64_t* status[2];
   uint32_t *hist, *tickets, *abort_word;
+  uint16_t* pre;
 };
 
 SortBufs sort_bufs(const SortLayout& lay, void* ws) {
@@ -471,6 +679,7 @@ SortBufs sort_bufs(const SortLayout& lay, void* ws) {
   b.hist = reinterpret_cast<uint32_t*>(base + lay.off_hist);
   b.tickets = reinterpret_cast<uint32_t*>(base + lay.off_tickets);
   b.abort_word = reinterpret_cast<uint32_t*>(base + lay.off_abort);
+  b.pre = reinterpret_cast<uint16_t*>(base + lay.off_pre);
   return b;
 }
 
@@ -486,7 +695,9 @@ hipError_t clear(const SortLayout& lay, const SortBufs& b, hipStream_t stream) {
 template <int MODE, int ROUNDS>
 hipError_t onesweep_r(const uint64_t* src, const int32_t* L, const int32_t* R, int64_t N,
                       int64_t n, const Digits& dg, const SortLayout& lay, const SortBufs& b,
-                      uint64_t* out, int32_t* LR, hipStream_t stream) {
+                      uint64_t* out, int32_t* LR, uint64_t* pairs, hipStream_t stream) {
+  // the remap through LR windows: a long list, 4096-item tiles, and pair scratch
+  const bool windows = LR && pairs && lay.nwin > 0 && ROUNDS == 16;
   RMQ_TRY(clear(lay, b, stream));
   RMQ_TRY(launch(k_os_hist<MODE, ROUNDS>, dim3((unsigned)lay.hist_groups), dim3(WG), 0, stream,
                  src, L, R, N, n, dg, lay.hist_per_group, b.hist));
@@ -498,7 +709,24 @@ hipError_t onesweep_r(const uint64_t* src, const int32_t* L, const int32_t* R, i
     uint64_t* st_next = p + 1 < dg.passes ? b.status[(p + 1) & 1] : nullptr;
     int32_t* lr = p + 1 < dg.passes ? nullptr : LR;
     const dim3 grid((unsigned)lay.num_tiles), block(WG);
-    if (p == 0)
+    if (windows && p + 1 == dg.passes) {
+      if (p == 0)
+        RMQ_TRY(launch(k_os_pass_windows<MODE>, grid, block, 0, stream, in, L, R, N, n,
+                       dg.shift[p], dg.bits[p], b.hist + p * RADIX, st, b.tickets + p,
+                       b.abort_word, dst, pairs, b.pre, lay.nwin));
+      else
+        RMQ_TRY(launch(k_os_pass_windows<ITEMS>, grid, block, 0, stream, in, L, R, N, n,
+                       dg.shift[p], dg.bits[p], b.hist + p * RADIX, st, b.tickets + p,
+                       b.abort_word, dst, pairs, b.pre, lay.nwin));
+      // lanes per tile: the power of two at or above the mean run length
+      // (4096 * WIN / N pairs), between 4 and 64
+      const double mean_run = (double)WIN_TILE * WIN / (double)N;
+      int lpt_shift = 2;
+      while (lpt_shift < 6 && (double)(1 << lpt_shift) < mean_run) ++lpt_shift;
+      RMQ_TRY(launch(k_remap_windows, dim3((unsigned)xcd_grid(lay.nwin)), dim3(AWG), 0, stream,
+                     static_cast<const uint64_t*>(pairs), static_cast<const uint16_t*>(b.pre),
+                     lay.num_tiles, lay.nwin, lpt_shift, N, LR));
+    } else if (p == 0)
       RMQ_TRY(launch(k_os_pass<MODE, ROUNDS>, grid, block, 0, stream, in, L, R, N, n,
                      dg.shift[p], dg.bits[p], b.hist + p * RADIX, st, st_next, b.tickets + p,
                      b.abort_word, dst, lr));
@@ -514,11 +742,11 @@ hipError_t onesweep_r(const uint64_t* src, const int32_t* L, const int32_t* R, i
 template <int MODE>
 hipError_t onesweep(const uint64_t* src, const int32_t* L, const int32_t* R, int64_t N, int64_t n,
                     const Digits& dg, const SortLayout& lay, const SortBufs& b, uint64_t* out,
-                    int32_t* LR, hipStream_t stream) {
+                    int32_t* LR, uint64_t* pairs, hipStream_t stream) {
   switch (lay.rounds) {
-    case 4: return onesweep_r<MODE, 4>(src, L, R, N, n, dg, lay, b, out, LR, stream);
-    case 8: return onesweep_r<MODE, 8>(src, L, R, N, n, dg, lay, b, out, LR, stream);
-    default: return onesweep_r<MODE, 16>(src, L, R, N, n, dg, lay, b, out, LR, stream);
+    case 4: return onesweep_r<MODE, 4>(src, L, R, N, n, dg, lay, b, out, LR, pairs, stream);
+    case 8: return onesweep_r<MODE, 8>(src, L, R, N, n, dg, lay, b, out, LR, pairs, stream);
+    default: return onesweep_r<MODE, 16>(src, L, R, N, n, dg, lay, b, out, LR, pairs, stream);
   }
 }
 
@@ -553,19 +781,19 @@ hipError_t launch_sort_pairs(const uint64_t* items, int64_t N, int key_bits, uin
   if (ws_bytes < lay.bytes || key_bits < 1 || key_bits > 32) return hipErrorInvalidValue;
   const SortBufs b = sort_bufs(lay, ws);
   return onesweep<ITEMS>(items, nullptr, nullptr, N, 0, split_digits(0, key_bits), lay, b, out,
-                         nullptr, stream);
+                         nullptr, nullptr, stream);
 }
 
 hipError_t launch_sort_endpoints(const int32_t* L, const int32_t* R, int64_t q, int64_t n,
-                                 uint64_t* E, int32_t* LR, void* ws, size_t ws_bytes,
-                                 hipStream_t stream) {
+                                 uint64_t* E, int32_t* LR, uint64_t* pair_scratch, void* ws,
+                                 size_t ws_bytes, hipStream_t stream) {
   if (q <= 0) return hipSuccess;
   const SortLayout lay = sort_layout(q);
   if (ws_bytes < lay.bytes) return hipErrorInvalidValue;
   const SortBufs b = sort_bufs(lay, ws);
   const int nbits = n > 1 ? bit_length((uint64_t)(n - 1)) : 1;
   return onesweep<QUERIES>(nullptr, L, R, lay.N, n, split_digits(0, nbits), lay, b, E, LR,
-                           stream);
+                           pair_scratch, stream);
 }
 
 hipError_t launch_remap(const uint64_t* E, int64_t q, int32_t* LR, void* ws, size_t ws_bytes,

@@ -171,3 +171,24 @@ def test_workspace_and_timer(orc):
             small = torch.empty(max(wsb // 2, 256), dtype=torch.uint8, device=d)
             rmq.query_batch(dev(A, d), dev(L, d), dev(R, d), path=path, block_size=k,
                             workspace=small)
+
+
+# The contracted path's remap for long endpoint lists goes through LR windows
+# of 32768 tags built in LDS (2q >= 2^22, up to 6144 tiles of 4096 items);
+# shorter lists write LR with scattered stores.  Both sides of the switch,
+# a ragged last window, the single-pass sort (n <= 256: the first pass is
+# also the last) and the longest list the windows take.
+@pytest.mark.parametrize("n,q", [(3_000_017, 2_097_151), (3_000_017, 2_097_152),
+                                 (10_000_019, 2_100_007), (200, 2_200_001),
+                                 (50_000_017, 12_000_007)])
+def test_contracted_remap_windows(orc, n, q):
+    d = need_gpu()
+    say("remap_windows", n, q)
+    A = W.uniform_int31(n, n + q)
+    L, R = W.uniform_queries(n, q, n + q, 5)
+    L[:3] = R[:3] = n // 2          # repeated single-point queries
+    L[3], R[3] = n - 1, 0           # an invalid query: sorts as position 0
+    L[4], R[4] = 0, n - 1
+    exp = reference(orc, A, L, R)  # -1 for the invalid one
+    got = host(rmq.query_batch(dev(A, d), dev(L, d), dev(R, d), path="contracted"))
+    assert np.array_equal(got, exp), (n, q)
