@@ -125,8 +125,10 @@ typedef struct rmq_options {
                                  doubling table. */
     int32_t no_query_records; /* nonzero: do not build query records.  By
                                  default a doubling table of nb blocks and L
-                                 levels also gets, when 32 * nb * L bytes <=
-                                 8 MiB, two records per block: for every
+                                 levels with one block level (no
+                                 sub_block_size) also gets, when
+                                 32 * nb * L bytes <= 8 MiB, two records per
+                                 block: for every
                                  level t, the block's minimum paired with the
                                  window of 2^t blocks starting just after it,
                                  and paired with the window ending just
@@ -241,8 +243,8 @@ size_t rmq_index_bytes(int64_t n, int32_t block_size);
 /* Number of Sparse Table levels for nb blocks (see rmq_index_bytes). */
 int32_t rmq_table_levels(int64_t num_blocks);
 
-/* Bytes of the query records built beside a doubling table of nb blocks
- * (see rmq_options.no_query_records); 0 when none are built. */
+/* Bytes of the query records built beside a one-level doubling table of nb
+ * blocks (see rmq_options.no_query_records); 0 when none are built. */
 size_t rmq_query_record_bytes(int64_t num_blocks);
 
 /* Levels of the table over powers of l = 2^table_arity_log2 (Section 3.1;

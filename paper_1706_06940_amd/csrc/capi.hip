@@ -79,12 +79,14 @@ struct Plan {
 };
 
 // Query records (see launch_records) for a doubling table of nb blocks and
-// `levels` levels: whether they are built (not for another arity, nor above
-// kMaxRecordBytes), and their bytes.
+// `levels` levels: whether they are built (not for another arity, not under
+// two block levels, nor above kMaxRecordBytes), and their bytes.  Measured
+// at n = 1e8 on the planner's two-level plans, whole jobs were faster
+// without them (q = 1e5: 0.083 vs 0.086 ms, q = 1e7: 0.162 vs 0.170 ms).
 constexpr size_t kMaxRecordBytes = 8u << 20;  // measured: larger records lose to L2 misses
 size_t records_bytes(int64_t nb, int levels) { return sizeof(uint64_t) * 4 * (size_t)nb * levels; }
-bool records_built(int64_t nb, int levels, int lg, bool allowed) {
-  return allowed && lg <= 1 && records_bytes(nb, levels) <= kMaxRecordBytes;
+bool records_built(int64_t nb, int levels, int lg, bool allowed, bool two_level) {
+  return allowed && !two_level && lg <= 1 && records_bytes(nb, levels) <= kMaxRecordBytes;
 }
 
 // opt->table_arity_log2 as lg (0 and 1 both mean doubling); -1 if invalid.
@@ -166,7 +168,7 @@ FullLayout full_layout(int64_t n, int64_t k, int k1shift, int lg, bool records) 
   FullLayout f{};
   f.nb = num_blocks(n, k);
   f.levels = table_levels(f.nb, lg);
-  f.rec = records_built(f.nb, f.levels, lg, records);
+  f.rec = records_built(f.nb, f.levels, lg, records, k1shift >= 0);
   f.off_st = 0;
   f.off_sub = align_up(sizeof(uint64_t) * (size_t)f.nb * (size_t)f.levels);
   f.nb1 = k1shift >= 0 ? num_blocks(n, 1ll << k1shift) : 0;
@@ -188,7 +190,7 @@ ConLayout con_layout(int64_t n, int64_t q, int64_t k, int lg, bool records) {
   c.m = c.M - 1;
   c.nb = num_blocks(c.m, k);
   c.levels = table_levels(c.nb, lg);
-  c.rec = records_built(c.nb, c.levels, lg, records);
+  c.rec = records_built(c.nb, c.levels, lg, records, false);
   size_t o = 0;
   c.off_E = o;
   o = align_up(o + sizeof(uint64_t) * (size_t)c.M);
@@ -400,7 +402,7 @@ int32_t rmq_table_levels(int64_t nb) {
 size_t rmq_query_record_bytes(int64_t nb) {
   if (nb < 1 || nb > RMQ_MAX_N) return 0;
   const int lv = rmq_table_levels(nb);
-  return records_built(nb, lv, 1, true) ? records_bytes(nb, lv) : 0;
+  return records_built(nb, lv, 1, true, false) ? records_bytes(nb, lv) : 0;
 }
 
 int32_t rmq_table_levels_ary(int64_t nb, int32_t table_arity_log2) {
@@ -557,7 +559,8 @@ rmq_status rmq_build(const int32_t* A, int64_t n, const rmq_options* opt, void* 
   ix->levels = table_levels(ix->nb, lg);
   ix->k1shift = k1 != 0 ? ilog2_i64(k1) : -1;
   ix->nb1 = k1 != 0 ? num_blocks(n, k1) : 0;
-  const bool with_rec = records_built(ix->nb, ix->levels, lg, !(opt && opt->no_query_records));
+  const bool with_rec =
+      records_built(ix->nb, ix->levels, lg, !(opt && opt->no_query_records), k1 != 0);
   const size_t table_bytes = sizeof(uint64_t) * (size_t)ix->nb * (size_t)ix->levels;
   const size_t sub_bytes = sizeof(uint64_t) * (size_t)ix->nb1;
   // the records start on a 256-byte boundary, so that each is whole lines

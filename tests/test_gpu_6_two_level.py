@@ -75,8 +75,8 @@ def test_default_block_and_resident_index(orc):
     At = dev(A, d)
     idx = rmq.Index(At, 0, sub_block_size=256)
     tab = 8 * (idx.num_blocks * idx.levels + -(-n // 256))
-    rec = rmq.query_record_bytes(idx.num_blocks)
-    assert idx.block_size > 256 and idx.bytes == (-(-tab // 256) * 256 + rec if rec else tab)
+    # two block levels: the table and the k1-block minima, no query records
+    assert idx.block_size > 256 and idx.bytes == tab
     for seed in (94, 95):
         L, R = W.skewed_queries(n, 50_000, seed)
         exp = reference(orc, A, L, R)
