@@ -118,7 +118,10 @@ def main() -> int:
                 return args.k_full, 0
             k, path, k1 = rmq.plan_ex(n, q)
             return (k, k1) if path == "full" else (rmq.default_block(n, q, "full"), 0)
-        return args.k_con or rmq.default_block(n, q, "contracted"), 0
+        if args.k_con:
+            return args.k_con, 0
+        # the library's default plan: two levels over A_Q from q = 1e6
+        return rmq.default_block(n, q, "contracted"), rmq.default_sub_block(n, q, "contracted")
 
     plans = {p: {q: k_for(p, q) for q in qs} for p in ("full", "contracted")}
     k_used = {p: {q: plans[p][q][0] for q in qs} for p in plans}
@@ -467,7 +470,7 @@ def bench_permutation(d, qs, reps=5):
         outs = {}
         for path in ("full", "contracted"):
             kk = k if path == "full" else rmq.default_block(n, q, "contracted")
-            kk1 = k1 if path == "full" else 0
+            kk1 = k1 if path == "full" else rmq.default_sub_block(n, q, "contracted")
             out = torch.empty(q, dtype=torch.int32, device=d)
             run = lambda: rmq.query_batch(A, L, R, path=path, block_size=kk, sub_block_size=kk1,
                                           out=out)

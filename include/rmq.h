@@ -102,12 +102,14 @@ typedef struct rmq_options {
     rmq_timer *timer;        /* optional: records per-stage events on the stream */
     int32_t sub_block_size;  /* Section 3.3, two block levels: k1, the size of the
                                 small blocks whose minima are also kept (0 = one
-                                level).  A power of two, 16 <= k1 < k.  Selects the
-                                plain method (path AUTO or FULL); partial blocks
+                                level).  A power of two, 16 <= k1 < k.  With path
+                                AUTO or FULL the plain method's blocks over A, with
+                                path CONTRACTED the blocks over A_Q; partial blocks
                                 of size k are then read as k1-block minima plus
                                 at most two partial k1-blocks.  With block_size 0,
                                 k is the power of two nearest
-                                sqrt(n) * log2(n)^(2/3) (at least 2 * k1). */
+                                sqrt(m) * log2(m)^(2/3) (at least 2 * k1), m = n
+                                for the plain method and 2q for A_Q. */
     int32_t table_arity_log2; /* Section 3.1, the table over powers of l instead
                                  of 2: l = 2^table_arity_log2.  0 or 1: the
                                  doubling table (l = 2).  2..5 (l = 4..32):
@@ -192,9 +194,17 @@ rmq_status rmq_planner_set_table(const rmq_plan_entry *entries, int32_t count);
 
 /* Block size a call with block_size 0 uses for the given path (FULL or
  * CONTRACTED): about sqrt(n)/8 for FULL (Section 3.2 takes k = Theta(sqrt(n))
- * for the average case), about sqrt(2q)/2 for CONTRACTED (Section 3.1's
- * O(1 + k^2/q) average query cost).  0 on invalid arguments. */
+ * for the average case); for CONTRACTED about sqrt(2q)/2 (Section 3.1's
+ * O(1 + k^2/q) average query cost), or 8 times that where the call also
+ * takes a second block level by default (rmq_default_sub_block).  0 on
+ * invalid arguments. */
 int32_t rmq_default_block(int64_t n, int64_t q, int32_t path);
+
+/* Sub-block size (Section 3.3) a call with block_size 0 and sub_block_size 0
+ * uses for the given path: 512 for CONTRACTED once q >= 1e6 (A_Q's partial
+ * blocks then read through k1-minima), else 0 (one level).  Batches keep
+ * one level.  0 on invalid arguments. */
+int32_t rmq_default_sub_block(int64_t n, int64_t q, int32_t path);
 
 /* ----------------------------------------------------------------------------
  * Resident index (Section 3.2): block minima and the block Sparse Table of A

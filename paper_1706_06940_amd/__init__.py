@@ -79,6 +79,7 @@ def lib() -> ctypes.CDLL:
         "rmq_plan_ex": ([i64, i64, ctypes.POINTER(i32), ctypes.POINTER(i32),
                          ctypes.POINTER(i32)], i32),
         "rmq_default_block": ([i64, i64, i32], i32),
+        "rmq_default_sub_block": ([i64, i64, i32], i32),
         "rmq_build": ([v, i64, opt, v, ctypes.POINTER(v)], i32),
         "rmq_query_index": ([v, v, v, i64, v, v], i32),
         "rmq_query_index_ex": ([v, v, v, i64, v, v, opt], i32),
@@ -254,6 +255,12 @@ def plan_ex(n: int, q: int):
 def default_block(n: int, q: int, path: str) -> int:
     """Block size a call with block_size=0 uses on the given path."""
     return int(lib().rmq_default_block(n, q, PATHS[path]))
+
+
+def default_sub_block(n: int, q: int, path: str) -> int:
+    """Sub-block size a call with block_size=0 and sub_block_size=0 uses on
+    the given path (0: one block level)."""
+    return int(lib().rmq_default_sub_block(n, q, PATHS[path]))
 
 
 def workspace_bytes(n: int, q: int, path="auto", block_size: int = 0,

@@ -108,11 +108,27 @@ int32_t default_block_two_level(int64_t n, int32_t k1) {
   return (int32_t)k;
 }
 
+// The contracted method's default second block level over A_Q, from
+// q = 1e6: k1 = 512 under k = 8 times the one-level block size (the
+// queries' partial blocks of A_Q are then read through k1-minima).
+// Measured at n = 1e8, whole jobs, uniform values / the paper's
+// permutation: q = 1e6 0.337 / 0.336 ms vs 0.338 / 0.340 with one level,
+// q = 1e7 1.114 / 1.120 ms vs 1.142 / 1.143.  No gain at q = 1e5.  With
+// k1 <= 256 (lane-by-lane piece scans) and k / k1 = 128, a nearly sorted
+// array made every query scan its left end lane by lane (2.9 ms at 1e7).
+int32_t default_sub_block_contracted(int64_t q) { return q >= 1000000 ? 512 : 0; }
+int32_t default_block_contracted_two_level(int64_t q) {
+  const int64_t k = 8ll * default_block_contracted(q);
+  return (int32_t)(k < RMQ_MAX_BLOCK ? k : RMQ_MAX_BLOCK);
+}
+
 rmq_status make_plan(int64_t n, int64_t q, const rmq_options* opt, Plan* p,
                      bool allow_two_level = true) {
   int32_t path = opt ? opt->path : RMQ_PATH_AUTO;
   int32_t k = opt ? opt->block_size : 0;
-  const int32_t k1 = opt ? opt->sub_block_size : 0;
+  int32_t k1 = opt ? opt->sub_block_size : 0;
+  if (path == RMQ_PATH_CONTRACTED && k == 0 && k1 == 0 && allow_two_level)
+    k1 = default_sub_block_contracted(q);
   if (path != RMQ_PATH_AUTO && path != RMQ_PATH_FULL && path != RMQ_PATH_CONTRACTED)
     return RMQ_ERR_INVALID_ARG;
   if (k != 0 && !is_pow2_block(k)) return RMQ_ERR_INVALID_ARG;
@@ -121,11 +137,14 @@ rmq_status make_plan(int64_t n, int64_t q, const rmq_options* opt, Plan* p,
   if (p->lg < 0) return RMQ_ERR_INVALID_ARG;
   p->records = !(opt && opt->no_query_records);
   if (k1 != 0) {
-    // two block levels: the plain method with k1 < k
-    if (!is_pow2_block(k1) || path == RMQ_PATH_CONTRACTED) return RMQ_ERR_INVALID_ARG;
-    if (k == 0) k = default_block_two_level(n, k1);
+    // two block levels (k1 < k): over A, or over A_Q for the contracted method
+    if (!is_pow2_block(k1)) return RMQ_ERR_INVALID_ARG;
+    const bool con = path == RMQ_PATH_CONTRACTED;
+    if (k == 0)
+      k = con && k1 == default_sub_block_contracted(q) ? default_block_contracted_two_level(q)
+                                                       : default_block_two_level(con ? 2 * q : n, k1);
     if (k1 >= k) return RMQ_ERR_INVALID_ARG;
-    p->path = RMQ_PATH_FULL;
+    p->path = con ? RMQ_PATH_CONTRACTED : RMQ_PATH_FULL;
     p->k = k;
     p->kshift = ilog2_i64(k);
     p->k1shift = ilog2_i64(k1);
@@ -178,19 +197,22 @@ FullLayout full_layout(int64_t n, int64_t k, int k1shift, int lg, bool records) 
 }
 
 struct ConLayout {
-  int64_t M, m, nb;
+  int64_t M, m, nb, nb1;
   int levels;
   bool rec;  // query records built
-  size_t off_E, off_sort, off_lr, off_aq, off_tiles, off_st, off_rec, bytes;
+  size_t off_E, off_sort, off_lr, off_aq, off_tiles, off_st, off_sub, off_rec, bytes;
 };
 
-ConLayout con_layout(int64_t n, int64_t q, int64_t k, int lg, bool records) {
+// k1shift >= 0: two block levels over A_Q (Section 3.3), the k1-block
+// minima kept beside the table.
+ConLayout con_layout(int64_t n, int64_t q, int64_t k, int k1shift, int lg, bool records) {
   ConLayout c{};
   c.M = 2 * q;
   c.m = c.M - 1;
   c.nb = num_blocks(c.m, k);
+  c.nb1 = k1shift >= 0 ? num_blocks(c.m, 1ll << k1shift) : 0;
   c.levels = table_levels(c.nb, lg);
-  c.rec = records_built(c.nb, c.levels, lg, records, false);
+  c.rec = records_built(c.nb, c.levels, lg, records, k1shift >= 0);
   size_t o = 0;
   c.off_E = o;
   o = align_up(o + sizeof(uint64_t) * (size_t)c.M);
@@ -204,6 +226,8 @@ ConLayout con_layout(int64_t n, int64_t q, int64_t k, int lg, bool records) {
   o = align_up(o + contract_tile_start_bytes(n));
   c.off_st = o;
   o = align_up(o + sizeof(uint64_t) * (size_t)c.nb * (size_t)c.levels);
+  c.off_sub = o;
+  o = align_up(o + sizeof(uint64_t) * (size_t)c.nb1);
   c.off_rec = o;
   o = align_up(o + (c.rec ? records_bytes(c.nb, c.levels) : 0));
   c.bytes = o;
@@ -212,7 +236,7 @@ ConLayout con_layout(int64_t n, int64_t q, int64_t k, int lg, bool records) {
 
 size_t plan_bytes(int64_t n, int64_t q, const Plan& p) {
   if (p.path == RMQ_PATH_FULL) return full_layout(n, p.k, p.k1shift, p.lg, p.records).bytes;
-  return con_layout(n, q, p.k, p.lg, p.records).bytes;
+  return con_layout(n, q, p.k, p.k1shift, p.lg, p.records).bytes;
 }
 
 std::once_flag g_pool_once[64];
@@ -342,13 +366,15 @@ rmq_status run_contracted(const int32_t* A, int64_t n, const int32_t* L, const i
                           int64_t q, int32_t* out, hipStream_t s, const rmq_options* opt,
                           const Plan& p, char* ws) {
   rmq_timer* t = opt ? opt->timer : nullptr;
-  const ConLayout c = con_layout(n, q, p.k, p.lg, p.records);
+  const ConLayout c = con_layout(n, q, p.k, p.k1shift, p.lg, p.records);
   uint64_t* E = reinterpret_cast<uint64_t*>(ws + c.off_E);
   uint64_t* rec = c.rec ? reinterpret_cast<uint64_t*>(ws + c.off_rec) : nullptr;
   int32_t* LR = reinterpret_cast<int32_t*>(ws + c.off_lr);
   uint64_t* aq = reinterpret_cast<uint64_t*>(ws + c.off_aq);
   int32_t* tiles = reinterpret_cast<int32_t*>(ws + c.off_tiles);
   uint64_t* st = reinterpret_cast<uint64_t*>(ws + c.off_st);
+  const bool two = p.k1shift >= 0;
+  uint64_t* sub = two ? reinterpret_cast<uint64_t*>(ws + c.off_sub) : nullptr;
   ClockGuard guard;
   stage_begin(t, 0);
   // the sort's last pass writes the remap as well
@@ -361,7 +387,12 @@ rmq_status run_contracted(const int32_t* A, int64_t n, const int32_t* L, const i
   if (e != hipSuccess) return from_hip(e);
   stage_end(t, 1, s);
   stage_begin(t, 2);
-  e = launch_blockmin_keys(aq, c.m, p.kshift, st, s);
+  if (two) {
+    e = launch_blockmin_keys(aq, c.m, p.k1shift, sub, s);
+    if (e == hipSuccess) e = launch_blockmin_keys(sub, c.nb1, p.kshift - p.k1shift, st, s);
+  } else {
+    e = launch_blockmin_keys(aq, c.m, p.kshift, st, s);
+  }
   if (e != hipSuccess) return from_hip(e);
   e = build_table(st, c.nb, c.levels, p.lg, s);
   if (e == hipSuccess && rec) e = launch_records(st, c.nb, c.levels, rec, s);
@@ -370,7 +401,7 @@ rmq_status run_contracted(const int32_t* A, int64_t n, const int32_t* L, const i
   stage_begin(t, 3);
   e = launch_query_contracted(aq, c.m, n, p.kshift, st, c.nb, L, R, LR, q, out,
                               opt ? opt->bad_count : nullptr, opt ? opt->stats : nullptr, s,
-                              p.lg, rec, c.levels);
+                              p.lg, rec, c.levels, sub, p.k1shift);
   if (e != hipSuccess) return from_hip(e);
   stage_end(t, 3, s);
   return RMQ_OK;
@@ -477,10 +508,18 @@ rmq_status rmq_plan(int64_t n, int64_t q, int32_t* block_size, int32_t* path) {
   return RMQ_OK;
 }
 
+int32_t rmq_default_sub_block(int64_t n, int64_t q, int32_t path) {
+  if (n < 1 || n > RMQ_MAX_N || q < 0 || q > RMQ_MAX_Q) return 0;
+  return path == RMQ_PATH_CONTRACTED ? default_sub_block_contracted(q) : 0;
+}
+
 int32_t rmq_default_block(int64_t n, int64_t q, int32_t path) {
   if (n < 1 || n > RMQ_MAX_N || q < 0 || q > RMQ_MAX_Q) return 0;
   if (path == RMQ_PATH_FULL) return default_block_full(n);
-  if (path == RMQ_PATH_CONTRACTED) return default_block_contracted(q);
+  if (path == RMQ_PATH_CONTRACTED) {
+    return default_sub_block_contracted(q) ? default_block_contracted_two_level(q)
+                                           : default_block_contracted(q);
+  }
   return 0;
 }
 

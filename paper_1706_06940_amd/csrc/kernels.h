@@ -169,6 +169,7 @@ hipError_t launch_query_contracted(const uint64_t* aq, int64_t m, int64_t n, int
                                    const uint64_t* st, int64_t nb, const int32_t* L,
                                    const int32_t* R, const int32_t* LR, int64_t q, int32_t* out,
                                    int64_t* bad_count, uint64_t* stats, hipStream_t stream,
-                                   int lg = 1, const uint64_t* rec = nullptr, int rlev = 0);
+                                   int lg = 1, const uint64_t* rec = nullptr, int rlev = 0,
+                                   const uint64_t* sub = nullptr, int k1shift = -1);
 
 }  // namespace rmq

@@ -82,6 +82,8 @@ struct SrcA {
     return best;
   }
   // This lane's source as seen by the whole wave (for a wave-wide scan).
+  // the source bound to one query's range in A (used by two-level sources)
+  __device__ __forceinline__ SrcA with_query(int64_t, int64_t) const { return *this; }
   __device__ __forceinline__ SrcA broadcast(int src_lane) const {
     return {reinterpret_cast<const int32_t*>(readlane64((int64_t)(uintptr_t)A, src_lane)),
             readlane64(len, src_lane)};
@@ -128,6 +130,21 @@ struct SrcKeys {
   }
   __device__ __forceinline__ uint32_t pos_of(uint64_t key) const { return key_pos(key); }
   static constexpr bool kLaneScans = false;  // as for the plain array
+  // min key over S[lo..hi] by this lane alone (a short piece under two block
+  // levels); 8 entries per step, their loads in flight together
+  __device__ uint64_t lane_scan(int64_t lo, int64_t hi, uint64_t bound, int64_t& reads) const {
+    reads += hi - lo + 1;
+    uint64_t best = KEY_NONE;
+    for (int64_t p = lo; p <= hi; p += 8) {
+      uint64_t x[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) x[u] = p + u <= hi ? S[p + u] : KEY_NONE;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) best = umin64(best, x[u]);
+    }
+    return best;
+  }
+  __device__ __forceinline__ SrcKeys with_query(int64_t, int64_t) const { return *this; }
   __device__ __forceinline__ SrcKeys broadcast(int src_lane) const {
     return {reinterpret_cast<const uint64_t*>(readlane64((int64_t)(uintptr_t)S, src_lane)),
             readlane64(len, src_lane)};
@@ -155,31 +172,48 @@ struct SrcKeys {
   }
 };
 
-// The plain array with two block levels (Section 3.3): the minima of its
-// k1-blocks are kept, so a partial k-block [lo, hi] is read as the k1-block
-// minima of the k1-blocks it covers plus at most two partial k1-blocks, and
-// those again only when their k1-block minimum can still beat the query's
-// best key (the same speculation as at the upper level).
-struct SrcA2 {
-  SrcA a;
+// An array with two block levels (Section 3.3): the minima of its k1-blocks
+// are kept, so a partial k-block [lo, hi] is read as the k1-block minima of
+// the k1-blocks it covers plus at most two partial k1-blocks, and those again
+// only when their k1-block minimum can still beat the query's best key (the
+// same speculation as at the upper level).  Inner: the plain array A (SrcA)
+// or the contracted A_Q (SrcKeys).
+//
+// Whether a k1-block's minimum lies inside a piece is decided in A: every
+// piece read here is the query's part of one k1-block, and the block's
+// minimum lies in the block, so it lies in the piece exactly when its
+// position in A lies in the query's range [ql, qr] (for A_Q, whose keys
+// carry positions in A, the entry indices of the piece would not do).
+template <class Inner>
+struct Src2 {
+  Inner a;
   const uint64_t* __restrict__ sub;  // k1-block minima
   int64_t nsub;
-  int s1;  // k1 = 2^s1
+  int s1;            // k1 = 2^s1
+  int64_t ql = 0;    // the query's range in A (with_query)
+  int64_t qr = -1;
   __device__ __forceinline__ uint32_t pos_of(uint64_t key) const { return key_pos(key); }
-  __device__ __forceinline__ SrcA2 broadcast(int src_lane) const {
+  __device__ __forceinline__ Src2 with_query(int64_t l, int64_t r) const {
+    Src2 c = *this;
+    c.ql = l;
+    c.qr = r;
+    return c;
+  }
+  __device__ __forceinline__ Src2 broadcast(int src_lane) const {
     return {a.broadcast(src_lane),
             reinterpret_cast<const uint64_t*>(readlane64((int64_t)(uintptr_t)sub, src_lane)),
-            readlane64(nsub, src_lane), __builtin_amdgcn_readlane(s1, src_lane)};
+            readlane64(nsub, src_lane), __builtin_amdgcn_readlane(s1, src_lane),
+            readlane64(ql, src_lane), readlane64(qr, src_lane)};
   }
-  // min over the elements of A[lo..hi], which lie in one k1-block: its
-  // minimum if that lies inside, nothing if it cannot beat `bound`, else a
-  // scan of the elements
+  // min over the entries lo..hi, which lie in one k1-block: its minimum if
+  // that lies inside, nothing if it cannot beat `bound`, else a scan of the
+  // entries
   __device__ uint64_t part(int64_t lo, int64_t hi, int lane, uint64_t bound,
                            int64_t& reads) const {
     const uint64_t kb = sub[lo >> s1];
     reads += 1;
     const int64_t p = (int64_t)key_pos(kb);
-    if (lo <= p && p <= hi) return kb;
+    if (ql <= p && p <= qr) return kb;
     if (!(kb < bound)) return KEY_NONE;
     return a.scan(lo, hi, lane, bound, reads);
   }
@@ -204,7 +238,7 @@ struct SrcA2 {
     reads += b_hi - b_lo + 1;
     auto piece = [&](uint64_t kb, int64_t p_lo, int64_t p_hi) {
       const int64_t p = (int64_t)key_pos(kb);
-      if (p_lo <= p && p <= p_hi) best = umin64(best, kb);
+      if (ql <= p && p <= qr) best = umin64(best, kb);
       else if (kb < umin64(best, bound))
         best = umin64(best, a.lane_scan(p_lo, p_hi, bound, reads));
     };
@@ -230,6 +264,8 @@ struct SrcA2 {
     return best;
   }
 };
+using SrcA2 = Src2<SrcA>;
+using SrcKeys2 = Src2<SrcKeys>;
 
 // --- the query step ----------------------------------------------------------
 // One lane's query [l, r] (positions in A, validated here) over source
@@ -316,10 +352,11 @@ __device__ __forceinline__ void query_core(const Src& src, int64_t src_len, int6
   // of them at once); a long one is queued and read by the whole wave ----
   uint64_t n_scans = 0, n_elems = 0;  // wave-uniform counts of queued scans
   int64_t lane_scans = 0, lane_reads = 0;
+  const Src qsrc = src.with_query(l, r);  // this lane's query range in A
   if constexpr (Src::kLaneScans) {
     if (__popcll(ballot(needL)) >= LANE_SCAN_MIN && needL &&
         src.lane_cost(loL, hiL) <= LANE_SCAN_MAX) {
-      best = umin64(best, src.lane_scan(loL, hiL, best, lane_reads));
+      best = umin64(best, qsrc.lane_scan(loL, hiL, best, lane_reads));
       lane_scans += 1;
       needL = false;
     }
@@ -331,7 +368,7 @@ __device__ __forceinline__ void query_core(const Src& src, int64_t src_len, int6
     const int64_t lo = readlane64(loL, src_lane), hi = readlane64(hiL, src_lane);
     const uint64_t bound = (uint64_t)readlane64((int64_t)best, src_lane);
     int64_t reads = 0;
-    const uint64_t m = src.broadcast(src_lane).scan(lo, hi, lane, bound, reads);
+    const uint64_t m = qsrc.broadcast(src_lane).scan(lo, hi, lane, bound, reads);
     if (lane == src_lane) best = umin64(best, m);
     n_scans += 1;
     n_elems += (uint64_t)reads;
@@ -340,7 +377,7 @@ __device__ __forceinline__ void query_core(const Src& src, int64_t src_len, int6
   if constexpr (Src::kLaneScans) {
     if (__popcll(ballot(needR)) >= LANE_SCAN_MIN && needR &&
         src.lane_cost(loR, hiR) <= LANE_SCAN_MAX) {
-      best = umin64(best, src.lane_scan(loR, hiR, best, lane_reads));
+      best = umin64(best, qsrc.lane_scan(loR, hiR, best, lane_reads));
       lane_scans += 1;
       needR = false;
     }
@@ -352,7 +389,7 @@ __device__ __forceinline__ void query_core(const Src& src, int64_t src_len, int6
     const int64_t lo = readlane64(loR, src_lane), hi = readlane64(hiR, src_lane);
     const uint64_t bound = (uint64_t)readlane64((int64_t)best, src_lane);
     int64_t reads = 0;
-    const uint64_t m = src.broadcast(src_lane).scan(lo, hi, lane, bound, reads);
+    const uint64_t m = qsrc.broadcast(src_lane).scan(lo, hi, lane, bound, reads);
     if (lane == src_lane) best = umin64(best, m);
     n_scans += 1;
     n_elems += (uint64_t)reads;
@@ -555,12 +592,21 @@ hipError_t launch_query_contracted(const uint64_t* aq, int64_t m, int64_t n, int
                                    const uint64_t* st, int64_t nb, const int32_t* L,
                                    const int32_t* R, const int32_t* LR, int64_t q, int32_t* out,
                                    int64_t* bad_count, uint64_t* stats, hipStream_t stream,
-                                   int lg, const uint64_t* rec, int rlev) {
+                                   int lg, const uint64_t* rec, int rlev, const uint64_t* sub,
+                                   int k1shift) {
   if (q <= 0) return hipSuccess;
   const int64_t grid = (q + WG - 1) / WG;
-  RMQ_TRY(launch(k_query<SrcKeys>, dim3((unsigned)grid), dim3(WG), 0, stream, SrcKeys{aq, m}, m,
-                 n, kshift, st, nb, L, R, LR, q, out, (unsigned long long*)bad_count,
-                 (unsigned long long*)stats, lg, rec, rlev));
+  if (sub) {
+    const int64_t nsub = (m + (1ll << k1shift) - 1) >> k1shift;
+    RMQ_TRY(launch(k_query<SrcKeys2>, dim3((unsigned)grid), dim3(WG), 0, stream,
+                   SrcKeys2{SrcKeys{aq, m}, sub, nsub, k1shift}, m, n, kshift, st, nb, L, R, LR,
+                   q, out, (unsigned long long*)bad_count, (unsigned long long*)stats, lg, rec,
+                   rlev));
+  } else {
+    RMQ_TRY(launch(k_query<SrcKeys>, dim3((unsigned)grid), dim3(WG), 0, stream, SrcKeys{aq, m},
+                   m, n, kshift, st, nb, L, R, LR, q, out, (unsigned long long*)bad_count,
+                   (unsigned long long*)stats, lg, rec, rlev));
+  }
   return hipGetLastError();
 }
 

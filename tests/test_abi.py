@@ -183,3 +183,31 @@ def test_plan_table_two_levels():
                 rmq.set_plan_table([bad])
     finally:
         rmq.set_plan_table([])
+
+
+def test_contracted_default_block_and_workspace():
+    """sub_block_size alone picks k from the length of A_Q; the workspace
+    holds the k1-block minima of A_Q beside its table (no query records)."""
+    n, q = 1_000_003, 100_000
+    one = rmq.workspace_bytes(n, q, "contracted", 4096, records=False)
+    two = rmq.workspace_bytes(n, q, "contracted", 4096, sub_block_size=64)
+    m = 2 * q - 1
+    assert two - one >= 8 * (-(-m // 64)) and two - one <= 8 * (-(-m // 64)) + 512
+    assert rmq.workspace_bytes(n, q, "contracted", 0, sub_block_size=64) > 0
+
+
+def test_contracted_default_plan():
+    """The contracted method's default: one level below q = 1e6, then
+    k1 = 512 under 8 times the one-level block size."""
+    n = 10 ** 8
+    for q in (1, 1000, 999_999):
+        assert rmq.default_sub_block(n, q, "contracted") == 0
+    for q in (10 ** 6, 10 ** 7):
+        assert rmq.default_sub_block(n, q, "contracted") == 512
+        k = rmq.default_block(n, q, "contracted")
+        assert k > 512 and k & (k - 1) == 0
+        assert rmq.workspace_bytes(n, q, "contracted") == \
+            rmq.workspace_bytes(n, q, "contracted", k, sub_block_size=512)
+    assert rmq.default_sub_block(n, 10 ** 7, "full") == 0
+    assert rmq.default_block(n, 10 ** 6, "contracted") == 4096
+    assert rmq.default_block(n, 10 ** 7, "contracted") == 16384

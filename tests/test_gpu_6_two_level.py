@@ -94,8 +94,43 @@ def test_invalid_options():
     A = torch.zeros(1000, dtype=torch.int32, device=d)
     L = torch.zeros(4, dtype=torch.int32, device=d)
     for k, k1, path in ((256, 256, "full"), (256, 512, "full"), (256, 24, "full"),
-                        (256, 8, "full"), (256, 16, "contracted")):
+                        (256, 8, "full"), (256, 256, "contracted"), (256, 24, "contracted")):
         with pytest.raises(rmq.RMQError):
             rmq.query_batch(A, L, L, path=path, block_size=k, sub_block_size=k1)
     with pytest.raises(rmq.RMQError):
         rmq.Index(A, 256, sub_block_size=512)
+
+
+# ---- two block levels over A_Q (the contracted method) ----
+# A_Q has 2q - 1 entries; its k-blocks are read through the minima of its
+# k1-blocks.  q spans A_Q lengths below, at and above k and k1, ragged ends.
+@pytest.mark.parametrize("n,q,k,k1", [(1, 1, 32, 16), (100, 17, 32, 16), (10_007, 300, 64, 16),
+                                      (10_007, 5000, 256, 32), (100_003, 40_000, 4096, 256),
+                                      (1_000_003, 300_000, 16_384, 512),
+                                      (3_000_017, 1_000_003, 8192, 64)])
+def test_contracted_families(orc, n, q, k, k1):
+    d = need_gpu()
+    for aname, A in list(arrays(n, n + q + k1))[:4]:
+        At = dev(A, d)
+        for qname, L, R in query_sets(n, k1, q, n * 5 + q + k):
+            say("two_level_contracted", n, q, k, k1, aname, qname)
+            exp = reference(orc, A, L, R)
+            got = host(rmq.query_batch(At, dev(L, d), dev(R, d), path="contracted", block_size=k,
+                                       sub_block_size=k1))
+            bad = np.nonzero(got != exp)[0]
+            assert bad.size == 0, (aname, qname, L[bad[:4]], R[bad[:4]], got[bad[:4]], exp[bad[:4]])
+
+
+def test_contracted_all_ranges_tiny(orc):
+    d = need_gpu()
+    for n in (1, 2, 5, 16, 17, 40, 64):
+        for aname, A in arrays(n, n + 1):
+            L, R = np.triu_indices(n)
+            L, R = L.astype(np.int32), R.astype(np.int32)
+            say("two_level_contracted_all_ranges", n, aname)
+            exp = orc.rmq_scan(A, L, R)
+            for k, k1 in ((32, 16), (64, 16), (128, 32)):
+                got = host(rmq.query_batch(dev(A, d), dev(L, d), dev(R, d), path="contracted",
+                                           block_size=k, sub_block_size=k1))
+                assert np.array_equal(got, exp), (n, aname, k, k1)
+
