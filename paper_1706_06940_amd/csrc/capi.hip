@@ -113,9 +113,8 @@ int32_t default_block_two_level(int64_t n, int32_t k1) {
 // queries' partial blocks of A_Q are then read through k1-minima).
 // Measured at n = 1e8, whole jobs, uniform values / the paper's
 // permutation: q = 1e6 0.337 / 0.336 ms vs 0.338 / 0.340 with one level,
-// q = 1e7 1.114 / 1.120 ms vs 1.142 / 1.143.  No gain at q = 1e5.  With
-// k1 <= 256 (lane-by-lane piece scans) and k / k1 = 128, a nearly sorted
-// array made every query scan its left end lane by lane (2.9 ms at 1e7).
+// q = 1e7 1.114 / 1.120 ms vs 1.142 / 1.143 (k1 = 256 under k = 32768:
+// 1.128 / 1.136).  No gain at q = 1e5.
 int32_t default_sub_block_contracted(int64_t q) { return q >= 1000000 ? 512 : 0; }
 int32_t default_block_contracted_two_level(int64_t q) {
   const int64_t k = 8ll * default_block_contracted(q);
