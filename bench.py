@@ -120,7 +120,7 @@ def main() -> int:
             return (k, k1) if path == "full" else (rmq.default_block(n, q, "full"), 0)
         if args.k_con:
             return args.k_con, 0
-        # the library's default plan: two levels over A_Q from q = 1e6
+        # the library's default plan for the contracted method
         return rmq.default_block(n, q, "contracted"), rmq.default_sub_block(n, q, "contracted")
 
     plans = {p: {q: k_for(p, q) for q in qs} for p in ("full", "contracted")}

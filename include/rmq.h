@@ -195,15 +195,15 @@ rmq_status rmq_planner_set_table(const rmq_plan_entry *entries, int32_t count);
 /* Block size a call with block_size 0 uses for the given path (FULL or
  * CONTRACTED): about sqrt(n)/8 for FULL (Section 3.2 takes k = Theta(sqrt(n))
  * for the average case); for CONTRACTED about sqrt(2q)/2 (Section 3.1's
- * O(1 + k^2/q) average query cost), or 8 times that where the call also
- * takes a second block level by default (rmq_default_sub_block).  0 on
- * invalid arguments. */
+ * O(1 + k^2/q) average query cost).  0 on invalid arguments. */
 int32_t rmq_default_block(int64_t n, int64_t q, int32_t path);
 
 /* Sub-block size (Section 3.3) a call with block_size 0 and sub_block_size 0
- * uses for the given path: 512 for CONTRACTED once q >= 1e6 (A_Q's partial
- * blocks then read through k1-minima), else 0 (one level).  Batches keep
- * one level.  0 on invalid arguments. */
+ * uses for the given path: 0 (one block level) for both methods; the plain
+ * method's path AUTO takes two levels from the planner's table instead
+ * (rmq_plan_ex).  Two levels over A_Q gain for uniform queries but lose on
+ * mixes of short ranges, so the contracted method takes them only when
+ * asked.  0 on invalid arguments. */
 int32_t rmq_default_sub_block(int64_t n, int64_t q, int32_t path);
 
 /* ----------------------------------------------------------------------------

@@ -108,18 +108,15 @@ int32_t default_block_two_level(int64_t n, int32_t k1) {
   return (int32_t)k;
 }
 
-// The contracted method's default second block level over A_Q, from
-// q = 1e6: k1 = 512 under k = 8 times the one-level block size (the
-// queries' partial blocks of A_Q are then read through k1-minima).
-// Measured at n = 1e8, whole jobs, uniform values / the paper's
-// permutation: q = 1e6 0.337 / 0.336 ms vs 0.338 / 0.340 with one level,
-// q = 1e7 1.114 / 1.120 ms vs 1.142 / 1.143 (k1 = 256 under k = 32768:
-// 1.128 / 1.136).  No gain at q = 1e5.
-int32_t default_sub_block_contracted(int64_t q) { return q >= 1000000 ? 512 : 0; }
-int32_t default_block_contracted_two_level(int64_t q) {
-  const int64_t k = 8ll * default_block_contracted(q);
-  return (int32_t)(k < RMQ_MAX_BLOCK ? k : RMQ_MAX_BLOCK);
-}
+// The contracted method's default is one block level over A_Q; two levels
+// (sub_block_size) are taken only when asked.  Measured at n = 1e8 with
+// k1 = 512 under k = 8 times the one-level block size, whole jobs: uniform
+// queries gain from q = 1e6 (q = 1e7: 1.114 vs 1.142 ms; the permutation
+// array 1.120 vs 1.143), but the skewed mix at n = 1e9 (half ranges of at
+// most 1024 elements, q = 1e7) loses (3.58 vs 3.25 ms): a short range is a
+// few entries of A_Q, whose k1-block minimum rarely lies inside it, so the
+// sub-block lookup only adds a dependent load before each scan.
+int32_t default_sub_block_contracted(int64_t) { return 0; }
 
 rmq_status make_plan(int64_t n, int64_t q, const rmq_options* opt, Plan* p,
                      bool allow_two_level = true) {
@@ -139,9 +136,7 @@ rmq_status make_plan(int64_t n, int64_t q, const rmq_options* opt, Plan* p,
     // two block levels (k1 < k): over A, or over A_Q for the contracted method
     if (!is_pow2_block(k1)) return RMQ_ERR_INVALID_ARG;
     const bool con = path == RMQ_PATH_CONTRACTED;
-    if (k == 0)
-      k = con && k1 == default_sub_block_contracted(q) ? default_block_contracted_two_level(q)
-                                                       : default_block_two_level(con ? 2 * q : n, k1);
+    if (k == 0) k = default_block_two_level(con ? 2 * q : n, k1);
     if (k1 >= k) return RMQ_ERR_INVALID_ARG;
     p->path = con ? RMQ_PATH_CONTRACTED : RMQ_PATH_FULL;
     p->k = k;
@@ -516,8 +511,8 @@ int32_t rmq_default_block(int64_t n, int64_t q, int32_t path) {
   if (n < 1 || n > RMQ_MAX_N || q < 0 || q > RMQ_MAX_Q) return 0;
   if (path == RMQ_PATH_FULL) return default_block_full(n);
   if (path == RMQ_PATH_CONTRACTED) {
-    return default_sub_block_contracted(q) ? default_block_contracted_two_level(q)
-                                           : default_block_contracted(q);
+    const int32_t k1 = default_sub_block_contracted(q);
+    return k1 ? default_block_two_level(2 * q, k1) : default_block_contracted(q);
   }
   return 0;
 }

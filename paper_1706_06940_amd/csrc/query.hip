@@ -82,6 +82,7 @@ struct SrcA {
     return best;
   }
   // This lane's source as seen by the whole wave (for a wave-wide scan).
+  static constexpr bool kIndexIsPos = true;  // entry index = position in A
   // the source bound to one query's range in A (used by two-level sources)
   __device__ __forceinline__ SrcA with_query(int64_t, int64_t) const { return *this; }
   __device__ __forceinline__ SrcA broadcast(int src_lane) const {
@@ -144,6 +145,7 @@ struct SrcKeys {
     }
     return best;
   }
+  static constexpr bool kIndexIsPos = false;  // keys carry positions in A
   __device__ __forceinline__ SrcKeys with_query(int64_t, int64_t) const { return *this; }
   __device__ __forceinline__ SrcKeys broadcast(int src_lane) const {
     return {reinterpret_cast<const uint64_t*>(readlane64((int64_t)(uintptr_t)S, src_lane)),
@@ -179,11 +181,11 @@ struct SrcKeys {
 // same speculation as at the upper level).  Inner: the plain array A (SrcA)
 // or the contracted A_Q (SrcKeys).
 //
-// Whether a k1-block's minimum lies inside a piece is decided in A: every
-// piece read here is the query's part of one k1-block, and the block's
-// minimum lies in the block, so it lies in the piece exactly when its
-// position in A lies in the query's range [ql, qr] (for A_Q, whose keys
-// carry positions in A, the entry indices of the piece would not do).
+// Whether a k1-block's minimum lies inside a piece: over A, by the piece's
+// bounds; over A_Q, whose keys carry positions in A, in A: every piece read
+// here is the query's part of one k1-block, and the block's minimum lies in
+// the block, so it lies in the piece exactly when its position in A lies in
+// the query's range [ql, qr].
 template <class Inner>
 struct Src2 {
   Inner a;
@@ -194,16 +196,26 @@ struct Src2 {
   int64_t qr = -1;
   __device__ __forceinline__ uint32_t pos_of(uint64_t key) const { return key_pos(key); }
   __device__ __forceinline__ Src2 with_query(int64_t l, int64_t r) const {
+    if constexpr (Inner::kIndexIsPos) return *this;  // the piece's own bounds serve
     Src2 c = *this;
     c.ql = l;
     c.qr = r;
     return c;
   }
+  // whether position p (of a k1-block's minimum) lies in the piece lo..hi
+  __device__ __forceinline__ bool inside(int64_t p, int64_t lo, int64_t hi) const {
+    if constexpr (Inner::kIndexIsPos) return lo <= p && p <= hi;
+    return ql <= p && p <= qr;
+  }
   __device__ __forceinline__ Src2 broadcast(int src_lane) const {
-    return {a.broadcast(src_lane),
-            reinterpret_cast<const uint64_t*>(readlane64((int64_t)(uintptr_t)sub, src_lane)),
-            readlane64(nsub, src_lane), __builtin_amdgcn_readlane(s1, src_lane),
-            readlane64(ql, src_lane), readlane64(qr, src_lane)};
+    Src2 c{a.broadcast(src_lane),
+           reinterpret_cast<const uint64_t*>(readlane64((int64_t)(uintptr_t)sub, src_lane)),
+           readlane64(nsub, src_lane), __builtin_amdgcn_readlane(s1, src_lane)};
+    if constexpr (!Inner::kIndexIsPos) {
+      c.ql = readlane64(ql, src_lane);
+      c.qr = readlane64(qr, src_lane);
+    }
+    return c;
   }
   // min over the entries lo..hi, which lie in one k1-block: its minimum if
   // that lies inside, nothing if it cannot beat `bound`, else a scan of the
@@ -213,7 +225,7 @@ struct Src2 {
     const uint64_t kb = sub[lo >> s1];
     reads += 1;
     const int64_t p = (int64_t)key_pos(kb);
-    if (ql <= p && p <= qr) return kb;
+    if (inside(p, lo, hi)) return kb;
     if (!(kb < bound)) return KEY_NONE;
     return a.scan(lo, hi, lane, bound, reads);
   }
@@ -238,7 +250,7 @@ struct Src2 {
     reads += b_hi - b_lo + 1;
     auto piece = [&](uint64_t kb, int64_t p_lo, int64_t p_hi) {
       const int64_t p = (int64_t)key_pos(kb);
-      if (ql <= p && p <= qr) best = umin64(best, kb);
+      if (inside(p, p_lo, p_hi)) best = umin64(best, kb);
       else if (kb < umin64(best, bound))
         best = umin64(best, a.lane_scan(p_lo, p_hi, bound, reads));
     };

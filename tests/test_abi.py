@@ -197,17 +197,14 @@ def test_contracted_default_block_and_workspace():
 
 
 def test_contracted_default_plan():
-    """The contracted method's default: one level below q = 1e6, then
-    k1 = 512 under 8 times the one-level block size."""
+    """The contracted method's default is one block level (two only when
+    sub_block_size is given), with k about sqrt(2q)/2."""
     n = 10 ** 8
-    for q in (1, 1000, 999_999):
+    for q in (1, 1000, 10 ** 6, 10 ** 7):
         assert rmq.default_sub_block(n, q, "contracted") == 0
-    for q in (10 ** 6, 10 ** 7):
-        assert rmq.default_sub_block(n, q, "contracted") == 512
-        k = rmq.default_block(n, q, "contracted")
-        assert k > 512 and k & (k - 1) == 0
-        assert rmq.workspace_bytes(n, q, "contracted") == \
-            rmq.workspace_bytes(n, q, "contracted", k, sub_block_size=512)
-    assert rmq.default_sub_block(n, 10 ** 7, "full") == 0
-    assert rmq.default_block(n, 10 ** 6, "contracted") == 4096
-    assert rmq.default_block(n, 10 ** 7, "contracted") == 16384
+        assert rmq.default_sub_block(n, q, "full") == 0
+    assert rmq.default_block(n, 10 ** 6, "contracted") == 512
+    assert rmq.default_block(n, 10 ** 7, "contracted") == 2048
+    k = rmq.default_block(n, 10 ** 7, "contracted")
+    assert rmq.workspace_bytes(n, 10 ** 7, "contracted") == \
+        rmq.workspace_bytes(n, 10 ** 7, "contracted", k)
