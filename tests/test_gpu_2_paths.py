@@ -177,10 +177,12 @@ def test_workspace_and_timer(orc):
 # of 32768 tags built in LDS (2q >= 2^22, up to 6144 tiles of 4096 items);
 # shorter lists write LR with scattered stores.  Both sides of the switch,
 # a ragged last window, the single-pass sort (n <= 256: the first pass is
-# also the last) and the longest list the windows take.
+# also the last), and both sides of the longest list the windows take.
 @pytest.mark.parametrize("n,q", [(3_000_017, 2_097_151), (3_000_017, 2_097_152),
                                  (10_000_019, 2_100_007), (200, 2_200_001),
-                                 (50_000_017, 12_000_007)])
+                                 (50_000_017, 12_000_007),
+                                 # 6144 tiles of 4096 items exactly, and one item more
+                                 (30_000_001, 12_582_912), (30_000_001, 12_582_913)])
 def test_contracted_remap_windows(orc, n, q):
     d = need_gpu()
     say("remap_windows", n, q)
