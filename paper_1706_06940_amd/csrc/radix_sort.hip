@@ -334,7 +334,10 @@ __device__ __forceinline__ void os_pass(const uint64_t* __restrict__ items_in,
     run += c;
   }
   uint64_t* mine = status + tile * RADIX + d;
-  store_status(mine, (tile == 0 ? ST_INC : ST_AGG) | run);
+  // digits at or above 2^bits occur in no item: their threads neither
+  // publish nor look back (no tile ever reads those words)
+  const bool used_digit = d <= (int)mask;
+  if (used_digit) store_status(mine, (tile == 0 ? ST_INC : ST_AGG) | run);
   {
     uint32_t excl;
     block_exclusive_scan(run, tmp, excl);
@@ -354,7 +357,7 @@ __device__ __forceinline__ void os_pass(const uint64_t* __restrict__ items_in,
   // LOOKBACK predecessors' words at once, newest first, and take values up to
   // the first inclusive one, or stop at an unpublished one and read again
   uint64_t before = 0;
-  if (tile > 0) {
+  if (tile > 0 && used_digit) {
     int64_t j = tile - 1;
     uint32_t spins = 0;
     for (;;) {
