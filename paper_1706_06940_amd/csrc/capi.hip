@@ -377,7 +377,8 @@ rmq_status run_contracted(const int32_t* A, int64_t n, const int32_t* L, const i
   if (e != hipSuccess) return from_hip(e);
   stage_end(t, 0, s);
   stage_begin(t, 1);
-  e = launch_contract(A, n, E, q, aq, tiles, s);
+  // the sort left the positions only (int32) in the first half of E
+  e = launch_contract(A, n, reinterpret_cast<const int32_t*>(E), q, aq, tiles, s);
   if (e != hipSuccess) return from_hip(e);
   stage_end(t, 1, s);
   stage_begin(t, 2);
@@ -767,7 +768,7 @@ rmq_status rmq_contract(const int32_t* A, int64_t n, const int32_t* pos, const i
   e = launch_pack_endpoints(pos, tag, q, E, s);
   if (e == hipSuccess) e = launch_remap(E, q, LR, w, sort_b, s);
   if (e == hipSuccess)
-    e = launch_contract(A, n, E, q, aq, reinterpret_cast<int32_t*>(w + sort_b + list_b), s);
+    e = launch_contract(A, n, pos, q, aq, reinterpret_cast<int32_t*>(w + sort_b + list_b), s);
   hipFreeAsync(scratch, s);
   return from_hip(e);
 }

@@ -34,12 +34,12 @@ constexpr int TSHIFT = 10;
 constexpr int T = 1 << TSHIFT;  // contraction tile (elements of A per wave)
 constexpr int EPL = T / 64;     // elements per lane
 
-// Position of sorted endpoint j: the list holds (position << 32) | tag.
-__device__ __forceinline__ int64_t epos(const uint64_t* __restrict__ E, int64_t j) {
-  return (int64_t)(int32_t)(E[j] >> 32);
+// Position of sorted endpoint j (P: the sorted endpoint positions).
+__device__ __forceinline__ int64_t epos(const int32_t* __restrict__ P, int64_t j) {
+  return (int64_t)P[j];
 }
 
-__global__ __launch_bounds__(WG) void k_tiles(const uint64_t* __restrict__ E, int64_t M,
+__global__ __launch_bounds__(WG) void k_tiles(const int32_t* __restrict__ E, int64_t M,
                                               uint64_t* __restrict__ aq,
                                               int32_t* __restrict__ tile_start,
                                               int64_t num_tiles) {
@@ -67,7 +67,7 @@ __device__ __forceinline__ int stage_index(int e) { return (e >> 4) * BLOCK_WORD
 constexpr int KREG = 8;  // endpoint slots per lane held in registers (512 per tile)
 
 __global__ __launch_bounds__(WG) void k_contract(const int32_t* __restrict__ A, int64_t n,
-                                                 const uint64_t* __restrict__ E, int64_t M,
+                                                 const int32_t* __restrict__ E, int64_t M,
                                                  const int32_t* __restrict__ tile_start,
                                                  int64_t num_tiles, uint64_t* __restrict__ aq) {
   __shared__ __align__(16) int32_t vals[WG / 64][(T / 16) * BLOCK_WORDS];
@@ -114,14 +114,13 @@ __global__ __launch_bounds__(WG) void k_contract(const int32_t* __restrict__ A, 
   const int rounds = marked ? (int)((jend - jlo + 63) >> 6) : 0;
   int32_t ep[KREG], epv[KREG];
   if (marked) {
-    const int32_t* Eh = reinterpret_cast<const int32_t*>(E) + 1;  // high words: positions
     int32_t raw[KREG];
 #pragma unroll
     for (int k = 0; k < KREG; ++k) {
       const int64_t j = jlo + lane + 64 * k;
-      raw[k] = k < rounds ? Eh[2 * (j < M ? j : M - 1)] : 0;
+      raw[k] = k < rounds ? E[j < M ? j : M - 1] : 0;
     }
-    const int32_t raw_lo = Eh[2 * (jlo > 0 ? jlo - 1 : 0)];
+    const int32_t raw_lo = E[jlo > 0 ? jlo - 1 : 0];
 #pragma unroll
     for (int k = 0; k < KREG; ++k)
       ep[k] = jlo + lane + 64 * k < jend ? (int32_t)(raw[k] - t0) : T;
@@ -255,7 +254,7 @@ __global__ __launch_bounds__(WG) void k_contract(const int32_t* __restrict__ A, 
 
 }  // namespace
 
-hipError_t launch_contract(const int32_t* A, int64_t n, const uint64_t* E, int64_t q,
+hipError_t launch_contract(const int32_t* A, int64_t n, const int32_t* E, int64_t q,
                            uint64_t* aq, int32_t* tile_start, hipStream_t stream) {
   if (q <= 0) return hipSuccess;
   const int64_t M = 2 * q;

@@ -139,8 +139,10 @@ hipError_t launch_query_full2(const int32_t* A, int64_t n, int kshift, const uin
 // ---- contracted path (Section 3.1) ----
 // Device LSD radix sort of the 2q endpoints by (position, tag).  The sorted
 // list E holds (position << 32) | tag per slot.  With LR non-null the last
-// pass also writes the remap (as launch_remap does); pair_scratch, when
-// given, is 2q 8-byte items through which long sorts stage the remap.
+// pass also writes the remap (as launch_remap does) and, since the tags are
+// then used up, writes only the positions, as int32 in the first half of E;
+// pair_scratch, when given, is 2q 8-byte items through which long sorts
+// stage the remap.
 size_t sort_workspace_bytes(int64_t q);
 hipError_t launch_sort_endpoints(const int32_t* L, const int32_t* R, int64_t q, int64_t n,
                                  uint64_t* E, int32_t* LR, uint64_t* pair_scratch, void* ws,
@@ -160,10 +162,11 @@ hipError_t launch_unpack_endpoints(const uint64_t* E, int64_t q, int32_t* pos, i
                                    hipStream_t stream);
 hipError_t launch_pack_endpoints(const int32_t* pos, const int32_t* tag, int64_t q, uint64_t* E,
                                  hipStream_t stream);
-// Contraction: A_Q over the closed areas between consecutive endpoints.
+// Contraction: A_Q over the closed areas between consecutive endpoints,
+// given the 2q sorted endpoint positions E (int32).
 // tile_start: scratch of contract_tile_start_bytes(n).
 size_t contract_tile_start_bytes(int64_t n);
-hipError_t launch_contract(const int32_t* A, int64_t n, const uint64_t* E, int64_t q,
+hipError_t launch_contract(const int32_t* A, int64_t n, const int32_t* E, int64_t q,
                            uint64_t* aq, int32_t* tile_start, hipStream_t stream);
 hipError_t launch_query_contracted(const uint64_t* aq, int64_t m, int64_t n, int kshift,
                                    const uint64_t* st, int64_t nb, const int32_t* L,

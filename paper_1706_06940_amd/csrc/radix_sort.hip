@@ -391,17 +391,23 @@ __device__ __forceinline__ void os_pass(const uint64_t* __restrict__ items_in,
   __syncthreads();
 
   const int64_t tile_n = N - tile0 < TILE ? N - tile0 : TILE;
+  int32_t* pos_out = reinterpret_cast<int32_t*>(items_out);
   if (!WINDOWS) {
     for (int t = threadIdx.x; t < tile_n; t += WG) {
       const uint64_t x = s_item[t];
       const uint32_t dd = digit_of(x, shift, mask);
       const uint32_t dst = global_start[dd] + (uint32_t)t - local_start[dd];
       if ((int64_t)dst < N) {  // always true for consistent counts
-        items_out[dst] = x;
-        // last pass of the endpoint sort: the remap, LR[tag] = slot (minus
-        // one for a right end), written here directly
-        const uint32_t g = (uint32_t)x;
-        if (LR && (int64_t)g < N) LR[g] = (g & 1u) ? (int32_t)dst - 1 : (int32_t)dst;
+        if (LR) {
+          // last pass of the endpoint sort: the remap, LR[tag] = slot
+          // (minus one for a right end), written here directly, and the
+          // position alone (the tag is used up)
+          pos_out[dst] = (int32_t)(x >> 32);
+          const uint32_t g = (uint32_t)x;
+          if ((int64_t)g < N) LR[g] = (g & 1u) ? (int32_t)dst - 1 : (int32_t)dst;
+        } else {
+          items_out[dst] = x;
+        }
       }
     }
     return;
@@ -420,7 +426,7 @@ __device__ __forceinline__ void os_pass(const uint64_t* __restrict__ items_in,
     const uint32_t dd = digit_of(x, shift, mask);
     const uint32_t dst = global_start[dd] + (uint32_t)t - local_start[dd];
     if ((int64_t)dst >= N) continue;  // never, for consistent counts
-    items_out[dst] = x;
+    pos_out[dst] = (int32_t)(x >> 32);  // the position alone (the tag is used up)
     const uint32_t g = (uint32_t)x;
     const uint32_t w = min(g >> WIN_SHIFT, (uint32_t)nwin - 1u);
     pr[i] = ((uint64_t)g << 32) | dst;
