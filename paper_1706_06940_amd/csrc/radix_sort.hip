@@ -176,8 +176,9 @@ __global__ __launch_bounds__(WG) void k_os_clear(uint32_t* __restrict__ hist,
   for (int64_t i = i0; i < status_words; i += (int64_t)gridDim.x * WG) status0[i] = 0;
 }
 
-// Digit totals of every pass: per-workgroup counts in LDS over per_group
-// tiles, then one global atomic add per digit.
+// Digit totals of every pass: per-wave counts in LDS over per_group tiles
+// (the four waves do not contend for one set of counters), summed per
+// workgroup, then one global atomic add per digit.
 template <int MODE, int ROUNDS>
 __global__ __launch_bounds__(WG) void k_os_hist(const uint64_t* __restrict__ items_in,
                                                 const int32_t* __restrict__ L,
@@ -185,10 +186,12 @@ __global__ __launch_bounds__(WG) void k_os_hist(const uint64_t* __restrict__ ite
                                                 int64_t n, Digits dg, int per_group,
                                                 uint32_t* __restrict__ hist) {
   constexpr int TILE = WG * ROUNDS;
-  __shared__ uint32_t h[MAX_PASSES][RADIX];
+  __shared__ uint32_t h[WG / 64][MAX_PASSES][RADIX];  // one set of counters per wave
   const int lane = lane_id(), wave = threadIdx.x >> 6;
 #pragma unroll
-  for (int p = 0; p < MAX_PASSES; ++p) h[p][threadIdx.x] = 0;
+  for (int w = 0; w < WG / 64; ++w)
+#pragma unroll
+    for (int p = 0; p < MAX_PASSES; ++p) h[w][p][threadIdx.x] = 0;
   __syncthreads();
   for (int t = 0; t < per_group; ++t) {
     const int64_t tile0 = ((int64_t)blockIdx.x * per_group + t) * TILE;
@@ -204,12 +207,14 @@ __global__ __launch_bounds__(WG) void k_os_hist(const uint64_t* __restrict__ ite
     for (int rd = 0; rd < ROUNDS; ++rd) {
       if (item_index<ROUNDS>(tile0, wave, rd, lane) < N)
         for (int p = 0; p < dg.passes; ++p)
-          atomicAdd(&h[p][digit_of(it[rd], dg.shift[p], (1u << dg.bits[p]) - 1u)], 1u);
+          atomicAdd(&h[wave][p][digit_of(it[rd], dg.shift[p], (1u << dg.bits[p]) - 1u)], 1u);
     }
   }
   __syncthreads();
   for (int p = 0; p < dg.passes; ++p) {
-    const uint32_t c = h[p][threadIdx.x];
+    uint32_t c = 0;
+#pragma unroll
+    for (int w = 0; w < WG / 64; ++w) c += h[w][p][threadIdx.x];
     if (c) atomicAdd(&hist[p * RADIX + threadIdx.x], c);
   }
 }
