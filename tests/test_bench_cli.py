@@ -30,3 +30,22 @@ def test_help_lists_the_sections():
     for flag in ("--no-cpu", "--no-batched", "--no-served", "--no-skewed", "--no-lca", "--no-lary",
                  "--no-small", "--no-permutation"):
         assert flag in r.stdout, flag
+
+
+def test_profile_commands_use_current_flags():
+    """Every benchmark command quoted in profiles/ still names flags the
+    benchmark accepts, so each summary can be made again as written."""
+    import glob
+    import re
+    help_text = run_bench("--help").stdout
+    pdir = os.path.join(ROOT, "profiles")
+    seen = 0
+    for path in sorted(glob.glob(os.path.join(pdir, "*.md")) + glob.glob(os.path.join(pdir, "*.txt"))):
+        for line in open(path, encoding="utf-8"):
+            if "bench.py" not in line:
+                continue
+            tail = line.split("bench.py", 1)[1]
+            for flag in re.findall(r"(?<![\w-])--[a-z][a-z0-9-]*", tail):
+                assert flag in help_text, (os.path.basename(path), flag)
+                seen += 1
+    assert seen > 0
