@@ -60,14 +60,19 @@ def test_c3_billion_skewed(orc):
     log("done")
 
 
+# Host-heavy: the tree, its tour and the parent climbing take 1-2 minutes of
+# CPU time at this size, more on a loaded host; the GPU parts take seconds.
+@pytest.mark.timeout(600)
 def test_c3_lca_half_billion_nodes(orc):
     d = need_gpu()
     say("c3_lca")
     N, q, seed = 5 * 10 ** 8, 10 ** 7, W.BASE_SEED + 2
     log("tree")
     parent = W.random_recursive_tree(N, seed)
-    log("euler tour")
-    depth, node, first = W.euler_tour(parent)
+    log("oracle tour")
+    # the oracle's tour is both the RMQ input and the device tour's expected value
+    exp = orc.euler_tour(parent)
+    depth, node, first = exp
     assert depth.shape[0] == 2 * N - 1
     u, v, L, R = W.lca_queries(first, q, seed)
     log("rmq on the gpu")
@@ -97,8 +102,6 @@ def test_c3_lca_half_billion_nodes(orc):
     h = rmq.LCA(dev(parent, d))
     got2 = h.query(dev(u, d), dev(v, d)).cpu().numpy()
     assert np.array_equal(got2, a)
-    log("oracle tour")
-    exp = orc.euler_tour(parent)
     tour = [t.cpu().numpy() for t in h.tour()]
     h.free()
     assert all(np.array_equal(x, y) for x, y in zip(tour, exp))
