@@ -234,20 +234,21 @@ def main() -> int:
                     "traffic_source": os.path.relpath(TRAFFIC_PROFILE, ROOT)}
 
     # the part's achievable read rate for this pass: the same loads over the
-    # same A, keeping nothing (25 launches timed by their own events)
-    if roofline is not None:
+    # same A, keeping nothing (25 launches timed by events attached to them;
+    # the bench's own helper library, not part of librmq)
+    probe = read_probe_lib()
+    if roofline is not None and probe is not None:
         sink = torch.zeros(1, dtype=torch.int32, device=d)
-        stream = torch.cuda.current_stream(d)
-        rmq.read_probe(A, sink, reps=2)
-        t_pr = rmq.Timer()
-        rmq.read_probe(A, sink, reps=25, timer=t_pr)  # back to back, launch-attached events
-        probe_ms = t_pr.read()[1] / 25
-        probe_gbs = 16 * (n // 4) / (probe_ms / 1e3) / 1e9  # 4 floor(n/4) int32 read
-        roofline["read_ceiling"] = {
-            "achieved": round(probe_gbs, 1), "frac": round(probe_gbs / HBM_PEAK_GBS, 4),
-            "kernel_over_ceiling": round(roofline["achieved"] / probe_gbs, 4),
-            "how": "rmq_read_probe: the block-minima loads over the same A with nothing kept, "
-                   "mean of 25 back-to-back launches"}
+        s_ptr = int(torch.cuda.current_stream(d).cuda_stream)
+        probe.bench_read_probe_ms(A.data_ptr(), n, sink.data_ptr(), 2, s_ptr)
+        probe_ms = probe.bench_read_probe_ms(A.data_ptr(), n, sink.data_ptr(), 25, s_ptr)
+        if probe_ms > 0:
+            probe_gbs = 16 * (n // 4) / (probe_ms / 1e3) / 1e9  # 4 floor(n/4) int32 read
+            roofline["read_ceiling"] = {
+                "achieved": round(probe_gbs, 1), "frac": round(probe_gbs / HBM_PEAK_GBS, 4),
+                "kernel_over_ceiling": round(roofline["achieved"] / probe_gbs, 4),
+                "how": "bench_aux/read_probe.hip: the block-minima loads over the same A with "
+                       "nothing kept, mean of 25 back-to-back launches"}
 
     # the same block-minima launches after a 1 GB write that evicts A from the
     # L2s and the MALL (the paper's cache flush before every repetition)
@@ -361,6 +362,23 @@ def main() -> int:
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_blockmin_i32_n1e8_traffic.md")
+
+
+def read_probe_lib():
+    """The benchmark's read-rate helper (bench_aux/libreadprobe.so), or None
+    when it has not been built."""
+    import ctypes
+
+    path = os.path.join(ROOT, "bench_aux", "libreadprobe.so")
+    if not os.path.exists(path):
+        print("[bench] bench_aux/libreadprobe.so not built: no read ceiling", file=sys.stderr,
+              flush=True)
+        return None
+    lib = ctypes.CDLL(path)
+    v = ctypes.c_void_p
+    lib.bench_read_probe_ms.argtypes = [v, ctypes.c_int64, v, ctypes.c_int32, v]
+    lib.bench_read_probe_ms.restype = ctypes.c_float
+    return lib
 
 
 def profiled_traffic(n: int):

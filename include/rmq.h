@@ -311,17 +311,6 @@ rmq_status rmq_lca_free(rmq_lca h);
 rmq_status rmq_block_minima(const int32_t *A, int64_t n, int32_t block_size, uint64_t *keys,
                             void *stream);
 
-/* Measurement aid, not a step of the method: one streaming read of A[0 ..
- * 4 floor(n/4)) with the access pattern of rmq_block_minima (16-byte
- * non-temporal loads, 4 KB per wave) that computes nothing kept, so that its
- * time is the part's achievable read rate for this pass.  A: device, 16-byte
- * aligned, n >= 4.  sink: device uint32, written only in a case that does
- * not occur (keeps the loads live).  reps (1..1000) launches are enqueued
- * back to back.  timer (optional): its stage 1 spans the reps launches,
- * timed by events attached to the launches as for the method's stages. */
-rmq_status rmq_read_probe(const int32_t *A, int64_t n, uint32_t *sink, int32_t reps,
-                          void *stream, rmq_timer *timer);
-
 /* Same over a key array (the contracted array A_Q of the CONTRACTED path):
  * keys[j] = min of src[j*k .. min((j+1)*k, m) - 1]. */
 rmq_status rmq_block_minima_keys(const uint64_t *src, int64_t m, int32_t block_size,

@@ -41,8 +41,6 @@ def load(path: str | None = None, fresh: bool = False):
     lib.oracle_set_threads.argtypes = [i32]
     lib.oracle_rmq_scan.argtypes = [v, i64, v, v, i64, v]
     lib.oracle_rmq_scan.restype = i64
-    lib.oracle_sparse_table_bytes.argtypes = [i64, i64]
-    lib.oracle_sparse_table_bytes.restype = i64
     lib.oracle_rmq_sparse_table.argtypes = [v, i64, i64, v, v, i64, v]
     lib.oracle_rmq_sparse_table.restype = i64
     lib.oracle_block_argmin.argtypes = [v, i64, i64, v]

@@ -97,15 +97,6 @@ int64_t oracle_rmq_scan(const int32_t *A, int64_t n, const int32_t *L, const int
     return bad;
 }
 
-/* Bytes of the table oracle_rmq_sparse_table builds for (n, b). */
-int64_t oracle_sparse_table_bytes(int64_t n, int64_t b)
-{
-    int64_t nb = n / b;
-    if (nb < 1)
-        return 0;
-    return (int64_t)sizeof(int32_t) * nb * (floor_log2(nb) + 1);
-}
-
 /* Section 2: Sparse Table over the nb = floor(n / b) whole blocks of b
  * elements.  M[j][i] is the minimum over blocks i .. i + 2^j - 1 (only
  * windows that fit are formed): M[0][i] scans block i, and M[j][i] is the

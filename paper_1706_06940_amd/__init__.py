@@ -96,7 +96,6 @@ def lib() -> ctypes.CDLL:
         "rmq_table_levels": ([i64], i32),
         "rmq_table_levels_ary": ([i64, i32], i32),
         "rmq_query_record_bytes": ([i64], sz),
-        "rmq_read_probe": ([v, i64, v, i32, v, v], i32),
         "rmq_block_minima": ([v, i64, i32, v, v], i32),
         "rmq_block_minima_keys": ([v, i64, i32, v, v], i32),
         "rmq_sparse_table_build": ([v, i64, i32, v], i32),
@@ -280,18 +279,6 @@ def query_record_bytes(num_blocks: int) -> int:
     return int(lib().rmq_query_record_bytes(num_blocks))
 
 
-def read_probe(A: torch.Tensor, sink: torch.Tensor, reps: int = 1, stream=None,
-               timer: Optional[Timer] = None) -> None:
-    """reps streaming reads of A with the block-minima pass's loads, back to
-    back (a measurement aid: their time is the achievable read rate of that
-    pass); with a timer, its stage 1 spans them."""
-    if sink.dtype != torch.int32 or not sink.is_cuda:
-        raise TypeError("sink must be a CUDA int32 tensor")
-    _check("rmq_read_probe", lib().rmq_read_probe(_dev_i32(A, "A"), A.numel(), sink.data_ptr(),
-                                                  int(reps), _stream(A.device, stream),
-                                                  timer.handle if timer is not None else None))
-
-
 def table_levels(num_blocks: int, arity_log2: int = 0) -> int:
     """Levels of the block table: doubling, or over powers of
     l = 2^arity_log2 (Section 3.1)."""
@@ -428,17 +415,6 @@ def contract(A: torch.Tensor, pos: torch.Tensor, tag: torch.Tensor, stream=None)
             _dev_i32(A, "A"), A.numel(), _dev_i32(pos, "pos"), _dev_i32(tag, "tag"), q,
             _dev_i32(LR, "LR"), aq.data_ptr(), _stream(A.device, stream)))
     return LR[0::2], LR[1::2], aq
-
-
-def key_positions(keys: torch.Tensor) -> torch.Tensor:
-    """Low 32 bits of keys (the positions in A)."""
-    return (keys & 0xFFFFFFFF).to(torch.int32)
-
-
-def key_values(keys: torch.Tensor) -> torch.Tensor:
-    """High 32 bits of keys mapped back to the int32 values."""
-    u = ((keys >> 32) & 0xFFFFFFFF) ^ 0x80000000
-    return torch.where(u >= 2 ** 31, u - 2 ** 32, u).to(torch.int32)
 
 
 class LCA:

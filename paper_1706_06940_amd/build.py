@@ -27,7 +27,6 @@ SOURCES = [
     "capi.hip",
     "server.hip",
     "lca.hip",
-    "probe.hip",
 ]
 
 ARCH = "gfx950"

@@ -686,24 +686,6 @@ rmq_status rmq_block_minima(const int32_t* A, int64_t n, int32_t k, uint64_t* ke
   return from_hip(launch_blockmin_i32(A, n, ilog2_i64(k), keys, static_cast<hipStream_t>(stream)));
 }
 
-rmq_status rmq_read_probe(const int32_t* A, int64_t n, uint32_t* sink, int32_t reps,
-                          void* stream, rmq_timer* timer) {
-  if (!A || !sink || n < 4 || n > RMQ_MAX_N || reps < 1 || reps > 1000)
-    return RMQ_ERR_INVALID_ARG;
-  if (!aligned_to(A, 16) || !aligned_to(sink, 4)) return RMQ_ERR_MISALIGNED;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  ClockGuard guard;
-  if (timer)
-    for (int i = 0; i < RMQ_NUM_STAGES; ++i) timer->ran[i] = false;
-  stage_begin(timer, 1);  // the launches' own events, as for block minima
-  for (int32_t r = 0; r < reps; ++r) {
-    const hipError_t e = launch_read_probe(A, n, sink, s);
-    if (e != hipSuccess) return from_hip(e);
-  }
-  stage_end(timer, 1, s);
-  return RMQ_OK;
-}
-
 rmq_status rmq_block_minima_keys(const uint64_t* src, int64_t m, int32_t k, uint64_t* keys,
                                  void* stream) {
   if (!src || !keys || m < 1 || m > 2 * RMQ_MAX_Q || !is_pow2_block(k)) return RMQ_ERR_INVALID_ARG;

@@ -84,9 +84,6 @@ hipError_t launch_blockmin_i32(const int32_t* A, int64_t n, int kshift, uint64_t
                                hipStream_t stream);
 hipError_t launch_blockmin_keys(const uint64_t* S, int64_t m, int kshift, uint64_t* keys,
                                 hipStream_t stream);
-// Streaming read of the first 4 floor(n/4) elements of A (16-byte loads)
-// that keeps nothing: the read rate block minima are measured against.
-hipError_t launch_read_probe(const int32_t* A, int64_t n, uint32_t* sink, hipStream_t stream);
 hipError_t launch_sparse_table(uint64_t* st, int64_t nb, int levels, hipStream_t stream);
 // l-ary table (Section 3.1), l = 2^lg >= 4: level i holds the minima over
 // l^i blocks (truncated at nb); levels = lary_levels(nb, lg).  Level 0 given.

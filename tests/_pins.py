@@ -129,7 +129,9 @@ def node_depths(parent):
 def check_lca(orc):
     for N, seed in ((1, 1), (2, 2), (10, 3), (100, 4), (1000, 5), (4000, 6)):
         parent = W.random_recursive_tree(N, seed)
-        depth, node, first = W.euler_tour(parent)
+        tour = orc.euler_tour(parent)
+        assert tour is not None, (N, seed)
+        depth, node, first = tour
         assert np.all(np.abs(np.diff(depth)) == 1)
         dn = node_depths(parent)
         u, v, L, R = W.lca_queries(first, 500, seed)
@@ -230,7 +232,9 @@ def check_golden(orc):
     assert aq.tolist() == c["aq_pos"]
     assert orc.contracted_answer(A, aq, Lc, Rc).tolist() == c["answers"]
     lg = g["lca"]
-    depth, node, first = W.euler_tour(np.array(lg["parent"], dtype=np.int32))
+    tour = orc.euler_tour(np.array(lg["parent"], dtype=np.int32))
+    assert tour is not None
+    depth, node, first = tour
     assert depth.tolist() == lg["euler_depth"] and node.tolist() == lg["euler_node"]
     assert first.tolist() == lg["first"]
     u = np.array([e["u"] for e in lg["queries"]])

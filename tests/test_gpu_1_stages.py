@@ -144,19 +144,3 @@ def test_device_generator_matches_host():
     Ln, Rn = W.uniform_queries(10 ** 8, 20_000, 6, 8)
     assert np.array_equal(Lt.cpu().numpy(), Ln) and np.array_equal(Rt.cpu().numpy(), Rn)
 
-
-def test_read_probe_runs_and_rejects_bad_input():
-    """The measurement aid (a read of A keeping nothing) runs on a real array
-    and leaves its sink alone; bad arguments are refused on the host."""
-    d = need_gpu()
-    say("read_probe")
-    A = torch.zeros(1 << 20, dtype=torch.int32, device=d)
-    sink = torch.zeros(1, dtype=torch.int32, device=d)
-    rmq.read_probe(A, sink, reps=3)
-    assert int(host(sink)[0]) == 0
-    with pytest.raises(rmq.RMQError):
-        rmq.read_probe(A[:3], sink)
-    with pytest.raises(rmq.RMQError):
-        rmq.read_probe(A[1:], sink)  # not 16-byte aligned
-    with pytest.raises(rmq.RMQError):
-        rmq.read_probe(A, sink, reps=0)

@@ -100,7 +100,7 @@ def test_lca_euler_tour(orc, path):
     for N, seed in ((1, 1), (1000, 2), (200_000, 3)):
         say("lca", path, N)
         parent = W.random_recursive_tree(N, seed)
-        depth, node, first = W.euler_tour(parent)
+        depth, node, first = orc.euler_tour(parent)
         u, v, L, R = W.lca_queries(first, 4000, seed)
         got = run(dev(depth, d), L, R, path, 256, d)
         assert np.array_equal(got, orc.rmq_scan(depth, L, R))

@@ -117,7 +117,7 @@ def test_lca_with_lary_table(orc):
     say("lary_lca")
     N = 200_003
     parent = W.random_recursive_tree(N, 75)
-    depth, node, first = W.euler_tour(parent)
+    depth, node, first = orc.euler_tour(parent)
     u = W.uniform_index(N, 20_000, 75, 1).astype(np.int32)
     v = W.uniform_index(N, 20_000, 75, 2).astype(np.int32)
     lo = np.minimum(first[u], first[v]).astype(np.int32)

@@ -87,7 +87,7 @@ def test_index_two_level_lca_and_serving_agree(orc):
         assert torch.equal(on.table(), off.table())
     N = 100_003
     parent = W.random_recursive_tree(N, 99)
-    depth, node, first = W.euler_tour(parent)
+    depth, node, first = orc.euler_tour(parent)
     u = W.uniform_index(N, 20_000, 99, 1).astype(np.int32)
     v = W.uniform_index(N, 20_000, 99, 2).astype(np.int32)
     lo = np.minimum(first[u], first[v]).astype(np.int32)

@@ -20,8 +20,9 @@ regenerated piecewise.  Derived draws:
 Workload shapes follow the experiments section of the paper (uniform query
 endpoints drawn over the whole array and swapped when the left one is larger)
 and the configurations the library is benchmarked on (uniform int32 values,
-short/long query mixes, log-uniform batch sizes, Euler tours of random
-recursive trees for the LCA reduction of the introduction).
+short/long query mixes, log-uniform batch sizes, random recursive trees as
+parent arrays for the LCA reduction of the introduction).  Tours of those
+trees are not drawn here: tests take them from the oracle.
 """
 from __future__ import annotations
 
@@ -213,8 +214,6 @@ def _lib():
             _b.build()
         lib = ctypes.CDLL(path)
         i64, p = ctypes.c_int64, ctypes.c_void_p
-        lib.wl_euler_tour.argtypes = [p, i64, p, p, p]
-        lib.wl_euler_tour.restype = ctypes.c_int
         lib.wl_swap_permutation.argtypes = [p, i64, p, p, i64]
         lib.wl_swap_permutation.restype = None
         _LIB = lib
@@ -237,25 +236,10 @@ def random_recursive_tree(N: int, seed: int, stream: int = 7) -> np.ndarray:
     return parent
 
 
-def euler_tour(parent: np.ndarray):
-    """Euler tour of the tree given by `parent` (children visited in increasing
-    id).  Returns (depth, node, first): depth[t] and node[t] for the 2N-1 tour
-    steps, and first[v], the first step that visits v.  Consecutive depths
-    differ by exactly one."""
-    N = int(parent.shape[0])
-    parent = np.ascontiguousarray(parent, dtype=np.int32)
-    depth = np.empty(2 * N - 1, dtype=np.int32)
-    node = np.empty(2 * N - 1, dtype=np.int32)
-    first = np.empty(N, dtype=np.int32)
-    rc = _lib().wl_euler_tour(_ptr(parent), N, _ptr(depth), _ptr(node), _ptr(first))
-    if rc != 0:
-        raise RuntimeError(f"euler tour failed ({rc})")
-    return depth, node, first
-
-
 def lca_queries(first: np.ndarray, q: int, seed: int, stream: int = 9):
-    """q LCA queries (u, v uniform over the nodes) turned into RMQ ranges
-    [min(first[u], first[v]), max(...)] over the Euler depth array.
+    """q LCA queries (u, v uniform over the nodes) and their ranges
+    [min(first[u], first[v]), max(...)] over a tour's depth array, where
+    `first` (first visit of each node) comes from the caller's tour.
     Returns (u, v, L, R)."""
     N = int(first.shape[0])
     u = uniform_index(N, q, seed, stream)
