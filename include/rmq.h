@@ -43,6 +43,16 @@
  * the device; other queries are unaffected.  q = 0 is a no-op returning
  * RMQ_OK.  No C++ exception crosses this interface.
  *
+ * Sort failure: the device radix sort of the CONTRACTED method (and of the
+ * LCA build) waits for earlier tiles with a bounded wait.  Should a wait run
+ * out (a predecessor stalled for millions of polls), the sort gives up on
+ * its order and says so in a device word; nothing reads memory out of
+ * bounds and every kernel ends.  The call then reports the failure instead
+ * of wrong answers: the CONTRACTED method answers -1 for EVERY query of the
+ * batch and adds q to *bad_count; rmq_sort_endpoints writes -1 to every pos
+ * and tag; rmq_contract writes -1 to every LR entry; rmq_lca_build returns
+ * RMQ_ERR_DEVICE.  (rmq_test_sort_abort forces this path for tests.)
+ *
  * Value encoding used by the key-valued outputs (block minima, Sparse Table
  * entries, A_Q): key(p) = ((uint32(A[p]) XOR 0x80000000) << 32) | p, a
  * uint64.  Comparing keys as unsigned integers compares (A[p], p)
@@ -280,7 +290,8 @@ typedef struct rmq_lca_s *rmq_lca;
  * table_arity_log2 choose the RMQ index over D as for rmq_build (NULL:
  * defaults).  The call waits
  * for the device (it checks the input and the tour) and returns
- * RMQ_ERR_INVALID_ARG for a forest, a parent out of range or a cycle.
+ * RMQ_ERR_INVALID_ARG for a forest, a parent out of range or a cycle, and
+ * RMQ_ERR_DEVICE if the sort of the children gave up (see "Sort failure").
  * Temporary device memory: about 60 bytes per node, freed before return. */
 rmq_status rmq_lca_build(const int32_t *parent, int64_t num_nodes, const rmq_options *opt,
                          void *stream, rmq_lca *out);
@@ -325,7 +336,8 @@ rmq_status rmq_sparse_table_build(uint64_t *st, int64_t num_blocks, int32_t leve
 /* Section 3.1 step 1: the 2q endpoints (L[i], tag 2i) and (R[i], tag 2i+1)
  * sorted by (position, tag) with a device LSD radix sort.  pos, tag:
  * int32[2q].  Endpoint positions must lie in [0, n); an invalid query's
- * endpoints are sorted as position 0.  Needs rmq_sort_workspace_bytes(q). */
+ * endpoints are sorted as position 0.  Needs rmq_sort_workspace_bytes(q).
+ * If the sort gives up (see "Sort failure" above), every pos and tag is -1. */
 rmq_status rmq_sort_endpoints(const int32_t *L, const int32_t *R, int64_t q, int64_t n,
                               int32_t *pos, int32_t *tag, void *workspace,
                               size_t workspace_bytes, void *stream);
@@ -336,7 +348,9 @@ size_t rmq_sort_workspace_bytes(int64_t q);
  * the slot of its right end minus one -- and build A_Q: aq[s] = min key over
  * the CLOSED area A[pos[s] .. pos[s+1]], s = 0 .. 2q-2.  pos, tag: the
  * output of rmq_sort_endpoints.  LR: int32[2q] (8-byte aligned);
- * aq: uint64[2q-1].  Takes its scratch from the stream-ordered pool. */
+ * aq: uint64[2q-1].  Takes its scratch from the stream-ordered pool.  The
+ * remap buckets the tags with one more sort sweep; if that sweep gives up
+ * (see "Sort failure" above), every LR entry is -1. */
 rmq_status rmq_contract(const int32_t *A, int64_t n, const int32_t *pos, const int32_t *tag,
                         int64_t q, int32_t *LR, uint64_t *aq, void *stream);
 
@@ -469,6 +483,15 @@ double rmq_server_clock(void);
 
 /* Drain every queued request, stop the threads and free everything. */
 rmq_status rmq_server_destroy(rmq_server s);
+
+/* ----------------------------------------------------------------------------
+ * For tests of the failure report only; not for production callers.
+ * on != 0: every endpoint or pair sort enqueued afterwards in this process
+ * starts with its abort word already set, as if a bounded wait had run out,
+ * so that each wait ends at its first unpublished predecessor, every kernel
+ * exits normally, and the call reports the failure as described under "Sort
+ * failure".  on = 0 restores normal sorting.  Process-wide. */
+rmq_status rmq_test_sort_abort(int32_t on);
 
 /* ----------------------------------------------------------------------------
  * Per-stage timing (Table 1's stages).  A timer collects HIP events that

@@ -108,6 +108,7 @@ def lib() -> ctypes.CDLL:
         "rmq_batch_item_plan": ([v, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
         "rmq_batch_workspace_bytes": ([v], sz),
         "rmq_batch_free": ([v], i32),
+        "rmq_test_sort_abort": ([i32], i32),
         "rmq_timer_create": ([ctypes.POINTER(v)], i32),
         "rmq_timer_read": ([v, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)], i32),
         "rmq_timer_destroy": ([v], i32),
@@ -228,6 +229,12 @@ def load_plan_table(path: str = TUNE_TABLE) -> bool:
     set_plan_table((e["n"], e["q"], e["block_size"], e["path"], e.get("sub_block_size", 0),
                     e.get("one_level_block_size", 0)) for e in data["entries"])
     return True
+
+
+def test_sort_abort(on: bool) -> None:
+    """For tests of the failure report only: every later device sort starts
+    as if a bounded wait had run out (rmq_test_sort_abort)."""
+    _check("rmq_test_sort_abort", lib().rmq_test_sort_abort(1 if on else 0))
 
 
 def version() -> str:

@@ -394,9 +394,12 @@ rmq_status run_contracted(const int32_t* A, int64_t n, const int32_t* L, const i
   if (e != hipSuccess) return from_hip(e);
   stage_end(t, 2, s);
   stage_begin(t, 3);
+  // a sort that gave up on its order (bounded look-back wait exceeded) makes
+  // the query kernel answer -1 for every query and count them all as invalid
   e = launch_query_contracted(aq, c.m, n, p.kshift, st, c.nb, L, R, LR, q, out,
                               opt ? opt->bad_count : nullptr, opt ? opt->stats : nullptr, s,
-                              p.lg, rec, c.levels, sub, p.k1shift);
+                              p.lg, rec, c.levels, sub, p.k1shift,
+                              sort_abort_word(ws + c.off_sort, q));
   if (e != hipSuccess) return from_hip(e);
   stage_end(t, 3, s);
   return RMQ_OK;
@@ -726,7 +729,7 @@ rmq_status rmq_sort_endpoints(const int32_t* L, const int32_t* R, int64_t q, int
   const size_t sort_b = align_up(sort_workspace_bytes(q));
   uint64_t* E = reinterpret_cast<uint64_t*>(static_cast<char*>(workspace) + sort_b);
   hipError_t e = launch_sort_endpoints(L, R, q, n, E, nullptr, nullptr, workspace, sort_b, s);
-  if (e == hipSuccess) e = launch_unpack_endpoints(E, q, pos, tag, s);
+  if (e == hipSuccess) e = launch_unpack_endpoints(E, q, pos, tag, sort_abort_word(workspace, q), s);
   return from_hip(e);
 }
 
@@ -753,6 +756,11 @@ rmq_status rmq_contract(const int32_t* A, int64_t n, const int32_t* pos, const i
     e = launch_contract(A, n, pos, q, aq, reinterpret_cast<int32_t*>(w + sort_b + list_b), s);
   hipFreeAsync(scratch, s);
   return from_hip(e);
+}
+
+rmq_status rmq_test_sort_abort(int32_t on) {
+  set_sort_abort_preset(on != 0);
+  return RMQ_OK;
 }
 
 // ---- timers ----

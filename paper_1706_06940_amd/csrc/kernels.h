@@ -154,9 +154,17 @@ hipError_t launch_remap(const uint64_t* E, int64_t q, int32_t* LR, void* ws, siz
 size_t sort_pairs_workspace_bytes(int64_t N);
 hipError_t launch_sort_pairs(const uint64_t* items, int64_t N, int key_bits, uint64_t* out,
                              void* ws, size_t ws_bytes, hipStream_t stream);
-// Split E into positions and tags, or join them into E.
+// The sort's abort word inside its workspace (for q queries, or N items of
+// sort_pairs): nonzero after a sort whose bounded look-back wait gave up, so
+// that its order cannot be trusted.  Device pointer; null for an empty sort.
+const uint32_t* sort_abort_word(const void* ws, int64_t q);
+const uint32_t* sort_pairs_abort_word(const void* ws, int64_t N);
+// Tests of the failure report: every later sort's abort word starts set.
+void set_sort_abort_preset(bool on);
+// Split E into positions and tags (all -1 if the sort's abort word is set),
+// or join them into E.
 hipError_t launch_unpack_endpoints(const uint64_t* E, int64_t q, int32_t* pos, int32_t* tag,
-                                   hipStream_t stream);
+                                   const uint32_t* abort_word, hipStream_t stream);
 hipError_t launch_pack_endpoints(const int32_t* pos, const int32_t* tag, int64_t q, uint64_t* E,
                                  hipStream_t stream);
 // Contraction: A_Q over the closed areas between consecutive endpoints,
@@ -165,11 +173,13 @@ hipError_t launch_pack_endpoints(const int32_t* pos, const int32_t* tag, int64_t
 size_t contract_tile_start_bytes(int64_t n);
 hipError_t launch_contract(const int32_t* A, int64_t n, const int32_t* E, int64_t q,
                            uint64_t* aq, int32_t* tile_start, hipStream_t stream);
+// fail: the endpoint sort's abort word; when it is set every query is
+// answered -1 and counted in bad_count.
 hipError_t launch_query_contracted(const uint64_t* aq, int64_t m, int64_t n, int kshift,
                                    const uint64_t* st, int64_t nb, const int32_t* L,
                                    const int32_t* R, const int32_t* LR, int64_t q, int32_t* out,
                                    int64_t* bad_count, uint64_t* stats, hipStream_t stream,
-                                   int lg = 1, const uint64_t* rec = nullptr, int rlev = 0,
-                                   const uint64_t* sub = nullptr, int k1shift = -1);
+                                   int lg, const uint64_t* rec, int rlev, const uint64_t* sub,
+                                   int k1shift, const uint32_t* fail);
 
 }  // namespace rmq

@@ -280,6 +280,18 @@ rmq_status build_tour(const int32_t* parent, int64_t N, int32_t root, rmq_lca_s*
     RMQ_TRY(hipMemsetAsync(stat, 0, 4 * 8, s));
     RMQ_TRY(launch(k_lca_items, dim3((unsigned)blocks(N)), dim3(WG), 0, s, parent, N, items));
     RMQ_TRY(launch_sort_pairs(items, N, bits_for((uint64_t)N), sorted, t + o_sort, sort_ws, s));
+    {
+      // a sort whose bounded look-back wait gave up leaves no usable order:
+      // report it before anything reads the list
+      uint32_t h_abort = 0;
+      RMQ_TRY(hipMemcpyAsync(&h_abort, sort_pairs_abort_word(t + o_sort, N), 4,
+                             hipMemcpyDeviceToHost, s));
+      RMQ_TRY(hipStreamSynchronize(s));
+      if (h_abort) {
+        st = RMQ_ERR_DEVICE;
+        return hipSuccess;
+      }
+    }
     RMQ_TRY(launch(k_fill_i32, dim3((unsigned)blocks(N)), dim3(WG), 0, s, fc, N, -1));
     RMQ_TRY(launch(k_fill_i32, dim3((unsigned)blocks(N)), dim3(WG), 0, s, ns, N, -1));
     RMQ_TRY(launch(k_fill_i32, dim3((unsigned)blocks(NA)), dim3(WG), 0, s, owner, NA, -1));

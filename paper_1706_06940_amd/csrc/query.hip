@@ -430,7 +430,10 @@ __device__ __forceinline__ void query_core(const Src& src, int64_t src_len, int6
 // One table.  L, R: the queries' positions in A.  For the contracted path, LR
 // holds their contracted index ranges as interleaved pairs (LR[2i],
 // LR[2i+1]); for the plain path LR is null and the ranges are [L[i], R[i]]
-// themselves.  src_len: number of source entries (n or 2q - 1).
+// themselves.  src_len: number of source entries (n or 2q - 1).  fail
+// (contracted path): the endpoint sort's abort word; when it is set the
+// contracted ranges cannot be trusted, and every query is answered -1 and
+// counted as invalid.
 template <class Src>
 __global__ __launch_bounds__(WG) void k_query(Src src, int64_t src_len, int64_t n, int kshift,
                                               const uint64_t* __restrict__ st, int64_t nb,
@@ -440,11 +443,13 @@ __global__ __launch_bounds__(WG) void k_query(Src src, int64_t src_len, int64_t 
                                               int32_t* __restrict__ out,
                                               unsigned long long* __restrict__ bad_count,
                                               unsigned long long* __restrict__ stats, int lg,
-                                              const uint64_t* __restrict__ rec, int rlev) {
+                                              const uint64_t* __restrict__ rec, int rlev,
+                                              const uint32_t* __restrict__ fail) {
   const int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
   const bool live = i < q;
+  const bool failed = fail && *fail != 0;  // uniform: one scalar load
   int64_t l = 0, r = -1, li = 0, ri = -1;
-  if (live) {
+  if (live && !failed) {
     l = L[i];
     r = R[i];
     if (LR) {
@@ -561,7 +566,8 @@ hipError_t launch_query_full(const int32_t* A, int64_t n, int kshift, const uint
   const int64_t grid = (q + WG - 1) / WG;
   RMQ_TRY(launch(k_query<SrcA>, dim3((unsigned)grid), dim3(WG), 0, stream, SrcA{A, n}, n, n,
                  kshift, st, nb, L, R, static_cast<const int32_t*>(nullptr), q, out,
-                 (unsigned long long*)bad_count, (unsigned long long*)stats, lg, rec, rlev));
+                 (unsigned long long*)bad_count, (unsigned long long*)stats, lg, rec, rlev,
+                 static_cast<const uint32_t*>(nullptr)));
   return hipGetLastError();
 }
 
@@ -576,7 +582,7 @@ hipError_t launch_query_full2(const int32_t* A, int64_t n, int kshift, const uin
   RMQ_TRY(launch(k_query<SrcA2>, dim3((unsigned)grid), dim3(WG), 0, stream,
                  SrcA2{SrcA{A, n}, sub, nsub, k1shift}, n, n, kshift, st, nb, L, R,
                  static_cast<const int32_t*>(nullptr), q, out, (unsigned long long*)bad_count,
-                 (unsigned long long*)stats, lg, rec, rlev));
+                 (unsigned long long*)stats, lg, rec, rlev, static_cast<const uint32_t*>(nullptr)));
   return hipGetLastError();
 }
 
@@ -605,7 +611,7 @@ hipError_t launch_query_contracted(const uint64_t* aq, int64_t m, int64_t n, int
                                    const int32_t* R, const int32_t* LR, int64_t q, int32_t* out,
                                    int64_t* bad_count, uint64_t* stats, hipStream_t stream,
                                    int lg, const uint64_t* rec, int rlev, const uint64_t* sub,
-                                   int k1shift) {
+                                   int k1shift, const uint32_t* fail) {
   if (q <= 0) return hipSuccess;
   const int64_t grid = (q + WG - 1) / WG;
   if (sub) {
@@ -613,11 +619,11 @@ hipError_t launch_query_contracted(const uint64_t* aq, int64_t m, int64_t n, int
     RMQ_TRY(launch(k_query<SrcKeys2>, dim3((unsigned)grid), dim3(WG), 0, stream,
                    SrcKeys2{SrcKeys{aq, m}, sub, nsub, k1shift}, m, n, kshift, st, nb, L, R, LR,
                    q, out, (unsigned long long*)bad_count, (unsigned long long*)stats, lg, rec,
-                   rlev));
+                   rlev, fail));
   } else {
     RMQ_TRY(launch(k_query<SrcKeys>, dim3((unsigned)grid), dim3(WG), 0, stream, SrcKeys{aq, m},
                    m, n, kshift, st, nb, L, R, LR, q, out, (unsigned long long*)bad_count,
-                   (unsigned long long*)stats, lg, rec, rlev));
+                   (unsigned long long*)stats, lg, rec, rlev, fail));
   }
   return hipGetLastError();
 }

@@ -24,6 +24,12 @@
 //                  that took their ticket earlier and are therefore running,
 //                  so the waits end; each is also bounded, and an exceeded
 //                  bound sets an abort word that ends every wait at once.
+//                  A sort whose abort word is set has given up on its order:
+//                  the word stays set for the kernels after it, which then
+//                  report the failure instead of their results (the query
+//                  kernel answers -1 for every query and counts each as
+//                  invalid; the stand-alone stages write -1; the LCA build
+//                  returns an error).
 // Items are 8 bytes, (position << 32) | tag, so each digit run a tile writes
 // is whole cache lines; the key bits are split into the fewest passes of at
 // most 8 bits with equal widths (27 bits -> 7, 7, 7, 6).
@@ -41,10 +47,19 @@
 // (tag, slot) pairs by the top bits of the tag with one more sweep and then
 // writes window by window, each window of the interleaved LR array while it
 // sits in one XCD's L2.
+#include <atomic>
+
 #include "device.h"
 #include "kernels.h"
 
 namespace rmq {
+
+// Value every later sort's abort word starts at (tests of the failure
+// report set it to 1, so that each wait ends at once; see
+// set_sort_abort_preset).
+static std::atomic<uint32_t> g_abort_preset{0};
+
+void set_sort_abort_preset(bool on) { g_abort_preset.store(on ? 1u : 0u); }
 
 namespace {
 
@@ -159,11 +174,12 @@ __device__ __forceinline__ void store_status(uint64_t* p, uint64_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Clears what the sweeps accumulate into: digit totals, tickets, abort word,
-// and the first pass's tile status words.
+// Clears what the sweeps accumulate into: digit totals, tickets, abort word
+// (to `preset`, normally 0), and the first pass's tile status words.
 __global__ __launch_bounds__(WG) void k_os_clear(uint32_t* __restrict__ hist,
                                                  uint32_t* __restrict__ tickets,
                                                  uint32_t* __restrict__ abort_word,
+                                                 uint32_t preset,
                                                  uint64_t* __restrict__ status0,
                                                  int64_t status_words) {
   const int64_t i0 = (int64_t)blockIdx.x * WG + threadIdx.x;
@@ -171,7 +187,7 @@ __global__ __launch_bounds__(WG) void k_os_clear(uint32_t* __restrict__ hist,
 #pragma unroll
     for (int p = 0; p < MAX_PASSES; ++p) hist[p * RADIX + threadIdx.x] = 0;
     if (threadIdx.x < MAX_PASSES) tickets[threadIdx.x] = 0;
-    if (threadIdx.x == 0) *abort_word = 0;
+    if (threadIdx.x == 0) *abort_word = preset;
   }
   for (int64_t i = i0; i < status_words; i += (int64_t)gridDim.x * WG) status0[i] = 0;
 }
@@ -594,15 +610,22 @@ __global__ __launch_bounds__(AWG) void k_remap_windows(const uint64_t* __restric
 }
 
 // Remap writes from (tag, slot) items ordered by the top bits of the tag.
+// If the bucketing sweep gave up (abort word set), every entry of LR is -1.
 __global__ __launch_bounds__(WG) void k_remap_apply(const uint64_t* __restrict__ items,
                                                     int64_t N, int32_t* __restrict__ LR,
-                                                    int64_t num_chunks) {
+                                                    int64_t num_chunks,
+                                                    const uint32_t* __restrict__ abort_word) {
   const int64_t chunk = xcd_tile(num_chunks);
   if (chunk < 0) return;
+  const bool failed = *abort_word != 0;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int64_t j = chunk * (4 * WG) + i * WG + threadIdx.x;
     if (j < N) {
+      if (failed) {
+        LR[j] = -1;
+        continue;
+      }
       const uint64_t x = items[j];
       const uint32_t t = (uint32_t)(x >> 32), s = (uint32_t)x;
       if ((int64_t)t < N) LR[t] = (t & 1u) ? (int32_t)s - 1 : (int32_t)s;
@@ -611,13 +634,16 @@ __global__ __launch_bounds__(WG) void k_remap_apply(const uint64_t* __restrict__
 }
 
 // Split / join of the packed sorted list (for the single-stage entry points).
+// If the sort gave up (abort word set), every position and tag is -1.
 __global__ __launch_bounds__(WG) void k_unpack(const uint64_t* __restrict__ E, int64_t N,
                                                int32_t* __restrict__ pos,
-                                               int32_t* __restrict__ tag) {
+                                               int32_t* __restrict__ tag,
+                                               const uint32_t* __restrict__ abort_word) {
   const int64_t j = (int64_t)blockIdx.x * WG + threadIdx.x;
   if (j < N) {
-    pos[j] = (int32_t)(E[j] >> 32);
-    tag[j] = (int32_t)(uint32_t)E[j];
+    const bool failed = *abort_word != 0;
+    pos[j] = failed ? -1 : (int32_t)(E[j] >> 32);
+    tag[j] = failed ? -1 : (int32_t)(uint32_t)E[j];
   }
 }
 __global__ __launch_bounds__(WG) void k_pack(const int32_t* __restrict__ pos,
@@ -701,7 +727,8 @@ hipError_t clear(const SortLayout& lay, const SortBufs& b, hipStream_t stream) {
   const int64_t status_words = lay.num_tiles * RADIX;
   const int64_t grid = status_words / (4 * WG) + 1;
   return launch(k_os_clear, dim3((unsigned)(grid < 1024 ? grid : 1024)), dim3(WG), 0, stream,
-                b.hist, b.tickets, b.abort_word, b.status[0], status_words);
+                b.hist, b.tickets, b.abort_word, g_abort_preset.load(), b.status[0],
+                status_words);
 }
 
 // A whole sort: clear, histograms of every pass, then the passes.  Passes
@@ -832,16 +859,26 @@ hipError_t launch_remap(const uint64_t* E, int64_t q, int32_t* LR, void* ws, siz
   }
   const int64_t chunks = (lay.N + 4 * WG - 1) / (4 * WG);
   RMQ_TRY(launch(k_remap_apply, dim3((unsigned)xcd_grid(chunks)), dim3(WG), 0, stream, sorted,
-                 lay.N, LR, chunks));
+                 lay.N, LR, chunks, static_cast<const uint32_t*>(b.abort_word)));
   return hipSuccess;
 }
 
+const uint32_t* sort_abort_word(const void* ws, int64_t q) {
+  return sort_pairs_abort_word(ws, 2 * q);
+}
+
+const uint32_t* sort_pairs_abort_word(const void* ws, int64_t N) {
+  if (!ws || N <= 0) return nullptr;
+  return reinterpret_cast<const uint32_t*>(static_cast<const char*>(ws) +
+                                           sort_layout_items(N).off_abort);
+}
+
 hipError_t launch_unpack_endpoints(const uint64_t* E, int64_t q, int32_t* pos, int32_t* tag,
-                                   hipStream_t stream) {
+                                   const uint32_t* abort_word, hipStream_t stream) {
   if (q <= 0) return hipSuccess;
   const int64_t N = 2 * q;
   RMQ_TRY(launch(k_unpack, dim3((unsigned)((N + WG - 1) / WG)), dim3(WG), 0, stream, E, N, pos,
-                 tag));
+                 tag, abort_word));
   return hipSuccess;
 }
 
