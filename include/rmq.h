@@ -75,7 +75,9 @@ typedef enum rmq_status {
     RMQ_ERR_OUT_OF_MEMORY = 2,    /* device allocation failed                */
     RMQ_ERR_DEVICE = 3,           /* a HIP runtime call failed               */
     RMQ_ERR_WORKSPACE_SMALL = 4,  /* caller workspace below the needed size  */
-    RMQ_ERR_MISALIGNED = 5        /* a device pointer is not 4/8-byte aligned */
+    RMQ_ERR_MISALIGNED = 5,       /* a device pointer is not 4/8-byte aligned */
+    RMQ_ERR_SCRATCH_LIMIT = 6     /* the call needs more scratch than the fixed
+                                     array of rmq_query_batch_noalloc holds   */
 } rmq_status;
 
 typedef enum rmq_path {
@@ -170,6 +172,26 @@ rmq_status rmq_query_batch(const int32_t *A, int64_t n, const int32_t *L, const 
 /* As rmq_query_batch, with options (opt may be NULL). */
 rmq_status rmq_query_batch_ex(const int32_t *A, int64_t n, const int32_t *L, const int32_t *R,
                               int64_t q, int32_t *out, void *stream, const rmq_options *opt);
+
+/* For callers that cannot allocate device memory (code under stream
+ * capture, serving loops that may not call the allocator): rmq_query_batch_ex
+ * with its scratch taken from a fixed device array of the library,
+ * RMQ_NOALLOC_SCRATCH_BYTES large, instead of the stream-ordered pool.  Each
+ * device holds its own array from the first call made with it current until
+ * the process ends; that first call looks up the array's address, later
+ * calls allocate nothing at all (no hipMalloc, hipMallocAsync or hipFree).
+ * opt->workspace must be NULL (and workspace_bytes 0); every other option is
+ * as for rmq_query_batch_ex.  A call whose rmq_workspace_bytes(n, q, opt)
+ * exceeds RMQ_NOALLOC_SCRATCH_BYTES returns RMQ_ERR_SCRATCH_LIMIT and enqueues
+ * nothing (the plain method fits at every n; the contracted one up to about
+ * q = 2e6).  All calls on one device share the one array and every call
+ * rewrites what it reads of it, so calls on ONE stream are safe in any order,
+ * while calls that overlap on one device (other streams, other host threads
+ * without ordering) race on the array and may return wrong answers. */
+#define RMQ_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+rmq_status rmq_query_batch_noalloc(const int32_t *A, int64_t n, const int32_t *L,
+                                   const int32_t *R, int64_t q, int32_t *out, void *stream,
+                                   const rmq_options *opt);
 
 /* Device scratch bytes rmq_query_batch_ex needs for (n, q, opt->block_size,
  * opt->path) after planning; 0 on invalid arguments.  A caller-provided

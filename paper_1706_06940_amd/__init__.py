@@ -25,7 +25,8 @@ LIB_PATH = os.path.join(HERE, "librmq.so")
 
 OK = 0
 STATUS = {0: "ok", 1: "invalid argument", 2: "out of device memory", 3: "HIP runtime error",
-          4: "workspace too small", 5: "misaligned device pointer"}
+          4: "workspace too small", 5: "misaligned device pointer",
+          6: "needs more than the fixed scratch array"}
 PATHS = {"auto": 0, "full": 1, "contracted": 2}
 MIN_BLOCK = 16
 MAX_BLOCK = 1 << 24
@@ -74,6 +75,7 @@ def lib() -> ctypes.CDLL:
         "rmq_version": ([], ctypes.c_char_p),
         "rmq_query_batch": ([v, i64, v, v, i64, v, v], i32),
         "rmq_query_batch_ex": ([v, i64, v, v, i64, v, v, opt], i32),
+        "rmq_query_batch_noalloc": ([v, i64, v, v, i64, v, v, opt], i32),
         "rmq_workspace_bytes": ([i64, i64, opt], sz),
         "rmq_plan": ([i64, i64, ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
         "rmq_plan_ex": ([i64, i64, ctypes.POINTER(i32), ctypes.POINTER(i32),
@@ -314,6 +316,31 @@ def query_batch(A: torch.Tensor, L: torch.Tensor, R: torch.Tensor, *, path="auto
                                   _dev_i32(out, "out") if q else None,
                                   _stream(A.device, stream), ctypes.byref(o))
     _check("rmq_query_batch_ex", st)
+    return out
+
+
+# Bytes of the fixed device scratch array behind query_batch_noalloc.
+NOALLOC_SCRATCH_BYTES = 128 << 20
+
+
+def query_batch_noalloc(A: torch.Tensor, L: torch.Tensor, R: torch.Tensor, out: torch.Tensor,
+                        *, path="auto", block_size: int = 0, sub_block_size: int = 0,
+                        arity_log2: int = 0, bad_count=None, stats=None, stream=None,
+                        records: bool = True) -> torch.Tensor:
+    """query_batch through rmq_query_batch_noalloc: the scratch is the
+    library's fixed device array, so the call allocates nothing (out must be
+    given).  Raises RMQError (status 6) when the batch needs more scratch
+    than NOALLOC_SCRATCH_BYTES.  Calls overlapping on one device race."""
+    n, q = A.numel(), L.numel()
+    if R.numel() != q or out.numel() != q:
+        raise ValueError("L, R and out differ in length")
+    o = _options(block_size, path, bad_count, stats, None, None, sub_block_size, arity_log2,
+                 records)
+    st = lib().rmq_query_batch_noalloc(_dev_i32(A, "A"), n, _dev_i32(L, "L") if q else None,
+                                       _dev_i32(R, "R") if q else None, q,
+                                       _dev_i32(out, "out") if q else None,
+                                       _stream(A.device, stream), ctypes.byref(o))
+    _check("rmq_query_batch_noalloc", st)
     return out
 
 

@@ -25,6 +25,7 @@ SOURCES = [
     "radix_sort.hip",
     "contract.hip",
     "capi.hip",
+    "noalloc.hip",
     "server.hip",
     "lca.hip",
 ]

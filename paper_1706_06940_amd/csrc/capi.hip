@@ -417,6 +417,7 @@ const char* rmq_status_string(rmq_status s) {
     case RMQ_ERR_DEVICE: return "HIP runtime error";
     case RMQ_ERR_WORKSPACE_SMALL: return "workspace too small";
     case RMQ_ERR_MISALIGNED: return "misaligned device pointer";
+    case RMQ_ERR_SCRATCH_LIMIT: return "needs more than the fixed scratch array";
   }
   return "unknown status";
 }

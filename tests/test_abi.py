@@ -32,7 +32,7 @@ def test_library_exports_every_declared_function():
 
 def test_status_strings():
     L = rmq.lib()
-    for code in range(6):
+    for code in range(7):
         assert L.rmq_status_string(code).decode() == rmq.STATUS[code]
 
 
