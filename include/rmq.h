@@ -260,6 +260,12 @@ rmq_status rmq_query_index(rmq_index idx, const int32_t *L, const int32_t *R, in
 rmq_status rmq_query_index_ex(rmq_index idx, const int32_t *L, const int32_t *R, int64_t q,
                               int32_t *out, void *stream, const rmq_options *opt);
 
+/* Device bytes rmq_build(A, n, opt, ...) allocates for the index (the
+ * table, the k1-block minima with two block levels, the query records when
+ * built; the same figure rmq_index_info reports afterwards), for admission
+ * by footprint before building.  0 on invalid arguments. */
+size_t rmq_build_bytes(int64_t n, const rmq_options *opt);
+
 /* Free an index.  The caller must make sure no enqueued work still uses it. */
 rmq_status rmq_index_free(rmq_index idx);
 
@@ -446,6 +452,12 @@ typedef struct rmq_server_config {
                                         over the slots (12 B a query + segment
                                         tables): pinned host memory, plus as
                                         much device memory with the copy flag */
+    size_t hbm_budget_bytes;         /* device memory (HBM) the server may hold:
+                                        the resident tables, the table
+                                        descriptors and, with the copy flag,
+                                        the slots' device buffers; 0 = no
+                                        limit.  rmq_server_add_array refuses a
+                                        table that would exceed it */
 } rmq_server_config;
 
 typedef struct rmq_server_stats {
@@ -453,6 +465,8 @@ typedef struct rmq_server_stats {
     int64_t slot_capacity;           /* queries one slot (one batch) can hold     */
     int64_t max_inflight;            /* most batches seen on the device at once   */
     size_t index_bytes;              /* device bytes of the resident tables       */
+    size_t hbm_bytes;                /* all device bytes the server holds and
+                                        admits against hbm_budget_bytes        */
 } rmq_server_stats;
 
 typedef struct rmq_request_info {
@@ -466,7 +480,11 @@ typedef struct rmq_server_s *rmq_server;
 rmq_status rmq_server_create(const rmq_server_config *cfg, rmq_server *out);
 
 /* Build and keep a resident index of device array A (k = block_size, 0 = auto);
- * synchronous.  A must stay alive and unmodified for the server's life. */
+ * synchronous.  A must stay alive and unmodified for the server's life.
+ * Admission by footprint: returns RMQ_ERR_OUT_OF_MEMORY, building nothing,
+ * when the table's rmq_build_bytes would take the server's device memory
+ * above cfg.hbm_budget_bytes, and RMQ_ERR_INVALID_ARG when max_tables are
+ * already resident (or being added by other threads). */
 rmq_status rmq_server_add_array(rmq_server s, const int32_t *A, int64_t n, int32_t block_size,
                                 int32_t *table_id);
 

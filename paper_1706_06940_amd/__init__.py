@@ -86,6 +86,7 @@ def lib() -> ctypes.CDLL:
         "rmq_query_index": ([v, v, v, i64, v, v], i32),
         "rmq_query_index_ex": ([v, v, v, i64, v, v, opt], i32),
         "rmq_index_free": ([v], i32),
+        "rmq_build_bytes": ([i64, opt], sz),
         "rmq_lca_build": ([v, i64, opt, v, ctypes.POINTER(v)], i32),
         "rmq_lca_query": ([v, v, v, i64, v, v, opt], i32),
         "rmq_lca_copy_tour": ([v, v, v, v, v], i32),
@@ -280,6 +281,14 @@ def workspace_bytes(n: int, q: int, path="auto", block_size: int = 0,
 
 def index_bytes(n: int, block_size: int) -> int:
     return int(lib().rmq_index_bytes(n, block_size))
+
+
+def build_bytes(n: int, block_size: int = 0, sub_block_size: int = 0, arity_log2: int = 0,
+                records: bool = True) -> int:
+    """Device bytes Index(A, ...) of n elements allocates (0: invalid)."""
+    o = _options(block_size, "full", sub_block_size=sub_block_size, arity_log2=arity_log2,
+                 records=records)
+    return int(lib().rmq_build_bytes(n, ctypes.byref(o)))
 
 
 def query_record_bytes(num_blocks: int) -> int:

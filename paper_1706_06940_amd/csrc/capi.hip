@@ -568,10 +568,21 @@ rmq_status rmq_query_batch(const int32_t* A, int64_t n, const int32_t* L, const 
 }
 
 // ---- resident index ----
-rmq_status rmq_build(const int32_t* A, int64_t n, const rmq_options* opt, void* stream,
-                     rmq_index* idx) {
-  if (!A || !idx || n < 1 || n > RMQ_MAX_N) return RMQ_ERR_INVALID_ARG;
-  if (!aligned_to(A, 4)) return RMQ_ERR_MISALIGNED;
+}  // extern "C"
+
+namespace {
+
+// Shape of a resident index for (n, opt): block sizes, levels, records and
+// the device bytes rmq_build allocates for it.
+struct IndexShape {
+  int kshift, k1shift, lg, levels;
+  int64_t nb, nb1;
+  bool rec;
+  size_t off_rec, bytes;
+};
+
+rmq_status index_shape(int64_t n, const rmq_options* opt, IndexShape* sh) {
+  if (n < 1 || n > RMQ_MAX_N) return RMQ_ERR_INVALID_ARG;
   int32_t k = opt ? opt->block_size : 0;
   const int32_t k1 = opt ? opt->sub_block_size : 0;
   const int lg = arity_lg(opt);
@@ -586,24 +597,51 @@ rmq_status rmq_build(const int32_t* A, int64_t n, const rmq_options* opt, void* 
     while (k < (1 << 20) && (double)(k * 2) <= tgt) k *= 2;
   }
   if (!is_pow2_block(k) || (k1 != 0 && k1 >= k)) return RMQ_ERR_INVALID_ARG;
+  sh->kshift = ilog2_i64(k);
+  sh->nb = num_blocks(n, k);
+  sh->lg = lg;
+  sh->levels = table_levels(sh->nb, lg);
+  sh->k1shift = k1 != 0 ? ilog2_i64(k1) : -1;
+  sh->nb1 = k1 != 0 ? num_blocks(n, k1) : 0;
+  sh->rec = records_built(sh->nb, sh->levels, lg, !(opt && opt->no_query_records), k1 != 0);
+  const size_t table_bytes = sizeof(uint64_t) * (size_t)sh->nb * (size_t)sh->levels;
+  const size_t sub_bytes = sizeof(uint64_t) * (size_t)sh->nb1;
+  // the records start on a 256-byte boundary, so that each is whole lines
+  sh->off_rec = align_up(table_bytes + sub_bytes);
+  sh->bytes = sh->rec ? sh->off_rec + records_bytes(sh->nb, sh->levels) : table_bytes + sub_bytes;
+  return RMQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t rmq_build_bytes(int64_t n, const rmq_options* opt) {
+  IndexShape sh;
+  return index_shape(n, opt, &sh) == RMQ_OK ? sh.bytes : 0;
+}
+
+rmq_status rmq_build(const int32_t* A, int64_t n, const rmq_options* opt, void* stream,
+                     rmq_index* idx) {
+  if (!A || !idx || n < 1 || n > RMQ_MAX_N) return RMQ_ERR_INVALID_ARG;
+  if (!aligned_to(A, 4)) return RMQ_ERR_MISALIGNED;
+  IndexShape sh;
+  const rmq_status bad = index_shape(n, opt, &sh);
+  if (bad != RMQ_OK) return bad;
   rmq_index_s* ix = static_cast<rmq_index_s*>(calloc(1, sizeof(rmq_index_s)));
   if (!ix) return RMQ_ERR_OUT_OF_MEMORY;
   hipGetDevice(&ix->device);
   ix->A = A;
   ix->n = n;
-  ix->kshift = ilog2_i64(k);
-  ix->nb = num_blocks(n, k);
-  ix->lg = lg;
-  ix->levels = table_levels(ix->nb, lg);
-  ix->k1shift = k1 != 0 ? ilog2_i64(k1) : -1;
-  ix->nb1 = k1 != 0 ? num_blocks(n, k1) : 0;
-  const bool with_rec =
-      records_built(ix->nb, ix->levels, lg, !(opt && opt->no_query_records), k1 != 0);
-  const size_t table_bytes = sizeof(uint64_t) * (size_t)ix->nb * (size_t)ix->levels;
-  const size_t sub_bytes = sizeof(uint64_t) * (size_t)ix->nb1;
-  // the records start on a 256-byte boundary, so that each is whole lines
-  const size_t off_rec = align_up(table_bytes + sub_bytes);
-  ix->bytes = with_rec ? off_rec + records_bytes(ix->nb, ix->levels) : table_bytes + sub_bytes;
+  ix->kshift = sh.kshift;
+  ix->nb = sh.nb;
+  ix->lg = sh.lg;
+  ix->levels = sh.levels;
+  ix->k1shift = sh.k1shift;
+  ix->nb1 = sh.nb1;
+  const bool with_rec = sh.rec;
+  const size_t off_rec = sh.off_rec;
+  ix->bytes = sh.bytes;
   void* mem = nullptr;
   hipError_t e = hipMalloc(&mem, ix->bytes);
   if (e != hipSuccess) {
@@ -611,7 +649,7 @@ rmq_status rmq_build(const int32_t* A, int64_t n, const rmq_options* opt, void* 
     return from_hip(e);
   }
   ix->st = static_cast<uint64_t*>(mem);
-  ix->sub = k1 != 0 ? ix->st + (size_t)ix->nb * (size_t)ix->levels : nullptr;
+  ix->sub = sh.k1shift >= 0 ? ix->st + (size_t)ix->nb * (size_t)ix->levels : nullptr;
   ix->rec = with_rec ? reinterpret_cast<uint64_t*>(static_cast<char*>(mem) + off_rec) : nullptr;
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (ix->sub) {

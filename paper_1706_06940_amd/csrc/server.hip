@@ -76,6 +76,11 @@ struct rmq_server_s {
   int64_t cap = 0;       // queries per slot
   int32_t max_reqs = 0;  // requests per batch
   size_t off_out = 0, off_prefix = 0, off_table = 0, slot_bytes = 0;
+  // device memory admitted against cfg.hbm_budget_bytes: the table
+  // descriptors and device slot buffers (fixed at creation), the resident
+  // tables, and tables whose build is under way (reserved, not yet added)
+  size_t hbm_fixed = 0, hbm_tables = 0, hbm_reserved = 0;
+  int32_t tables_reserved = 0;
   std::vector<rmq_index> tables;
   std::vector<ArrayDesc> h_tables;
   ArrayDesc* d_tables = nullptr;
@@ -292,6 +297,13 @@ rmq_status rmq_server_create(const rmq_server_config* cfg, rmq_server* out) {
   S->off_prefix = S->off_out + align_up(sizeof(int32_t) * (size_t)S->cap);
   S->off_table = S->off_prefix + align_up(sizeof(int64_t) * (size_t)(S->max_reqs + 1));
   S->slot_bytes = S->off_table + align_up(sizeof(int32_t) * (size_t)S->max_reqs);
+  S->hbm_fixed = sizeof(ArrayDesc) * (size_t)cfg->max_tables +
+                 ((cfg->flags & RMQ_SERVER_COPY_QUERIES) ? (size_t)cfg->num_streams * S->slot_bytes
+                                                         : 0);
+  if (cfg->hbm_budget_bytes && S->hbm_fixed > cfg->hbm_budget_bytes) {
+    delete S;
+    return RMQ_ERR_OUT_OF_MEMORY;
+  }
   S->slots.resize(cfg->num_streams);
   hipError_t e = hipMalloc(&S->d_tables, sizeof(ArrayDesc) * (size_t)cfg->max_tables);
   for (Slot& sl : S->slots) {
@@ -308,6 +320,7 @@ rmq_status rmq_server_create(const rmq_server_config* cfg, rmq_server* out) {
     return from_hip(e);
   }
   S->stats.slot_capacity = S->cap;
+  S->stats.hbm_bytes = S->hbm_fixed;
   S->dispatcher = std::thread(dispatcher_loop, S);
   S->completer = std::thread(completer_loop, S);
   *out = S;
@@ -317,20 +330,38 @@ rmq_status rmq_server_create(const rmq_server_config* cfg, rmq_server* out) {
 rmq_status rmq_server_add_array(rmq_server S, const int32_t* A, int64_t n, int32_t block_size,
                                 int32_t* table_id) {
   if (!S || !table_id) return RMQ_ERR_INVALID_ARG;
-  if ((int32_t)S->tables.size() >= S->cfg.max_tables) return RMQ_ERR_INVALID_ARG;
   rmq_options o{};
   o.block_size = block_size;
+  const size_t need = rmq_build_bytes(n, &o);
+  if (need == 0) return RMQ_ERR_INVALID_ARG;
+  {
+    // admission: a table slot and, under an HBM budget, the table's bytes
+    // are reserved before the build, so concurrent adds cannot overrun either
+    std::lock_guard<std::mutex> lk(S->mu);
+    if ((int32_t)S->tables.size() + S->tables_reserved >= S->cfg.max_tables)
+      return RMQ_ERR_INVALID_ARG;
+    const size_t held = S->hbm_fixed + S->hbm_tables + S->hbm_reserved;
+    if (S->cfg.hbm_budget_bytes && held + need > S->cfg.hbm_budget_bytes)
+      return RMQ_ERR_OUT_OF_MEMORY;
+    S->tables_reserved += 1;
+    S->hbm_reserved += need;
+  }
+  auto release = [&] {
+    S->tables_reserved -= 1;
+    S->hbm_reserved -= need;
+  };
   rmq_index ix = nullptr;
   rmq_status st = rmq_build(A, n, &o, nullptr, &ix);
-  if (st != RMQ_OK) return st;
-  hipError_t e = hipDeviceSynchronize();
-  if (e != hipSuccess) {
+  hipError_t e = st == RMQ_OK ? hipDeviceSynchronize() : hipSuccess;
+  if (st == RMQ_OK && e != hipSuccess) {
     rmq_index_free(ix);
-    return from_hip(e);
+    st = from_hip(e);
   }
+  std::lock_guard<std::mutex> lk(S->mu);
+  release();
+  if (st != RMQ_OK) return st;
   const ArrayDesc d{ix->A, ix->n, ix->kshift, ix->levels, ix->nb, ix->st,
                     nullptr, nullptr, 0, nullptr, ix->lg, ix->rec, ix->levels};
-  std::lock_guard<std::mutex> lk(S->mu);
   const int32_t id = (int32_t)S->tables.size();
   e = hipMemcpy(S->d_tables + id, &d, sizeof(ArrayDesc), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
@@ -339,7 +370,9 @@ rmq_status rmq_server_add_array(rmq_server S, const int32_t* A, int64_t n, int32
   }
   S->tables.push_back(ix);
   S->h_tables.push_back(d);
+  S->hbm_tables += ix->bytes;
   S->stats.index_bytes += ix->bytes;
+  S->stats.hbm_bytes = S->hbm_fixed + S->hbm_tables;
   *table_id = id;
   return RMQ_OK;
 }

@@ -208,3 +208,21 @@ def test_contracted_default_plan():
     k = rmq.default_block(n, 10 ** 7, "contracted")
     assert rmq.workspace_bytes(n, 10 ** 7, "contracted") == \
         rmq.workspace_bytes(n, 10 ** 7, "contracted", k)
+
+
+def test_build_bytes_is_the_index_footprint():
+    """rmq_build_bytes: the table (Table 2's 8 * nb * levels for one block
+    level), plus the k1-block minima with two levels (Section 3.3), plus the
+    query records when they are built."""
+    for n in (1, 1000, 10 ** 6 + 3, 10 ** 8):
+        for k in (256, 4096, 65536):
+            assert rmq.build_bytes(n, k, records=False) == rmq.index_bytes(n, k)
+            rec = rmq.query_record_bytes(-(-n // k))
+            with_rec = rmq.build_bytes(n, k)
+            if rec:
+                base = -(-rmq.index_bytes(n, k) // 256) * 256  # records start on 256 B
+                assert with_rec == base + rec
+            else:
+                assert with_rec == rmq.index_bytes(n, k)
+        assert rmq.build_bytes(n, 65536, 1024) == rmq.index_bytes(n, 65536) + 8 * (-(-n // 1024))
+    assert rmq.build_bytes(0) == 0 and rmq.build_bytes(10, 100) == 0
