@@ -37,6 +37,63 @@ METRIC = ("queries/s and HBM GB/s (% of peak) at n=1e8, q=1e3..1e7; "
 HBM_PEAK_GBS = 8000.0
 
 
+def table_levels(nb: int) -> int:
+    """Levels of the doubling block table over nb blocks (the library's
+    rule: floor(log2(nb - 2)) + 1, one level for nb <= 3)."""
+    return 1 if nb <= 3 else (nb - 2).bit_length()
+
+
+def algorithmic_bytes(path: str, n: int, q: int, k: int, k1: int, lo: int, hi: int):
+    """Bytes one whole job must move through HBM, by stage (Table 1's four
+    stages), from the per-unit figures of the method:
+      block minima: 4 B per element of A read + 8 B per block written;
+      block table: 8 B per (block, level) written (+ 8 B per k1-block read
+        and 8 B per block written when the blocks come from k1-blocks);
+      queries: 12 B each (L, R read, out written), + 8 B of LR each on A_Q;
+      endpoint sort: 2q 8-byte items read and written per pass of 8 key
+        bits, ceil(log2 n / 8) passes, + remap 12 B per endpoint;
+      contraction: 4 B per element between the outermost endpoints + 8 B per
+        endpoint + 8 B per A_Q entry written;
+      A_Q's table: 8 B per A_Q entry read, then as the block table above.
+    lo, hi: smallest left and largest right endpoint of the batch."""
+    def table(m, kk, kk1, per_elem):
+        nb = -(-m // kk)
+        b = 8 * nb * table_levels(nb)
+        if kk1:
+            nb1 = -(-m // kk1)
+            return per_elem * m + 8 * nb1, b + 8 * nb1 + 8 * nb
+        return per_elem * m + 8 * nb, b
+    if path == "full":
+        pass_b, st_b = table(n, k, k1, 4)
+        return {"sort": 0, "contract_or_blockmin": pass_b, "sparse_table": st_b,
+                "query": 12 * q}
+    m = 2 * q - 1
+    passes = -(-max(1, (n - 1).bit_length()) // 8)
+    sort_b = passes * 2 * (2 * q) * 8 + 12 * (2 * q)
+    contract_b = 4 * (hi - lo + 1) + 8 * (2 * q) + 8 * m
+    pass_b, st_b = table(m, k, k1, 8)
+    return {"sort": sort_b, "contract_or_blockmin": contract_b, "sparse_table": pass_b + st_b,
+            "query": 20 * q}
+
+
+def cpu_facts() -> dict:
+    """The host's CPU model and core counts, for the oracle's baseline."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = None
+    return {"cpu_model": model, "nproc": usable, "logical_cpus": os.cpu_count()}
+
+
 def parse_qs(s: str):
     return [int(float(x)) for x in s.split(",") if x]
 
@@ -206,10 +263,23 @@ def main() -> int:
             per = [timers[s][(p, j)].read() for s in range(args.steps)]
             tot = statistics.median(t for _, t in per)
             stages = [statistics.median(st[i] for st, _ in per) for i in range(4)]
+            L_h, R_h = batches_h[j]
+            ab = algorithmic_bytes(p, n, q, k_used[p][q], k1_used[p][q], int(L_h.min()),
+                                   int(R_h.max()))
+            job_b = sum(ab.values())
+            gbs = job_b / (tot / 1e3) / 1e9
+            stage_gbs = {name: (round(ab[name] / (v / 1e3) / 1e9, 1) if v > 0 and ab[name] else None)
+                         for name, v in zip(rmq.STAGE_NAMES, stages)}
             breakdown[f"{p}/q={q}"] = {
                 "ms": round(tot, 4), "queries_per_s": round(q / (tot / 1e3), 1),
+                "algorithmic_bytes": job_b, "GB_per_s": round(gbs, 1),
+                "frac": round(gbs / HBM_PEAK_GBS, 4),
                 "block_size": k_used[p][q], "sub_block_size": k1_used[p][q],
-                "stage_ms": {name: round(v, 4) for name, v in zip(rmq.STAGE_NAMES, stages)}}
+                "stage_ms": {name: round(v, 4) for name, v in zip(rmq.STAGE_NAMES, stages)},
+                "stage_algorithmic_bytes": ab,
+                "stage_GB_per_s": stage_gbs,
+                "stage_frac": {name: (round(v / HBM_PEAK_GBS, 4) if v else None)
+                               for name, v in stage_gbs.items()}}
             if p == "full":
                 # the pass over A takes the k1-block minima under two levels
                 kb = k1_used[p][q] or k_used[p][q]
@@ -315,6 +385,7 @@ def main() -> int:
                 break
         cpu = {"value": round(reps * sum(qs) / dt, 1), "unit": "queries/s",
                "cores": orc.num_threads(), "kind": "oracle",
+               "omp_threads": orc.num_threads(), **cpu_facts(),
                "sample": (f"oracle Sparse Table over 32-element blocks, build + answers for "
                           f"each batch of the sweep q={qs} on the same n={n} array, "
                           f"{reps} sweeps in {dt:.1f}s on the host")}
@@ -352,6 +423,10 @@ def main() -> int:
                    "block_size": {p: k_used[p] for p in paths},
                    "sub_block_size": {p: k1_used[p] for p in paths},
                    "parallelism": "single GPU"},
+        "value_cache_state": ("warm: A (400 MB) and the batches stay in HBM across steps with no "
+                              "flush between them; part of the data may still sit in the 256 MB "
+                              "MALL from the previous call. roofline.flushed is the block-minima "
+                              "pass after a 1 GiB write before every launch"),
         "roofline": roofline, "cpu_baseline": cpu, "breakdown": breakdown,
         "resident": resident, "small": small, "permutation": permutation,
         "skewed": skewed, "lca": lca, "lary": lary,

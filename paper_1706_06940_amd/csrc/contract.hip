@@ -1,4 +1,4 @@
-// Remap and contraction (Section 3.1 steps 1-2).
+// Contraction (Section 3.1 step 2).
 //
 // With the M = 2q endpoints sorted (E_0 <= ... <= E_{M-1}), A_Q[s] is the min
 // key over the CLOSED area A[E_s .. E_{s+1}], s = 0 .. M-2.  Split each area
@@ -7,21 +7,29 @@
 // where the half-open parts of consecutive areas tile [E_0, E_{M-1}) and are
 // empty for repeated endpoints (then A_Q[s] = key(E_s)).
 //
-// k_tiles (one thread per contraction tile of T = 1024 elements, plus one):
-//   * tile_start[t] = first slot whose endpoint is >= t * T (binary search
-//     over the sorted list);
-//   * A_Q[tile_start[t] - 1] = +inf: that area holds t * T and spans two or
-//     more tiles, so several waves finish it with atomicMin.
-// k_contract (one wave per tile, one streaming pass over A):
-//   * a tile without endpoints lies inside one area: wave min, atomicMin;
-//   * otherwise the tile's endpoints set head bits in LDS; lane l walks its
-//     16 consecutive elements with a running min that restarts at heads; a
-//     segmented min-scan over the lanes carries runs across lanes, and the
-//     1024 running minima go to LDS.  Then one lane per endpoint slot j in
-//     the tile reads off area j-1: the running min just before E_j (the
-//     half-open part, or its piece inside this tile) and the key at E_j.
-//     Areas inside the tile get plain coalesced stores; the area entering
-//     the tile and the one leaving it get atomicMin.
+// A is cut into tiles of T = 1024 elements.
+// k_tiles_search / k_tiles_scatter: tile_start[t] = first slot whose
+//   endpoint is >= t * T (by binary search per tile for sparse lists, by
+//   streaming the list for dense ones); and A_Q[j - 1] = +inf for every slot
+//   j that is the first in its tile -- that area reaches into the tile from
+//   an earlier one, so it may be finished by atomicMin from several waves.
+// k_contract (one streaming pass over A): each wave walks TPW consecutive
+//   tiles, the next tile's values and first endpoints in flight while it
+//   works on the current one, and carries the area that is still open at a
+//   tile's end into the next tile (no barrier: waves share nothing).
+//   * a tile without endpoints lies inside the open area: its min (32-bit
+//     compares, leftmost on ties) joins the carried value;
+//   * otherwise the tile is staged in LDS, its endpoints set head bits, and
+//     lane l takes elements 16l .. 16l+15 with a running min that restarts
+//     at heads; a segmented min-scan over the lanes' last runs gives each
+//     lane the min of the run coming in from the lanes before it.  Then one
+//     lane per endpoint slot j reads off area j-1: the key at E_j, the
+//     running min just before E_j, and the incoming run when E_{j-1} lies in
+//     an earlier lane.  Areas inside the tile are stored; the area entering
+//     the tile is stored too when it opened in an earlier tile of the same
+//     wave, and the run after the last endpoint becomes the open area.
+//   Only areas open at the wave's first tile or still open after its last
+//   tile take atomicMin (at most two per wave).
 #include "device.h"
 #include "kernels.h"
 
@@ -30,26 +38,29 @@ namespace rmq {
 namespace {
 
 constexpr int WG = 256;
+constexpr int WAVES = WG / 64;
 constexpr int TSHIFT = 10;
 constexpr int T = 1 << TSHIFT;  // contraction tile (elements of A per wave)
-constexpr int EPL = T / 64;     // elements per lane
+constexpr int EPL = T / 64;     // elements per lane in the lane-consecutive layout
 
-// Position of sorted endpoint j (P: the sorted endpoint positions).
-__device__ __forceinline__ int64_t epos(const int32_t* __restrict__ P, int64_t j) {
-  return (int64_t)P[j];
-}
-
-__global__ __launch_bounds__(WG) void k_tiles(const int32_t* __restrict__ E, int64_t M,
-                                              uint64_t* __restrict__ aq,
-                                              int32_t* __restrict__ tile_start,
-                                              int64_t num_tiles) {
+// Where each tile's endpoints start: tile_start[t] = first slot whose
+// endpoint is >= t * T (t = 0 .. num_tiles, the last entry M), and
+// A_Q[j - 1] = +inf for every slot j that is the first of its tile (that
+// area reaches into the tile from an earlier one).
+//
+// Sparse lists (fewer than 8 endpoints per tile on average): one thread per
+// tile, binary search over the sorted list (it stays in cache).
+__global__ __launch_bounds__(WG) void k_tiles_search(const int32_t* __restrict__ E, int64_t M,
+                                                     uint64_t* __restrict__ aq,
+                                                     int32_t* __restrict__ tile_start,
+                                                     int64_t num_tiles) {
   const int64_t t = (int64_t)blockIdx.x * WG + threadIdx.x;
   if (t > num_tiles) return;
   const int64_t target = t << TSHIFT;
   int64_t lo = 0, hi = M;  // first j in [lo, hi] with E_j >= target
   while (lo < hi) {
     const int64_t mid = lo + ((hi - lo) >> 1);
-    if (epos(E, mid) < target)
+    if ((int64_t)E[mid] < target)
       lo = mid + 1;
     else
       hi = mid;
@@ -58,198 +69,276 @@ __global__ __launch_bounds__(WG) void k_tiles(const int32_t* __restrict__ E, int
   if (lo >= 1 && lo <= M - 1) aq[lo - 1] = KEY_NONE;
 }
 
-// LDS staging of a tile's values: 16-element block b at word 20 b, so lane l
-// reading block l (16 bytes at a time) and lanes writing 4-element pieces of
-// the coalesced load stay spread over the banks.
+// Dense lists: four slots per thread, streaming the list.  Slot j is the
+// first of its tile p when slot j - 1 lies in an earlier tile pp; it then
+// starts every tile of (pp, p] (a short run when endpoints are dense), and
+// the last slot starts every tile after its own.
+__global__ __launch_bounds__(WG) void k_tiles_scatter(const int32_t* __restrict__ E, int64_t M,
+                                                      uint64_t* __restrict__ aq,
+                                                      int32_t* __restrict__ tile_start,
+                                                      int64_t num_tiles) {
+  const int64_t j0 = ((int64_t)blockIdx.x * WG + threadIdx.x) * 4;
+  if (j0 >= M) return;
+  int32_t e[5];  // E[j0 - 1 .. j0 + 3]
+  if (j0 + 4 <= M && (((uintptr_t)(E + j0)) & 15) == 0) {
+    const v4i32 v = *reinterpret_cast<const v4i32*>(E + j0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) e[i + 1] = v[i];
+  } else {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) e[i + 1] = j0 + i < M ? E[j0 + i] : 0;
+  }
+  e[0] = j0 > 0 ? E[j0 - 1] : 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t j = j0 + i;
+    if (j >= M) break;
+    const int64_t p = (int64_t)e[i + 1] >> TSHIFT;
+    const int64_t pp = j > 0 ? ((int64_t)e[i] >> TSHIFT) : -1;
+    if (p > pp) {
+      if (j >= 1) aq[j - 1] = KEY_NONE;
+      for (int64_t t = pp + 1; t <= p; ++t) tile_start[t] = (int32_t)j;
+    }
+    if (j == M - 1)
+      for (int64_t t = p + 1; t <= num_tiles; ++t) tile_start[t] = (int32_t)M;
+  }
+}
+
+// LDS staging of a tile's values: the 16 elements of lane l at words
+// 20 l .. 20 l + 15, so that lane l reading its 16 values (16 bytes at a
+// time) and lanes writing 4-element pieces of the coalesced load stay spread
+// over the banks.
 constexpr int BLOCK_WORDS = 20;
+constexpr int XWORDS = 64 * BLOCK_WORDS;
 __device__ __forceinline__ int stage_index(int e) { return (e >> 4) * BLOCK_WORDS + (e & 15); }
 
-constexpr int KREG = 8;  // endpoint slots per lane held in registers (512 per tile)
+// Completes this wave's LDS operations before the next ones (the waves of a
+// workgroup never share LDS here, so no workgroup barrier is needed).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
-__global__ __launch_bounds__(WG) void k_contract(const int32_t* __restrict__ A, int64_t n,
-                                                 const int32_t* __restrict__ E, int64_t M,
-                                                 const int32_t* __restrict__ tile_start,
-                                                 int64_t num_tiles, uint64_t* __restrict__ aq) {
-  __shared__ __align__(16) int32_t vals[WG / 64][(T / 16) * BLOCK_WORDS];
-  __shared__ uint32_t offs[WG / 64][EPL / 2][64];  // argmin offsets of the runs
-  __shared__ uint32_t heads[WG / 64][T / 32];       // endpoint bits
-  __shared__ uint64_t wmin[WG / 64];                // tiles without endpoints:
-  __shared__ int64_t warea[WG / 64];                //   their min and area
-  const int lane = lane_id(), wave = threadIdx.x >> 6;
-  const int64_t tile = (int64_t)blockIdx.x * (WG / 64) + wave;
-  const bool tile_ok = tile < num_tiles;
-  const int64_t tc = tile_ok ? tile : num_tiles - 1;  // loads below stay in bounds
-  const int64_t t0 = tile << TSHIFT;
-  const int64_t tile_n = n - t0 < T ? n - t0 : T;
+constexpr int TPW = 8;   // tiles per wave
+constexpr int KREG = 4;  // endpoint slots per lane of a tile held in registers (256 a tile)
 
-  // every load that does not depend on another is issued at once: the
-  // tile's endpoint range, then its 1024 elements (coalesced 16-byte loads:
-  // lane l holds elements 256c + 4l + (0..3))
-  int64_t jlo = tile_start[tc];
-  int64_t jend = tile_start[tc + 1];  // endpoints in [t0, t0+T)
-  v4i32 xv[4];
-  if (((uintptr_t)A & 15) == 0 && (tc << TSHIFT) + T <= n) {
+// The tile's values, coalesced: lane l holds elements 256 c + 4 l + (0..3);
+// INT32_MAX past the end of A (never part of an area).
+__device__ __forceinline__ void load_tile(const int32_t* __restrict__ A, int64_t n, int64_t t0,
+                                          bool aligned, int lane, v4i32 (&xv)[4]) {
+  if (aligned && t0 + T <= n) {
 #pragma unroll
-    for (int c = 0; c < 4; ++c) xv[c] = load_stream(A + (tc << TSHIFT) + c * 256 + lane * 4);
+    for (int c = 0; c < 4; ++c) xv[c] = load_stream(A + t0 + c * 256 + lane * 4);
   } else {
 #pragma unroll
     for (int c = 0; c < 4; ++c)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int64_t p = (tc << TSHIFT) + c * 256 + lane * 4 + i;
-        xv[c][i] = p < n ? A[p] : INT32_MAX;  // never part of an area
-      }
-  }
-  if (!tile_ok) jlo = jend = M;
-  jlo = jlo < 0 ? 0 : (jlo > M ? M : jlo);
-  jend = jend < jlo ? jlo : (jend > M ? M : jend);
-  // tiles wholly before E_0 (jend == 0) or after E_{M-1} (jlo == M) hold no area
-  const bool active = tile_ok && jend > 0 && jlo < M;
-  const bool marked = active && jend > jlo;  // the tile holds endpoints
-  const int64_t last_area = M - 2;           // valid areas are 0 .. M-2
-
-  // tile offsets of this lane's endpoint slots j = jlo + lane + 64k (first
-  // KREG rounds), and of the slot before each; loads clamped to the list
-  // (rounds with no slot are skipped as a whole: the test is uniform)
-  const int rounds = marked ? (int)((jend - jlo + 63) >> 6) : 0;
-  int32_t ep[KREG], epv[KREG];
-  if (marked) {
-    int32_t raw[KREG];
-#pragma unroll
-    for (int k = 0; k < KREG; ++k) {
-      const int64_t j = jlo + lane + 64 * k;
-      raw[k] = k < rounds ? E[j < M ? j : M - 1] : 0;
-    }
-    const int32_t raw_lo = E[jlo > 0 ? jlo - 1 : 0];
-#pragma unroll
-    for (int k = 0; k < KREG; ++k)
-      ep[k] = jlo + lane + 64 * k < jend ? (int32_t)(raw[k] - t0) : T;
-    const int32_t before_lo = jlo > 0 ? (int32_t)(raw_lo - t0) : -1;
-#pragma unroll
-    for (int k = 0; k < KREG; ++k) {
-      if (k >= rounds) break;
-      const int32_t up = (int32_t)dpp_u32_id<DPP_WAVE_SHR1>((uint32_t)ep[k], 0u);
-      const int32_t wrap = k == 0 ? before_lo : __builtin_amdgcn_readlane(ep[k - 1], 63);
-      epv[k] = lane == 0 ? wrap : up;
-    }
-  }
-
-  uint64_t m = KEY_NONE;
-  if (active && !marked) {
-    // no endpoint inside: the whole tile lies in area jlo - 1
-#pragma unroll
-    for (int c = 0; c < 4; ++c)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
         const int64_t p = t0 + c * 256 + lane * 4 + i;
-        if (p < n) m = umin64(m, make_key(xv[c][i], (uint32_t)p));
+        xv[c][i] = p < n ? A[p] : INT32_MAX;
       }
-    m = group_min_u64<64>(m);  // the wave's min lands in lane 63
   }
-  if (lane == 63) {
-    wmin[wave] = m;
-    warea[wave] = active && !marked ? jlo - 1 : -1;
-  }
+}
 
-  int32_t* xs = vals[wave];
-  if (marked) {
-    if (lane < T / 32) heads[wave][lane] = 0;
+// Tile offsets of the endpoint slots j = jlo + lane + 64 k (k < KREG) of
+// the tile starting at t0, T for slots past jend; only the rounds the tile
+// has are loaded.
+__device__ __forceinline__ void load_ends(const int32_t* __restrict__ E, uint32_t jlo,
+                                          uint32_t jend, uint32_t t0, int lane,
+                                          int32_t (&ep)[KREG]) {
+  const uint32_t rounds = (jend - jlo + 63u) >> 6;  // wave-uniform
+#pragma unroll
+  for (int k = 0; k < KREG; ++k) {
+    int32_t v = T;
+    if ((uint32_t)k < rounds) {
+      const uint32_t j = jlo + (uint32_t)lane + 64u * k;
+      if (j < jend) v = (int32_t)((uint32_t)E[j] - t0);
+    }
+    ep[k] = v;
+  }
+}
+
+__global__ __launch_bounds__(WG) void k_contract(const int32_t* __restrict__ A, int64_t n,
+                                                 const int32_t* __restrict__ E, int64_t M,
+                                                 const int32_t* __restrict__ tile_start,
+                                                 int64_t num_tiles, uint64_t* __restrict__ aq) {
+  __shared__ __align__(16) int32_t s_x[WAVES][XWORDS];  // the tile, lane-consecutive
+  __shared__ uint32_t s_off[WAVES][EPL / 2][64];         // run-min offsets, 2 x 16 bits
+  __shared__ uint32_t s_head[WAVES][T / 32];             // endpoint bits
+  __shared__ uint64_t s_carry[WAVES][64];                // run entering each lane
+  const int lane = lane_id();
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int64_t tb = ((int64_t)blockIdx.x * WAVES + wave) * TPW;
+  if (tb >= num_tiles) return;  // the whole wave
+  const int cnt = (int)(num_tiles - tb < TPW ? num_tiles - tb : TPW);
+  const bool aligned = ((uintptr_t)A & 15) == 0;
+  // slots and areas as 32-bit unsigned (M <= 2^31); area j - 1 of slot 0
+  // wraps above the last area, M - 2
+  const uint32_t Mu = (uint32_t)M;
+  const uint32_t last_area = Mu - 2u;
+  // tile_start of the wave's tiles and of the tile after them, one per lane
+  const uint32_t ts_lane = lane <= cnt ? (uint32_t)tile_start[tb + lane] : 0u;
+  auto ts = [&](int i) { return (uint32_t)__builtin_amdgcn_readlane((int)ts_lane, i); };
+  int32_t* xs = s_x[wave];
+
+  v4i32 xv[4];
+  int32_t en[KREG];
+  load_tile(A, n, tb << TSHIFT, aligned, lane, xv);
+  load_ends(E, ts(0), ts(1), (uint32_t)(tb << TSHIFT), lane, en);
+  // the area open at the current tile's start: its index, its min over the
+  // part already seen in this wave, and whether it opened before the wave
+  // (then other waves add to it too)
+  uint32_t open_area = ts(0) - 1u;
+  uint64_t acc = KEY_NONE;
+  bool shared = true;
+
+  for (int i = 0; i < cnt; ++i) {
+    const int64_t t0l = (tb + i) << TSHIFT;
+    const uint32_t t0 = (uint32_t)t0l;
+    const uint32_t jlo = ts(i), jend = ts(i + 1);  // endpoints in [t0, t0 + T)
+    const int tile_n = (int)(n - t0l < T ? n - t0l : T);
+    const bool more = i + 1 < cnt;
+    int32_t ep[KREG];
+#pragma unroll
+    for (int k = 0; k < KREG; ++k) ep[k] = en[k];
+
+    if (jlo == jend) {
+      // no endpoint inside: the tile lies in the open area (none before E_0
+      // or after E_{M-1})
+      if (jlo != 0 && jlo < Mu) {
+        int32_t cv = INT32_MAX;
+        int co = T;  // none yet
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const int a = c * 256 + lane * 4 + k;
+            const bool take = tile_n == T ? (xv[c][k] < cv || (c == 0 && k == 0))
+                                          : (a < tile_n && (xv[c][k] < cv || co == T));
+            cv = take ? xv[c][k] : cv;
+            co = take ? a : co;
+          }
+        const uint64_t m =
+            group_min_u64<64>(co < T ? make_key(cv, t0 + (uint32_t)co) : KEY_NONE);
+        acc = umin64(acc, (uint64_t)readlane64((int64_t)m, 63));
+      }
+      if (more) {  // the next tile's loads go out now
+        load_tile(A, n, t0l + T, aligned, lane, xv);
+        load_ends(E, jend, ts(i + 2), t0 + T, lane, en);
+      }
+      continue;
+    }
+
+    // ---- a tile with endpoints: staged in LDS, then the registers take
+    // the next tile's loads ----
 #pragma unroll
     for (int c = 0; c < 4; ++c)
       *reinterpret_cast<v4i32*>(xs + stage_index(c * 256 + lane * 4)) = xv[c];
-  }
-  __syncthreads();
-  if (active && !marked && lane == 63) {
-    // consecutive endpoint-free tiles of this workgroup in the same area
-    // make one atomic, issued by the first of them
-    const int64_t area = jlo - 1;
-    if ((wave == 0 || warea[wave - 1] != area) && area >= 0 && area <= last_area) {
-      uint64_t r = m;
-      for (int w = wave + 1; w < WG / 64 && warea[w] == area; ++w) r = umin64(r, wmin[w]);
-      atomicMin((unsigned long long*)&aq[area], (unsigned long long)r);
+    if (lane < T / 32) s_head[wave][lane] = 0;
+    if (more) {
+      load_tile(A, n, t0l + T, aligned, lane, xv);
+      load_ends(E, jend, ts(i + 2), t0 + T, lane, en);
     }
-  }
-  if (marked) {
+    // the slot before each of this lane's slots (-1: before the tile)
+    const uint32_t rounds = (jend - jlo + 63u) >> 6;
+    int32_t epv[KREG];
 #pragma unroll
     for (int k = 0; k < KREG; ++k) {
-      if (k >= rounds) break;
-      if (ep[k] >= 0 && ep[k] < T) atomicOr(&heads[wave][ep[k] >> 5], 1u << (ep[k] & 31));
+      const int32_t up = (int32_t)dpp_u32_id<DPP_WAVE_SHR1>((uint32_t)ep[k], 0u);
+      const int32_t wrap = k == 0 ? -1 : __builtin_amdgcn_readlane(ep[k - 1], 63);
+      epv[k] = lane == 0 ? wrap : up;
     }
-    for (int64_t j = jlo + 64 * KREG + lane; j < jend; j += 64) {
-      const int64_t e = epos(E, j) - t0;
-      if (e >= 0 && e < T) atomicOr(&heads[wave][e >> 5], 1u << (e & 31));
+    wave_lds_sync();  // head words cleared
+#pragma unroll
+    for (int k = 0; k < KREG; ++k)
+      if ((uint32_t)k < rounds && ep[k] < T)
+        atomicOr(&s_head[wave][ep[k] >> 5], 1u << (ep[k] & 31));
+    for (uint32_t j = jlo + 64u * KREG + (uint32_t)lane; j < jend; j += 64u) {
+      const int e = (int)((uint32_t)E[j] - t0);
+      atomicOr(&s_head[wave][e >> 5], 1u << (e & 31));
     }
-  }
-  __syncthreads();
-  if (marked) {
-    // ---- lane l: elements 16l .. 16l+15, a running min restarting at heads;
-    // values compared with < keep the leftmost of equal values ----
-    const uint32_t hb = (heads[wave][lane >> 1] >> ((lane & 1) * 16)) & 0xFFFFu;
-    int32_t rv[EPL];
-    uint32_t ro[EPL];
+    // the tile's last endpoint
+    const uint32_t lastj = jend - 1u - jlo;
+    int last;
+    if (lastj < 64u * KREG) {
+      const uint32_t k = lastj >> 6;
+      const int32_t v = k == 0 ? ep[0] : (k == 1 ? ep[1] : (k == 2 ? ep[2] : ep[3]));
+      last = __builtin_amdgcn_readlane(v, (int)(lastj & 63u));
+    } else {
+      last = (int)((uint32_t)E[jend - 1u] - t0);
+    }
+    wave_lds_sync();  // tile staged, heads set
+
+    // lane l: elements 16 l .. 16 l + 15, a running min restarting at heads
+    // (and at the lane's first element); < keeps the leftmost
+    const uint32_t hb = (s_head[wave][lane >> 1] >> ((lane & 1) * 16)) & 0xFFFFu;
+    int32_t cv = 0;
+    uint32_t co = 0;
 #pragma unroll
     for (int c = 0; c < EPL; c += 4) {
       const v4i32 v = *reinterpret_cast<const v4i32*>(xs + lane * BLOCK_WORDS + c);
+      uint32_t pair = 0;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) rv[c + i] = v[i];
+      for (int k = 0; k < 4; ++k) {
+        const int cc = c + k;
+        const bool take = cc == 0 || ((hb >> cc) & 1u) || v[k] < cv;
+        cv = take ? v[k] : cv;
+        co = take ? (uint32_t)(lane * EPL + cc) : co;
+        if (k & 1)
+          s_off[wave][cc >> 1][lane] = pair | (co << 16);
+        else
+          pair = co;
+      }
     }
-    int32_t cv = INT32_MAX;
-    uint32_t co = 0;
-#pragma unroll
-    for (int c = 0; c < EPL; ++c) {
-      const uint32_t o = (uint32_t)(lane * EPL + c);
-      const bool take = ((hb >> c) & 1u) || rv[c] < cv || c == 0;
-      cv = take ? rv[c] : cv;
-      co = take ? o : co;
-      rv[c] = cv;
-      ro[c] = co;
-    }
-    // ---- runs across lanes: segmented inclusive min-scan of lane totals
-    // (keys of value and offset, so equal values keep the leftmost) ----
-    const uint64_t v = seg_scan_min_u64(make_key(cv, co), hb != 0);
-    const uint64_t carry = dpp_u64_id<DPP_WAVE_SHR1>(v, KEY_NONE);  // lane 0: no run comes in
-    const int first = hb ? __builtin_ctz(hb) : EPL;
-    const int32_t kv = (int32_t)((uint32_t)(carry >> 32) ^ 0x80000000u);
-    const uint32_t ko = (uint32_t)carry;
-#pragma unroll
-    for (int c = 0; c < EPL; ++c)
-      if (lane > 0 && c < first && kv <= rv[c]) ro[c] = ko;  // the run coming in
-#pragma unroll
-    for (int c = 0; c < EPL; c += 2) offs[wave][c >> 1][lane] = ro[c] | (ro[c + 1] << 16);
-  }
-  __syncthreads();
-  if (!marked) return;  // whole wave leaves together; no barrier follows
+    // the run entering lane l: min over the lanes' last runs back to the
+    // nearest lane with a head (its run from that head on)
+    const uint64_t incl = seg_scan_min_u64(make_key(cv, t0 + co), hb != 0);
+    s_carry[wave][lane] = dpp_u64_id<DPP_WAVE_SHR1>(incl, KEY_NONE);  // lane 0: none comes in
+    wave_lds_sync();
 
-  // key of the run minimum ending at tile offset e
-  auto run_key = [&](int e) {
-    const uint32_t o = (offs[wave][(e & 15) >> 1][e >> 4] >> ((e & 1) * 16)) & 0xFFFFu;
-    return make_key(xs[stage_index((int)o)], (uint32_t)(t0 + o));
-  };
-  // area j - 1 from endpoint slot j at tile offset e (previous endpoint at eprev)
-  auto finish = [&](int64_t j, int64_t e, int64_t eprev) {
-    const int64_t area = j - 1;
-    if (area < 0 || area > last_area || e < 0 || e >= tile_n) return;  // e: never, if sorted
-    uint64_t val = make_key(xs[stage_index((int)e)], (uint32_t)(t0 + e));  // key(E_j)
-    if (eprev < e && e > 0) val = umin64(val, run_key((int)e - 1));
-    if (eprev < 0)
-      atomicMin((unsigned long long*)&aq[area], (unsigned long long)val);  // entering area
-    else
-      aq[area] = val;
-  };
+    // min over the half-open part of an area up to tile offset r
+    // (inclusive), whose last head is at tile offset h <= r (h = -1: none in
+    // this tile)
+    auto run_min = [&](int r, int h) {
+      const uint32_t o = (s_off[wave][(r & 15) >> 1][r >> 4] >> ((r & 1) * 16)) & 0xFFFFu;
+      uint64_t v = make_key(xs[stage_index((int)o)], t0 + o);
+      if ((h >> 4) < (r >> 4)) v = umin64(v, s_carry[wave][r >> 4]);  // h >> 4 = -1 for h = -1
+      return v;
+    };
+    // area j - 1, closed by slot j at tile offset e, the slot before at
+    // tile offset eprev (-1: before the tile; the area is the open one)
+    auto finish = [&](uint32_t j, int e, int eprev) {
+      const uint32_t area = j - 1u;
+      if (area > last_area) return;
+      uint64_t val = make_key(xs[stage_index(e)], t0 + (uint32_t)e);  // key(E_j)
+      if (eprev < e && e > 0) val = umin64(val, run_min(e - 1, eprev));
+      if (eprev < 0) {
+        val = umin64(val, acc);
+        if (shared)
+          atomicMin((unsigned long long*)&aq[area], (unsigned long long)val);
+        else
+          aq[area] = val;
+      } else {
+        aq[area] = val;
+      }
+    };
 #pragma unroll
-  for (int k = 0; k < KREG; ++k) {
-    if (k >= rounds) break;
-    const int64_t j = jlo + lane + 64 * k;
-    if (j < jend) finish(j, ep[k], epv[k]);
+    for (int k = 0; k < KREG; ++k) {
+      if ((uint32_t)k >= rounds) break;
+      const uint32_t j = jlo + (uint32_t)lane + 64u * k;
+      if (j < jend) finish(j, ep[k], epv[k]);
+    }
+    for (uint32_t j = jlo + 64u * KREG + (uint32_t)lane; j < jend; j += 64u)
+      finish(j, (int)((uint32_t)E[j] - t0), (int)((uint32_t)E[j - 1u] - t0));
+    // the area after the last endpoint stays open
+    acc = run_min(tile_n - 1, last);
+    open_area = jend - 1u;
+    shared = false;
   }
-  for (int64_t j = jlo + 64 * KREG + lane; j < jend; j += 64)
-    finish(j, epos(E, j) - t0, epos(E, j - 1) - t0);
-  // the area leaving the tile: from the last head to the tile's end
-  if (lane == 0) {
-    const int64_t area = jend - 1;
-    if (area <= last_area)
-      atomicMin((unsigned long long*)&aq[area], (unsigned long long)run_key((int)tile_n - 1));
-  }
+  // the area still open after the wave's last tile continues in later waves
+  if (lane == 0 && open_area <= last_area && acc != KEY_NONE)
+    atomicMin((unsigned long long*)&aq[open_area], (unsigned long long)acc);
 }
 
 }  // namespace
@@ -259,9 +348,14 @@ hipError_t launch_contract(const int32_t* A, int64_t n, const int32_t* E, int64_
   if (q <= 0) return hipSuccess;
   const int64_t M = 2 * q;
   const int64_t num_tiles = (n + T - 1) / T;
-  RMQ_TRY(launch(k_tiles, dim3((unsigned)((num_tiles + 1 + WG - 1) / WG)), dim3(WG), 0, stream, E,
-                 M, aq, tile_start, num_tiles));
-  const int64_t grid = (num_tiles + (WG / 64) - 1) / (WG / 64);
+  if (M >= 8 * num_tiles)
+    RMQ_TRY(launch(k_tiles_scatter, dim3((unsigned)((M + 4 * WG - 1) / (4 * WG))), dim3(WG), 0,
+                   stream, E, M, aq, tile_start, num_tiles));
+  else
+    RMQ_TRY(launch(k_tiles_search, dim3((unsigned)((num_tiles + 1 + WG - 1) / WG)), dim3(WG), 0,
+                   stream, E, M, aq, tile_start, num_tiles));
+  const int64_t waves = (num_tiles + TPW - 1) / TPW;
+  const int64_t grid = (waves + WAVES - 1) / WAVES;
   RMQ_TRY(launch(k_contract, dim3((unsigned)grid), dim3(WG), 0, stream, A, n, E, M, tile_start,
                  num_tiles, aq));
   return hipSuccess;
