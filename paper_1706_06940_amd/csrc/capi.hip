@@ -378,7 +378,10 @@ rmq_status run_contracted(const int32_t* A, int64_t n, const int32_t* L, const i
   stage_end(t, 0, s);
   stage_begin(t, 1);
   // the sort left the positions only (int32) in the first half of E
-  e = launch_contract(A, n, reinterpret_cast<const int32_t*>(E), q, aq, tiles, s);
+  // (nothing is contracted after a sort that gave up; the queries then
+  // report every query as invalid)
+  e = launch_contract(A, n, reinterpret_cast<const int32_t*>(E), q, aq, tiles, s,
+                      sort_abort_word(ws + c.off_sort, q));
   if (e != hipSuccess) return from_hip(e);
   stage_end(t, 1, s);
   stage_begin(t, 2);
@@ -792,7 +795,8 @@ rmq_status rmq_contract(const int32_t* A, int64_t n, const int32_t* pos, const i
   e = launch_pack_endpoints(pos, tag, q, E, s);
   if (e == hipSuccess) e = launch_remap(E, q, LR, w, sort_b, s);
   if (e == hipSuccess)
-    e = launch_contract(A, n, pos, q, aq, reinterpret_cast<int32_t*>(w + sort_b + list_b), s);
+    e = launch_contract(A, n, pos, q, aq, reinterpret_cast<int32_t*>(w + sort_b + list_b), s,
+                        nullptr);
   hipFreeAsync(scratch, s);
   return from_hip(e);
 }

@@ -53,9 +53,10 @@ constexpr int EPL = T / 64;     // elements per lane in the lane-consecutive lay
 __global__ __launch_bounds__(WG) void k_tiles_search(const int32_t* __restrict__ E, int64_t M,
                                                      uint64_t* __restrict__ aq,
                                                      int32_t* __restrict__ tile_start,
-                                                     int64_t num_tiles) {
+                                                     int64_t num_tiles,
+                                                     const uint32_t* __restrict__ fail) {
   const int64_t t = (int64_t)blockIdx.x * WG + threadIdx.x;
-  if (t > num_tiles) return;
+  if (t > num_tiles || (fail && *fail)) return;
   const int64_t target = t << TSHIFT;
   int64_t lo = 0, hi = M;  // first j in [lo, hi] with E_j >= target
   while (lo < hi) {
@@ -72,13 +73,20 @@ __global__ __launch_bounds__(WG) void k_tiles_search(const int32_t* __restrict__
 // Dense lists: four slots per thread, streaming the list.  Slot j is the
 // first of its tile p when slot j - 1 lies in an earlier tile pp; it then
 // starts every tile of (pp, p] (a short run when endpoints are dense), and
-// the last slot starts every tile after its own.
+// the last slot starts every tile after its own.  Tile indices are clamped
+// to the tiles of A, so a list that is not sorted positions of A (a caller's
+// buffer) cannot send a write out of bounds.
+__device__ __forceinline__ int64_t tile_of(int32_t e, int64_t num_tiles) {
+  const int64_t p = (int64_t)(uint32_t)e >> TSHIFT;
+  return p < num_tiles ? p : num_tiles - 1;
+}
 __global__ __launch_bounds__(WG) void k_tiles_scatter(const int32_t* __restrict__ E, int64_t M,
                                                       uint64_t* __restrict__ aq,
                                                       int32_t* __restrict__ tile_start,
-                                                      int64_t num_tiles) {
+                                                      int64_t num_tiles,
+                                                      const uint32_t* __restrict__ fail) {
   const int64_t j0 = ((int64_t)blockIdx.x * WG + threadIdx.x) * 4;
-  if (j0 >= M) return;
+  if (j0 >= M || (fail && *fail)) return;
   int32_t e[5];  // E[j0 - 1 .. j0 + 3]
   if (j0 + 4 <= M && (((uintptr_t)(E + j0)) & 15) == 0) {
     const v4i32 v = *reinterpret_cast<const v4i32*>(E + j0);
@@ -93,8 +101,8 @@ __global__ __launch_bounds__(WG) void k_tiles_scatter(const int32_t* __restrict_
   for (int i = 0; i < 4; ++i) {
     const int64_t j = j0 + i;
     if (j >= M) break;
-    const int64_t p = (int64_t)e[i + 1] >> TSHIFT;
-    const int64_t pp = j > 0 ? ((int64_t)e[i] >> TSHIFT) : -1;
+    const int64_t p = tile_of(e[i + 1], num_tiles);
+    const int64_t pp = j > 0 ? tile_of(e[i], num_tiles) : -1;
     if (p > pp) {
       if (j >= 1) aq[j - 1] = KEY_NONE;
       for (int64_t t = pp + 1; t <= p; ++t) tile_start[t] = (int32_t)j;
@@ -162,7 +170,8 @@ __device__ __forceinline__ void load_ends(const int32_t* __restrict__ E, uint32_
 __global__ __launch_bounds__(WG) void k_contract(const int32_t* __restrict__ A, int64_t n,
                                                  const int32_t* __restrict__ E, int64_t M,
                                                  const int32_t* __restrict__ tile_start,
-                                                 int64_t num_tiles, uint64_t* __restrict__ aq) {
+                                                 int64_t num_tiles, uint64_t* __restrict__ aq,
+                                                 const uint32_t* __restrict__ fail) {
   __shared__ __align__(16) int32_t s_x[WAVES][XWORDS];  // the tile, lane-consecutive
   __shared__ uint32_t s_off[WAVES][EPL / 2][64];         // run-min offsets, 2 x 16 bits
   __shared__ uint32_t s_head[WAVES][T / 32];             // endpoint bits
@@ -170,7 +179,7 @@ __global__ __launch_bounds__(WG) void k_contract(const int32_t* __restrict__ A, 
   const int lane = lane_id();
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int64_t tb = ((int64_t)blockIdx.x * WAVES + wave) * TPW;
-  if (tb >= num_tiles) return;  // the whole wave
+  if (tb >= num_tiles || (fail && *fail)) return;  // the whole wave
   const int cnt = (int)(num_tiles - tb < TPW ? num_tiles - tb : TPW);
   const bool aligned = ((uintptr_t)A & 15) == 0;
   // slots and areas as 32-bit unsigned (M <= 2^31); area j - 1 of slot 0
@@ -178,7 +187,14 @@ __global__ __launch_bounds__(WG) void k_contract(const int32_t* __restrict__ A, 
   const uint32_t Mu = (uint32_t)M;
   const uint32_t last_area = Mu - 2u;
   // tile_start of the wave's tiles and of the tile after them, one per lane
-  const uint32_t ts_lane = lane <= cnt ? (uint32_t)tile_start[tb + lane] : 0u;
+  // (made non-decreasing and at most M, whatever the table holds)
+  uint32_t ts_lane = lane <= cnt ? (uint32_t)tile_start[tb + lane] : 0u;
+  ts_lane = ts_lane < Mu ? ts_lane : Mu;
+#pragma unroll
+  for (int dlt = 1; dlt < 16; dlt <<= 1) {  // running max over lanes 0 .. cnt (<= 8)
+    const uint32_t up = (uint32_t)__shfl_up((int)ts_lane, dlt);
+    if (lane >= dlt && up > ts_lane) ts_lane = up;
+  }
   auto ts = [&](int i) { return (uint32_t)__builtin_amdgcn_readlane((int)ts_lane, i); };
   int32_t* xs = s_x[wave];
 
@@ -252,11 +268,11 @@ __global__ __launch_bounds__(WG) void k_contract(const int32_t* __restrict__ A, 
     wave_lds_sync();  // head words cleared
 #pragma unroll
     for (int k = 0; k < KREG; ++k)
-      if ((uint32_t)k < rounds && ep[k] < T)
+      if ((uint32_t)k < rounds && (uint32_t)ep[k] < (uint32_t)T)
         atomicOr(&s_head[wave][ep[k] >> 5], 1u << (ep[k] & 31));
     for (uint32_t j = jlo + 64u * KREG + (uint32_t)lane; j < jend; j += 64u) {
-      const int e = (int)((uint32_t)E[j] - t0);
-      atomicOr(&s_head[wave][e >> 5], 1u << (e & 31));
+      const uint32_t e = (uint32_t)E[j] - t0;
+      if (e < (uint32_t)T) atomicOr(&s_head[wave][e >> 5], 1u << (e & 31));
     }
     // the tile's last endpoint
     const uint32_t lastj = jend - 1u - jlo;
@@ -310,7 +326,7 @@ __global__ __launch_bounds__(WG) void k_contract(const int32_t* __restrict__ A, 
     // tile offset eprev (-1: before the tile; the area is the open one)
     auto finish = [&](uint32_t j, int e, int eprev) {
       const uint32_t area = j - 1u;
-      if (area > last_area) return;
+      if (area > last_area || (uint32_t)e >= (uint32_t)tile_n) return;  // e: never, if sorted
       uint64_t val = make_key(xs[stage_index(e)], t0 + (uint32_t)e);  // key(E_j)
       if (eprev < e && e > 0) val = umin64(val, run_min(e - 1, eprev));
       if (eprev < 0) {
@@ -344,20 +360,21 @@ __global__ __launch_bounds__(WG) void k_contract(const int32_t* __restrict__ A, 
 }  // namespace
 
 hipError_t launch_contract(const int32_t* A, int64_t n, const int32_t* E, int64_t q,
-                           uint64_t* aq, int32_t* tile_start, hipStream_t stream) {
+                           uint64_t* aq, int32_t* tile_start, hipStream_t stream,
+                           const uint32_t* fail) {
   if (q <= 0) return hipSuccess;
   const int64_t M = 2 * q;
   const int64_t num_tiles = (n + T - 1) / T;
   if (M >= 8 * num_tiles)
     RMQ_TRY(launch(k_tiles_scatter, dim3((unsigned)((M + 4 * WG - 1) / (4 * WG))), dim3(WG), 0,
-                   stream, E, M, aq, tile_start, num_tiles));
+                   stream, E, M, aq, tile_start, num_tiles, fail));
   else
     RMQ_TRY(launch(k_tiles_search, dim3((unsigned)((num_tiles + 1 + WG - 1) / WG)), dim3(WG), 0,
-                   stream, E, M, aq, tile_start, num_tiles));
+                   stream, E, M, aq, tile_start, num_tiles, fail));
   const int64_t waves = (num_tiles + TPW - 1) / TPW;
   const int64_t grid = (waves + WAVES - 1) / WAVES;
   RMQ_TRY(launch(k_contract, dim3((unsigned)grid), dim3(WG), 0, stream, A, n, E, M, tile_start,
-                 num_tiles, aq));
+                 num_tiles, aq, fail));
   return hipSuccess;
 }
 

@@ -169,10 +169,14 @@ hipError_t launch_pack_endpoints(const int32_t* pos, const int32_t* tag, int64_t
                                  hipStream_t stream);
 // Contraction: A_Q over the closed areas between consecutive endpoints,
 // given the 2q sorted endpoint positions E (int32).
-// tile_start: scratch of contract_tile_start_bytes(n).
+// tile_start: scratch of contract_tile_start_bytes(n).  fail (may be null):
+// the endpoint sort's abort word; when it is set nothing is done.  A list
+// that is not sorted positions of A gives meaningless A_Q but never an
+// access out of bounds.
 size_t contract_tile_start_bytes(int64_t n);
 hipError_t launch_contract(const int32_t* A, int64_t n, const int32_t* E, int64_t q,
-                           uint64_t* aq, int32_t* tile_start, hipStream_t stream);
+                           uint64_t* aq, int32_t* tile_start, hipStream_t stream,
+                           const uint32_t* fail);
 // fail: the endpoint sort's abort word; when it is set every query is
 // answered -1 and counted in bad_count.
 hipError_t launch_query_contracted(const uint64_t* aq, int64_t m, int64_t n, int kshift,

@@ -10,9 +10,9 @@
 //   k_os_clear  -- clears digit totals, tickets and the first status words;
 //   k_os_hist   -- one read of the input: digit totals of every pass at once
 //                  (per workgroup in LDS, then global atomics);
-//   k_os_pass   -- per pass, one workgroup per tile of 1024, 2048 or 4096
-//                  items (by list length), tiles taken in
-//                  order from an atomic ticket.  The tile ranks its items
+//   k_os_pass   -- per pass, one workgroup (one thread per digit value) per
+//                  tile of 1024, 2048 or 8192 items (by list length), tiles
+//                  taken in order from an atomic ticket.  The tile ranks its items
 //                  stably (one wave ballot per digit bit gives the lanes that
 //                  share a digit), publishes its per-digit counts at once,
 //                  stages the tile in LDS in digit order, and meanwhile finds
@@ -30,9 +30,17 @@
 //                  kernel answers -1 for every query and counts each as
 //                  invalid; the stand-alone stages write -1; the LCA build
 //                  returns an error).
-// Items are 8 bytes, (position << 32) | tag, so each digit run a tile writes
-// is whole cache lines; the key bits are split into the fewest passes of at
-// most 8 bits with equal widths (27 bits -> 7, 7, 7, 6).
+// Items are 8 bytes, (position << 32) | tag; the key bits are split into the
+// fewest passes of at most 9 bits with equal widths (27 bits -> 9, 9, 9).
+// The passes issue more instructions than they move bytes (the ranking takes
+// one ballot per key bit of every item, whatever the split), so fewer, wider
+// passes over large tiles cost less: measured at n = 1e8, the sort of 2q
+// endpoints took 0.64 / 0.11 / 0.044 ms at q = 1e7 / 1e6 / 1e5 with 9-bit
+// digits and 8192-item tiles against 0.65 / 0.135 / 0.054 ms with four
+// passes of 7 bits over 4096-item tiles.  Staging the tile in LDS before the
+// global writes pays: storing each item straight from registers at its
+// digit run (runs written by many store instructions) was slower at
+// q = 1e7 (0.71 - 0.77 ms).
 // The first pass reads L and R directly (invalid queries sort as position
 // 0; the query kernel re-checks them), the last writes the output list E.
 //
@@ -63,15 +71,25 @@ void set_sort_abort_preset(bool on) { g_abort_preset.store(on ? 1u : 0u); }
 
 namespace {
 
-constexpr int WG = 256;
+// Digit width and the tile of long lists (build-time choices).
+#ifndef RMQ_SORT_RADIX_BITS
+#define RMQ_SORT_RADIX_BITS 9
+#endif
+#ifndef RMQ_SORT_BIG_TILE
+#define RMQ_SORT_BIG_TILE 8192
+#endif
+constexpr int RADIX_BITS = RMQ_SORT_RADIX_BITS;
+constexpr int RADIX = 1 << RADIX_BITS;
+constexpr int WG = RADIX;  // one thread per digit value
+constexpr int BIG_TILE = RMQ_SORT_BIG_TILE;
+constexpr int BIG_ROUNDS = BIG_TILE / WG;
+constexpr int R1K = 1024 / WG > 0 ? 1024 / WG : 1;
+constexpr int R2K = 2048 / WG > 0 ? 2048 / WG : 1;
 // Items per thread of a tile (a tile is WG * ROUNDS items), chosen by the
 // list length N: small lists take small tiles so that more workgroups share
-// them, long ones large tiles (fewer look-back steps, longer digit runs).
-// Measured sort times of the 2q endpoints at n = 1e8: 4 items per thread is
-// fastest up to q = 3e4, 8 at q = 1e5, 16 from q = 3e5.
-int rounds_for(int64_t N) { return N < 100000 ? 4 : (N < 400000 ? 8 : 16); }
-constexpr int RADIX_BITS = 8;
-constexpr int RADIX = 1 << RADIX_BITS;
+// them, long ones large tiles (fewer look-back steps, longer digit runs):
+// 1024-item tiles below 10^5 items, 2048 below 4 * 10^5, BIG_TILE above.
+int rounds_for(int64_t N) { return N < 100000 ? R1K : (N < 400000 ? R2K : BIG_ROUNDS); }
 constexpr int NXCD = 8;
 
 // Items are 8 bytes: (key << 32) | value, so a digit run of a tile is one
@@ -149,7 +167,7 @@ struct Digits {  // the digit split of one sort: pass p covers key bits
 };
 
 // Balanced split of nbits key bits starting at bit `base` into the fewest
-// passes of at most 8 bits (27 bits -> 7, 7, 7, 6): every pass then has
+// passes of at most 9 bits (27 bits -> 9, 9, 9; 20 bits -> 7, 7, 6): every pass then has
 // digits of similar spread, which keeps LDS counters uncontended and digit
 // runs long.
 Digits split_digits(int base, int nbits) {
@@ -202,10 +220,11 @@ __global__ __launch_bounds__(WG) void k_os_hist(const uint64_t* __restrict__ ite
                                                 int64_t n, Digits dg, int per_group,
                                                 uint32_t* __restrict__ hist) {
   constexpr int TILE = WG * ROUNDS;
-  __shared__ uint32_t h[WG / 64][MAX_PASSES][RADIX];  // one set of counters per wave
-  const int lane = lane_id(), wave = threadIdx.x >> 6;
+  constexpr int HSETS = 4;  // counter sets, one per pair of waves
+  __shared__ uint32_t h[HSETS][MAX_PASSES][RADIX];
+  const int lane = lane_id(), wave = threadIdx.x >> 6, hs = wave & (HSETS - 1);
 #pragma unroll
-  for (int w = 0; w < WG / 64; ++w)
+  for (int w = 0; w < HSETS; ++w)
 #pragma unroll
     for (int p = 0; p < MAX_PASSES; ++p) h[w][p][threadIdx.x] = 0;
   __syncthreads();
@@ -223,19 +242,19 @@ __global__ __launch_bounds__(WG) void k_os_hist(const uint64_t* __restrict__ ite
     for (int rd = 0; rd < ROUNDS; ++rd) {
       if (item_index<ROUNDS>(tile0, wave, rd, lane) < N)
         for (int p = 0; p < dg.passes; ++p)
-          atomicAdd(&h[wave][p][digit_of(it[rd], dg.shift[p], (1u << dg.bits[p]) - 1u)], 1u);
+          atomicAdd(&h[hs][p][digit_of(it[rd], dg.shift[p], (1u << dg.bits[p]) - 1u)], 1u);
     }
   }
   __syncthreads();
   for (int p = 0; p < dg.passes; ++p) {
     uint32_t c = 0;
 #pragma unroll
-    for (int w = 0; w < WG / 64; ++w) c += h[w][p][threadIdx.x];
+    for (int w = 0; w < HSETS; ++w) c += h[w][p][threadIdx.x];
     if (c) atomicAdd(&hist[p * RADIX + threadIdx.x], c);
   }
 }
 
-// Exclusive scan of 256 values held one per thread; returns the total.
+// Exclusive scan of WG values held one per thread; returns the total.
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* tmp,
                                                          uint32_t& excl) {
   const int lane = lane_id(), wave = threadIdx.x >> 6;
@@ -253,6 +272,63 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* t
   return total;
 }
 
+// Decoupled look-back for digit d of `tile`: the number of digit-d items in
+// all earlier tiles.  Reads LOOKBACK predecessors' words at once, newest
+// first, and takes values up to the first inclusive one, or stops at an
+// unpublished one and reads again.  A tile only waits on tiles that took
+// their ticket earlier; the wait is bounded, and an exceeded bound (or an
+// abort word already set) ends it with a partial count and sets the abort
+// word, which ends every other wait at once.
+__device__ __forceinline__ uint64_t look_back(const uint64_t* status, int64_t tile, int d,
+                                              uint32_t* abort_word) {
+  uint64_t before = 0;
+  int64_t j = tile - 1;
+  uint32_t spins = 0;
+  for (;;) {
+    uint64_t w[LOOKBACK];
+#pragma unroll
+    for (int i = 0; i < LOOKBACK; ++i)
+      w[i] = j - i >= 0 ? load_status(status + (j - i) * RADIX + d) : 0;
+    bool done = false;
+    int used = 0;
+#pragma unroll
+    for (int i = 0; i < LOOKBACK; ++i) {
+      if (done || used != i || (w[i] & ~ST_VAL) == 0) continue;
+      before += w[i] & ST_VAL;
+      done = (w[i] & ST_INC) != 0;
+      used = i + 1;
+    }
+    if (done) break;
+    j -= used;
+    if (used == 0) {  // the nearest unread predecessor has not published yet
+      if (++spins > SPIN_LIMIT ||
+          __hip_atomic_load(abort_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        __hip_atomic_store(abort_word, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+  }
+  return before;
+}
+
+// Stable rank of each lane's digit among the lanes of the wave holding the
+// same digit: the lanes whose every one of the BITS digit bits equals this
+// lane's are those outside the OR over the bits of (ballot of the bit) XOR
+// (own bit spread over the word).  Returns the mask of those lanes.
+template <int BITS>
+__device__ __forceinline__ uint64_t same_digit_lanes(uint32_t d, uint64_t valid_mask) {
+  uint32_t xlo = 0, xhi = 0;
+#pragma unroll
+  for (int b = 0; b < BITS; ++b) {
+    const uint32_t x = (uint32_t)((int32_t)(d << (31 - b)) >> 31);  // bit b, spread
+    const uint64_t m = ballot(x != 0);
+    xlo |= (uint32_t)m ^ x;
+    xhi |= (uint32_t)(m >> 32) ^ x;
+  }
+  return valid_mask & ~(((uint64_t)xhi << 32) | xlo);
+}
+
 // The remap through LR windows (the last pass of long endpoint sorts): tags
 // fall into windows of 2^WIN_SHIFT consecutive tags (128 KiB of LR); the
 // last pass writes each tile's (tag << 32 | slot) pairs grouped by window
@@ -267,7 +343,7 @@ constexpr int64_t WIN_MIN_N = 1 << 22;  // shorter lists keep the scattered stor
 
 // One pass over a tile (see the top of this file).  WINDOWS: the last pass
 // of a long endpoint sort, which also writes the tile's remap pairs.
-template <int MODE, int ROUNDS, bool WINDOWS>
+template <int MODE, int ROUNDS, bool WINDOWS, int BITS>
 __device__ __forceinline__ void os_pass(const uint64_t* __restrict__ items_in,
                                         const int32_t* __restrict__ L,
                                         const int32_t* __restrict__ R, int64_t N, int64_t n,
@@ -325,16 +401,7 @@ __device__ __forceinline__ void os_pass(const uint64_t* __restrict__ items_in,
     // i.e. outside the OR over the bits of (ballot of the bit) XOR (own bit
     // spread over the word); bits above `bits` are zero in every lane and
     // add nothing
-    const uint64_t vm = ballot(valid);
-    uint32_t xlo = 0, xhi = 0;
-#pragma unroll
-    for (int b = 0; b < RADIX_BITS; ++b) {
-      const uint32_t x = (uint32_t)((int32_t)(d << (31 - b)) >> 31);  // bit b, spread
-      const uint64_t m = ballot(x != 0);
-      xlo |= (uint32_t)m ^ x;
-      xhi |= (uint32_t)(m >> 32) ^ x;
-    }
-    const uint64_t match = vm & ~(((uint64_t)xhi << 32) | xlo);
+    const uint64_t match = same_digit_lanes<BITS>(d, ballot(valid));
     const uint32_t before = wave_cnt[wave][d];
     rank[rd] = before + (uint32_t)__popcll(match & lt);
     // every lane of a digit group stores the same new count (an invalid
@@ -374,40 +441,9 @@ __device__ __forceinline__ void os_pass(const uint64_t* __restrict__ items_in,
     }
   }
 
-  // look back for the number of digit-d items in all earlier tiles: read
-  // LOOKBACK predecessors' words at once, newest first, and take values up to
-  // the first inclusive one, or stop at an unpublished one and read again
-  uint64_t before = 0;
-  if (tile > 0 && used_digit) {
-    int64_t j = tile - 1;
-    uint32_t spins = 0;
-    for (;;) {
-      uint64_t w[LOOKBACK];
-#pragma unroll
-      for (int i = 0; i < LOOKBACK; ++i)
-        w[i] = j - i >= 0 ? load_status(status + (j - i) * RADIX + d) : 0;
-      bool done = false;
-      int used = 0;
-#pragma unroll
-      for (int i = 0; i < LOOKBACK; ++i) {
-        if (done || used != i || (w[i] & ~ST_VAL) == 0) continue;
-        before += w[i] & ST_VAL;
-        done = (w[i] & ST_INC) != 0;
-        used = i + 1;
-      }
-      if (done) break;
-      j -= used;
-      if (used == 0) {  // the nearest unread predecessor has not published yet
-        if (++spins > SPIN_LIMIT ||
-            __hip_atomic_load(abort_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-          __hip_atomic_store(abort_word, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-      }
-    }
-    store_status(mine, ST_INC | (before + run));
-  }
+  // digit d's count in all earlier tiles
+  const uint64_t before = tile > 0 && used_digit ? look_back(status, tile, d, abort_word) : 0;
+  if (tile > 0 && used_digit) store_status(mine, ST_INC | (before + run));
   global_start[d] = digit_base + (uint32_t)before;
   __syncthreads();
 
@@ -492,7 +528,7 @@ __device__ __forceinline__ void os_pass(const uint64_t* __restrict__ items_in,
   }
 }
 
-template <int MODE, int ROUNDS>
+template <int MODE, int ROUNDS, int BITS>
 __global__ __launch_bounds__(WG) void k_os_pass(const uint64_t* __restrict__ items_in,
                                                 const int32_t* __restrict__ L,
                                                 const int32_t* __restrict__ R, int64_t N,
@@ -502,22 +538,64 @@ __global__ __launch_bounds__(WG) void k_os_pass(const uint64_t* __restrict__ ite
                                                 uint32_t* ticket, uint32_t* abort_word,
                                                 uint64_t* __restrict__ items_out,
                                                 int32_t* __restrict__ LR) {
-  os_pass<MODE, ROUNDS, false>(items_in, L, R, N, n, shift, bits, hist, status, status_next,
-                               ticket, abort_word, items_out, LR, nullptr, nullptr, 1);
+  os_pass<MODE, ROUNDS, false, BITS>(items_in, L, R, N, n, shift, bits, hist, status,
+                                     status_next, ticket, abort_word, items_out, LR, nullptr,
+                                     nullptr, 1);
+}
+
+// Launch of a pass whose digits have `bits` bits: the ranking takes one
+// ballot per digit bit, unrolled for the widths digit splits produce (the
+// others rank all RADIX_BITS bits, those above the digit zero everywhere).
+template <int MODE, int ROUNDS>
+hipError_t launch_pass(dim3 grid, hipStream_t stream, int bits, const uint64_t* in,
+                       const int32_t* L, const int32_t* R, int64_t N, int64_t n, int shift,
+                       const uint32_t* hist, uint64_t* st, uint64_t* st_next, uint32_t* ticket,
+                       uint32_t* abort_word, uint64_t* dst, int32_t* lr) {
+  switch (bits) {
+    case RADIX_BITS - 2:
+      return launch(k_os_pass<MODE, ROUNDS, RADIX_BITS - 2>, grid, dim3(WG), 0, stream, in, L, R,
+                    N, n, shift, bits, hist, st, st_next, ticket, abort_word, dst, lr);
+    case RADIX_BITS - 1:
+      return launch(k_os_pass<MODE, ROUNDS, RADIX_BITS - 1>, grid, dim3(WG), 0, stream, in, L, R,
+                    N, n, shift, bits, hist, st, st_next, ticket, abort_word, dst, lr);
+    default:
+      return launch(k_os_pass<MODE, ROUNDS, RADIX_BITS>, grid, dim3(WG), 0, stream, in, L, R, N,
+                    n, shift, bits, hist, st, st_next, ticket, abort_word, dst, lr);
+  }
 }
 
 // The last pass of a long endpoint sort (4096-item tiles), remap through
 // LR windows.  Its own kernel, so that the registers the pairs take do not
 // lower the occupancy of the other passes.
-template <int MODE>
-__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) void k_os_pass_windows(
+template <int MODE, int BITS>
+__global__ __launch_bounds__(WG) void k_os_pass_windows(
     const uint64_t* __restrict__ items_in, const int32_t* __restrict__ L,
     const int32_t* __restrict__ R, int64_t N, int64_t n, int shift, int bits,
     const uint32_t* __restrict__ hist, uint64_t* status, uint32_t* ticket, uint32_t* abort_word,
     uint64_t* __restrict__ items_out, uint64_t* __restrict__ pairs, uint16_t* __restrict__ pre,
     int nwin) {
-  os_pass<MODE, 16, true>(items_in, L, R, N, n, shift, bits, hist, status, nullptr, ticket,
+  os_pass<MODE, BIG_ROUNDS, true, BITS>(items_in, L, R, N, n, shift, bits, hist, status, nullptr,
+                                        ticket,
                           abort_word, items_out, nullptr, pairs, pre, nwin);
+}
+
+template <int MODE>
+hipError_t launch_win_pass(dim3 grid, hipStream_t stream, const uint64_t* in, const int32_t* L,
+                           const int32_t* R, int64_t N, int64_t n, int shift, int bits,
+                           const uint32_t* hist, uint64_t* st, uint32_t* ticket,
+                           uint32_t* abort_word, uint64_t* dst, uint64_t* pairs, uint16_t* pre,
+                           int nwin) {
+  switch (bits) {
+    case RADIX_BITS - 2:
+      return launch(k_os_pass_windows<MODE, RADIX_BITS - 2>, grid, dim3(WG), 0, stream, in, L, R,
+                    N, n, shift, bits, hist, st, ticket, abort_word, dst, pairs, pre, nwin);
+    case RADIX_BITS - 1:
+      return launch(k_os_pass_windows<MODE, RADIX_BITS - 1>, grid, dim3(WG), 0, stream, in, L, R,
+                    N, n, shift, bits, hist, st, ticket, abort_word, dst, pairs, pre, nwin);
+    default:
+      return launch(k_os_pass_windows<MODE, RADIX_BITS>, grid, dim3(WG), 0, stream, in, L, R, N,
+                    n, shift, bits, hist, st, ticket, abort_word, dst, pairs, pre, nwin);
+  }
 }
 
 // LR window w (tags [w * WIN, (w + 1) * WIN)) from the pairs of every tile:
@@ -531,7 +609,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) void k_
 // (At 2q = 2e7 it fetches 1.25x the pair bytes from HBM; with the windows
 // spread over the XCDs it fetched 3.6x.)
 constexpr int AWG = 1024;  // threads of a window workgroup
-constexpr int WIN_TILE = 4096;
+constexpr int WIN_TILE = BIG_TILE;
 __global__ __launch_bounds__(AWG) void k_remap_windows(const uint64_t* __restrict__ pairs,
                                                        const uint16_t* __restrict__ pre,
                                                        int64_t num_tiles, int nwin, int lpt_shift,
@@ -694,7 +772,7 @@ SortLayout sort_layout_items(int64_t N) {
   s.off_tickets = take(sizeof(uint32_t) * MAX_PASSES);
   s.off_abort = take(sizeof(uint32_t));
   const int64_t nwin = (N + WIN - 1) / WIN;
-  s.nwin = N >= WIN_MIN_N && s.rounds == 16 && s.num_tiles <= WIN_MAX_TILES &&
+  s.nwin = N >= WIN_MIN_N && s.rounds == BIG_ROUNDS && s.num_tiles <= WIN_MAX_TILES &&
                    nwin <= MAX_WINDOWS
                ? (int)nwin
                : 0;
@@ -738,7 +816,7 @@ hipError_t onesweep_r(const uint64_t* src, const int32_t* L, const int32_t* R, i
                       int64_t n, const Digits& dg, const SortLayout& lay, const SortBufs& b,
                       uint64_t* out, int32_t* LR, uint64_t* pairs, hipStream_t stream) {
   // the remap through LR windows: a long list, 4096-item tiles, and pair scratch
-  const bool windows = LR && pairs && lay.nwin > 0 && ROUNDS == 16;
+  const bool windows = LR && pairs && lay.nwin > 0 && ROUNDS == BIG_ROUNDS;
   RMQ_TRY(clear(lay, b, stream));
   RMQ_TRY(launch(k_os_hist<MODE, ROUNDS>, dim3((unsigned)lay.hist_groups), dim3(WG), 0, stream,
                  src, L, R, N, n, dg, lay.hist_per_group, b.hist));
@@ -752,13 +830,13 @@ hipError_t onesweep_r(const uint64_t* src, const int32_t* L, const int32_t* R, i
     const dim3 grid((unsigned)lay.num_tiles), block(WG);
     if (windows && p + 1 == dg.passes) {
       if (p == 0)
-        RMQ_TRY(launch(k_os_pass_windows<MODE>, grid, block, 0, stream, in, L, R, N, n,
-                       dg.shift[p], dg.bits[p], b.hist + p * RADIX, st, b.tickets + p,
-                       b.abort_word, dst, pairs, b.pre, lay.nwin));
+        RMQ_TRY((launch_win_pass<MODE>)(grid, stream, in, L, R, N, n, dg.shift[p], dg.bits[p],
+                                        b.hist + p * RADIX, st, b.tickets + p, b.abort_word,
+                                        dst, pairs, b.pre, lay.nwin));
       else
-        RMQ_TRY(launch(k_os_pass_windows<ITEMS>, grid, block, 0, stream, in, L, R, N, n,
-                       dg.shift[p], dg.bits[p], b.hist + p * RADIX, st, b.tickets + p,
-                       b.abort_word, dst, pairs, b.pre, lay.nwin));
+        RMQ_TRY((launch_win_pass<ITEMS>)(grid, stream, in, L, R, N, n, dg.shift[p], dg.bits[p],
+                                         b.hist + p * RADIX, st, b.tickets + p, b.abort_word,
+                                         dst, pairs, b.pre, lay.nwin));
       // lanes per tile: the power of two at or above the mean run length
       // (4096 * WIN / N pairs), between 4 and 64
       const double mean_run = (double)WIN_TILE * WIN / (double)N;
@@ -768,13 +846,13 @@ hipError_t onesweep_r(const uint64_t* src, const int32_t* L, const int32_t* R, i
                      static_cast<const uint64_t*>(pairs), static_cast<const uint16_t*>(b.pre),
                      lay.num_tiles, lay.nwin, lpt_shift, N, LR));
     } else if (p == 0)
-      RMQ_TRY(launch(k_os_pass<MODE, ROUNDS>, grid, block, 0, stream, in, L, R, N, n,
-                     dg.shift[p], dg.bits[p], b.hist + p * RADIX, st, st_next, b.tickets + p,
-                     b.abort_word, dst, lr));
+      RMQ_TRY((launch_pass<MODE, ROUNDS>)(grid, stream, dg.bits[p], in, L, R, N, n, dg.shift[p],
+                                        b.hist + p * RADIX, st, st_next, b.tickets + p,
+                                        b.abort_word, dst, lr));
     else
-      RMQ_TRY(launch(k_os_pass<ITEMS, ROUNDS>, grid, block, 0, stream, in, L, R, N, n,
-                     dg.shift[p], dg.bits[p], b.hist + p * RADIX, st, st_next, b.tickets + p,
-                     b.abort_word, dst, lr));
+      RMQ_TRY((launch_pass<ITEMS, ROUNDS>)(grid, stream, dg.bits[p], in, L, R, N, n, dg.shift[p],
+                                         b.hist + p * RADIX, st, st_next, b.tickets + p,
+                                         b.abort_word, dst, lr));
     in = dst;
   }
   return hipSuccess;
@@ -785,9 +863,10 @@ hipError_t onesweep(const uint64_t* src, const int32_t* L, const int32_t* R, int
                     const Digits& dg, const SortLayout& lay, const SortBufs& b, uint64_t* out,
                     int32_t* LR, uint64_t* pairs, hipStream_t stream) {
   switch (lay.rounds) {
-    case 4: return onesweep_r<MODE, 4>(src, L, R, N, n, dg, lay, b, out, LR, pairs, stream);
-    case 8: return onesweep_r<MODE, 8>(src, L, R, N, n, dg, lay, b, out, LR, pairs, stream);
-    default: return onesweep_r<MODE, 16>(src, L, R, N, n, dg, lay, b, out, LR, pairs, stream);
+    case R1K: return onesweep_r<MODE, R1K>(src, L, R, N, n, dg, lay, b, out, LR, pairs, stream);
+    case R2K: return onesweep_r<MODE, R2K>(src, L, R, N, n, dg, lay, b, out, LR, pairs, stream);
+    default:
+      return onesweep_r<MODE, BIG_ROUNDS>(src, L, R, N, n, dg, lay, b, out, LR, pairs, stream);
   }
 }
 
@@ -799,11 +878,10 @@ hipError_t tag_sweep(const uint64_t* E, const SortLayout& lay, const SortBufs& b
   RMQ_TRY(launch(k_os_hist<E_TAGS, ROUNDS>, dim3((unsigned)lay.hist_groups), dim3(WG), 0, stream,
                  E, static_cast<const int32_t*>(nullptr), static_cast<const int32_t*>(nullptr),
                  lay.N, (int64_t)0, dg, lay.hist_per_group, b.hist));
-  RMQ_TRY(launch(k_os_pass<E_TAGS, ROUNDS>, dim3((unsigned)lay.num_tiles), dim3(WG), 0, stream, E,
-                 static_cast<const int32_t*>(nullptr), static_cast<const int32_t*>(nullptr),
-                 lay.N, (int64_t)0, dg.shift[0], dg.bits[0], b.hist, b.status[0],
-                 static_cast<uint64_t*>(nullptr), b.tickets, b.abort_word, sorted,
-                 static_cast<int32_t*>(nullptr)));
+  RMQ_TRY((launch_pass<E_TAGS, ROUNDS>)(dim3((unsigned)lay.num_tiles), stream, dg.bits[0], E,
+                                       nullptr, nullptr, lay.N, 0, dg.shift[0], b.hist,
+                                       b.status[0], nullptr, b.tickets, b.abort_word, sorted,
+                                       nullptr));
   return hipSuccess;
 }
 
@@ -853,9 +931,9 @@ hipError_t launch_remap(const uint64_t* E, int64_t q, int32_t* LR, void* ws, siz
   dg.bits[0] = top;
   uint64_t* sorted = b.items;
   switch (lay.rounds) {
-    case 4: RMQ_TRY(tag_sweep<4>(E, lay, b, dg, sorted, stream)); break;
-    case 8: RMQ_TRY(tag_sweep<8>(E, lay, b, dg, sorted, stream)); break;
-    default: RMQ_TRY(tag_sweep<16>(E, lay, b, dg, sorted, stream)); break;
+    case R1K: RMQ_TRY(tag_sweep<R1K>(E, lay, b, dg, sorted, stream)); break;
+    case R2K: RMQ_TRY(tag_sweep<R2K>(E, lay, b, dg, sorted, stream)); break;
+    default: RMQ_TRY(tag_sweep<BIG_ROUNDS>(E, lay, b, dg, sorted, stream)); break;
   }
   const int64_t chunks = (lay.N + 4 * WG - 1) / (4 * WG);
   RMQ_TRY(launch(k_remap_apply, dim3((unsigned)xcd_grid(chunks)), dim3(WG), 0, stream, sorted,
