@@ -384,11 +384,14 @@ rmq_status rmq_contract(const int32_t *A, int64_t n, const int32_t *pos, const i
 
 /* ----------------------------------------------------------------------------
  * Batches of arrays.  Many independent arrays, each with its own batch of
- * queries, answered together: the planner picks each array's block size and
- * method (the automated choice of k left open in Section 5), and the arrays
- * that take the plain method (Section 3.2) run as ONE launch per phase for
- * all of them -- block minima, each round of Sparse Table levels, queries --
- * instead of a few launches per array.  A batch owns its device scratch and a
+ * queries, answered together: the planner picks each array's block size,
+ * method and block levels (the automated choice of k left open in Section
+ * 5; two block levels, Section 3.3, where its measured table chooses them),
+ * and the arrays that take the plain method (Section 3.2) run as ONE launch
+ * per phase for all of them -- block minima, the k-block minima from the
+ * k1-block minima (arrays with two levels), each round of Sparse Table
+ * levels, queries (one launch for the arrays with two levels, one for the
+ * others) -- instead of a few launches per array.  A batch owns its device scratch and a
  * device table describing the arrays; inputs and outputs stay the caller's.
  * Pointers in the items must stay valid, and the arrays unmodified, for the
  * batch's life: runs reuse them. */
@@ -417,6 +420,12 @@ rmq_status rmq_batch_run(rmq_batch b, int32_t mode, int32_t use_graph, void *str
 
 /* The block size and method the planner gave item i. */
 rmq_status rmq_batch_item_plan(rmq_batch b, int32_t i, int32_t *block_size, int32_t *path);
+
+/* As rmq_batch_item_plan, and the sub-block size k1 when the planner gave
+ * the item two block levels (Section 3.3; 0: one level).  Any output
+ * pointer may be NULL. */
+rmq_status rmq_batch_item_plan_ex(rmq_batch b, int32_t i, int32_t *block_size, int32_t *path,
+                                  int32_t *sub_block_size);
 
 /* Device scratch the batch holds for its items. */
 size_t rmq_batch_workspace_bytes(rmq_batch b);
@@ -458,6 +467,10 @@ typedef struct rmq_server_config {
                                         the slots' device buffers; 0 = no
                                         limit.  rmq_server_add_array refuses a
                                         table that would exceed it */
+    int32_t sub_block_size;          /* 0: one block level; else k1 (a power of
+                                        two, 16 <= k1 < k): every table gets two
+                                        block levels (Section 3.3), as
+                                        rmq_build with this sub_block_size */
 } rmq_server_config;
 
 typedef struct rmq_server_stats {
@@ -479,7 +492,8 @@ typedef struct rmq_server_s *rmq_server;
 
 rmq_status rmq_server_create(const rmq_server_config *cfg, rmq_server *out);
 
-/* Build and keep a resident index of device array A (k = block_size, 0 = auto);
+/* Build and keep a resident index of device array A (k = block_size, 0 = auto;
+ * two block levels when the server's config has a sub_block_size);
  * synchronous.  A must stay alive and unmodified for the server's life.
  * Admission by footprint: returns RMQ_ERR_OUT_OF_MEMORY, building nothing,
  * when the table's rmq_build_bytes would take the server's device memory

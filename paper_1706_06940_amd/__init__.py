@@ -109,6 +109,8 @@ def lib() -> ctypes.CDLL:
         "rmq_batch_create": ([v, i32, ctypes.POINTER(v)], i32),
         "rmq_batch_run": ([v, i32, i32, v], i32),
         "rmq_batch_item_plan": ([v, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
+        "rmq_batch_item_plan_ex": ([v, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                    ctypes.POINTER(i32)], i32),
         "rmq_batch_workspace_bytes": ([v], sz),
         "rmq_batch_free": ([v], i32),
         "rmq_test_sort_abort": ([i32], i32),
@@ -559,6 +561,14 @@ class Batch:
         _check("rmq_batch_item_plan", lib().rmq_batch_item_plan(self.handle, i, ctypes.byref(k),
                                                                 ctypes.byref(p)))
         return k.value, {v: k_ for k_, v in PATHS.items()}[p.value]
+
+    def plan_ex(self, i: int):
+        """(block_size, path name, sub_block_size) of item i; sub_block_size
+        > 0 means two block levels."""
+        k, p, k1 = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check("rmq_batch_item_plan_ex", lib().rmq_batch_item_plan_ex(
+            self.handle, i, ctypes.byref(k), ctypes.byref(p), ctypes.byref(k1)))
+        return k.value, {v: k_ for k_, v in PATHS.items()}[p.value], k1.value
 
     def workspace_bytes(self) -> int:
         return int(lib().rmq_batch_workspace_bytes(self.handle))

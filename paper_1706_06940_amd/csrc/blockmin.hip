@@ -4,12 +4,12 @@
 // One streaming pass over the input with 16-byte loads.  A workgroup of 4
 // waves owns a chunk of C elements -- one whole block when k > 4 wave loads,
 // else 16 wave loads -- and wave w owns the w-th quarter of it.  Inside a wave:
-//   * k >= one wave load  -> each lane keeps a running (value, position)
-//     minimum over the iterations of the block, then a full-wave DPP min;
-//   * k <  one wave load  -> a block is k/V lanes of one load and is reduced
-//     with a DPP group min right after the load;
-//   * k >  4 wave loads   -> the four waves hold quarters of one block and
-//     combine their minima through LDS.
+//   * k <= 4 wave loads   -> the wave's four loads go out together; a block
+//     is then k / (one wave load) of them (a per-lane running (value,
+//     position) minimum, then a full-wave DPP min), or k / V lanes of one
+//     load (a DPP group min);
+//   * k >  4 wave loads   -> the four waves hold quarters of one block, four
+//     loads in flight per step, and combine their minima through LDS.
 #include "device.h"
 #include "kernels.h"
 
@@ -65,49 +65,61 @@ __device__ __forceinline__ void blockmin_i32_wg(const int32_t* __restrict__ A, i
   const int64_t WS = C / 4;  // elements per wave, >= 4 * WL
   const int64_t w0 = wg * C + wave * WS;
 
-  if (k >= WL) {
-    // one block spans >= 1 wave loads; this wave holds WS / min(k, WS) block slices
-    const int64_t span = k < WS ? k : WS;
-    for (int64_t s0 = w0; s0 < w0 + WS; s0 += span) {
-      const int64_t first = s0 + lane * V;
-      LaneMin m{INT32_MAX, first};
-      int64_t it = 0;
-      for (; it + 4 * WL <= span; it += 4 * WL) {
-        v4i32 x0 = load4_i32<ALIGNED>(A, first + it, n);
-        v4i32 x1 = load4_i32<ALIGNED>(A, first + it + WL, n);
-        v4i32 x2 = load4_i32<ALIGNED>(A, first + it + 2 * WL, n);
-        v4i32 x3 = load4_i32<ALIGNED>(A, first + it + 3 * WL, n);
-        lane_update(m, x0, first + it);
-        lane_update(m, x1, first + it + WL);
-        lane_update(m, x2, first + it + 2 * WL);
-        lane_update(m, x3, first + it + 3 * WL);
+  if (k <= 4 * WL) {
+    // the wave's four loads (WS = 4 WL) go out together, then its blocks
+    // are reduced: k / WL loads per block, or k / V lanes of one load
+    v4i32 x[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) x[c] = load4_i32<ALIGNED>(A, w0 + c * WL + lane * V, n);
+    if (k >= WL) {
+      const int per = (int)(k / WL);  // 1, 2 or 4
+#pragma unroll
+      for (int b0 = 0; b0 < 4; ++b0) {
+        if (b0 % per) continue;
+        const int64_t first = w0 + b0 * WL + lane * V;
+        LaneMin m{INT32_MAX, first};
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          if (c >= b0 && c < b0 + per) lane_update(m, x[c], w0 + c * WL + lane * V);
+        const uint64_t key = group_min_u64<64>(lane_key(m, first, n));
+        const int64_t s0 = w0 + b0 * WL;
+        if (lane == 63 && s0 < n) keys[s0 >> kshift] = key;
       }
-      for (; it < span; it += WL) lane_update(m, load4_i32<ALIGNED>(A, first + it, n), first + it);
-      uint64_t key = group_min_u64<64>(lane_key(m, first, n));
-      if (k > WS) {
-        if (lane == 63) part[wave] = key;
-      } else if (lane == 63 && s0 < n) {
-        keys[s0 >> kshift] = key;
+    } else {
+      // several blocks per wave load: groups of g = k / V lanes
+      const int g = (int)(k / V);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int64_t first = w0 + c * WL + lane * V;
+        LaneMin m{INT32_MAX, first};
+        lane_update(m, x[c], first);
+        const uint64_t key = group_min_u64_rt(lane_key(m, first, n), g);
+        const int64_t blk_start = first - (int64_t)(lane % g) * V;
+        if ((lane % g) == g - 1 && blk_start < n) keys[blk_start >> kshift] = key;
       }
     }
-    if (k > WS) {
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        uint64_t b = umin64(umin64(part[0], part[1]), umin64(part[2], part[3]));
-        if (wg * C < n) keys[wg] = b;
-      }
-    }
-  } else {
-    // several blocks per wave load: groups of g = k / V lanes
-    const int g = (int)(k / V);
-    for (int64_t it = 0; it < WS; it += WL) {
-      const int64_t first = w0 + it + lane * V;
-      LaneMin m{INT32_MAX, first};
-      lane_update(m, load4_i32<ALIGNED>(A, first, n), first);
-      uint64_t key = group_min_u64_rt(lane_key(m, first, n), g);
-      const int64_t blk_start = first - (int64_t)(lane % g) * V;
-      if ((lane % g) == g - 1 && blk_start < n) keys[blk_start >> kshift] = key;
-    }
+    return;
+  }
+
+  // one block spans more than 4 wave loads: the workgroup holds one block,
+  // each wave a quarter of it, with four loads in flight per step
+  const int64_t first = w0 + lane * V;
+  LaneMin m{INT32_MAX, first};
+  const v4i32 none = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MAX};
+  for (int64_t it = 0; it < WS; it += 4 * WL) {  // WS = 2, 4, 8, ... wave loads
+    v4i32 x[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      x[c] = it + c * WL < WS ? load4_i32<ALIGNED>(A, first + it + c * WL, n) : none;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) lane_update(m, x[c], first + it + c * WL);
+  }
+  const uint64_t key = group_min_u64<64>(lane_key(m, first, n));
+  if (lane == 63) part[wave] = key;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint64_t b = umin64(umin64(part[0], part[1]), umin64(part[2], part[3]));
+    if (wg * C < n) keys[wg] = b;
   }
 }
 
@@ -118,19 +130,16 @@ __global__ __launch_bounds__(WG) void k_blockmin_i32(const int32_t* __restrict__
   blockmin_i32_wg<ALIGNED>(A, n, kshift, keys, blockIdx.x, part);
 }
 
-// Block minima of every array of a batch in one launch: workgroup w works on
-// the array whose range of workgroups holds w.
-__global__ __launch_bounds__(WG) void k_blockmin_multi(const ArrayDesc* __restrict__ items,
-                                                       const int64_t* __restrict__ wg_prefix,
-                                                       int count) {
+// Block minima of every array of a batch in one launch: workgroup w does
+// job w, one chunk of one array.
+__global__ __launch_bounds__(WG) void k_blockmin_multi(const ChunkJob* __restrict__ jobs) {
   __shared__ uint64_t part[4];
-  const int j = find_item(wg_prefix, count, blockIdx.x);
-  const ArrayDesc& d = items[j];
-  const int64_t wg = blockIdx.x - wg_prefix[j];
-  if (((uintptr_t)d.A & 15) == 0)
-    blockmin_i32_wg<true>(d.A, d.n, d.kshift, d.st, wg, part);
+  const ChunkJob jb = jobs[blockIdx.x];
+  const int32_t* A = static_cast<const int32_t*>(jb.src);
+  if (((uintptr_t)A & 15) == 0)
+    blockmin_i32_wg<true>(A, jb.len, jb.shift, jb.keys, jb.chunk, part);
   else
-    blockmin_i32_wg<false>(d.A, d.n, d.kshift, d.st, wg, part);
+    blockmin_i32_wg<false>(A, jb.len, jb.shift, jb.keys, jb.chunk, part);
 }
 
 // ---------------------------------------------------------------- uint64 keys
@@ -148,15 +157,15 @@ __device__ __forceinline__ void load2_key(const uint64_t* __restrict__ S, int64_
 }
 
 template <bool ALIGNED>
-__global__ __launch_bounds__(WG) void k_blockmin_keys(const uint64_t* __restrict__ S, int64_t m,
-                                                      int kshift, uint64_t* __restrict__ keys) {
+__device__ __forceinline__ void blockmin_keys_wg(const uint64_t* __restrict__ S, int64_t m,
+                                                 int kshift, uint64_t* __restrict__ keys,
+                                                 int64_t wg, uint64_t* part) {
   constexpr int V = 2, WL = 64 * V;
   const int lane = lane_id(), wave = threadIdx.x >> 6;
   const int64_t k = 1ll << kshift;
   const int64_t C = k > 4 * WL ? k : 16 * WL;
   const int64_t WS = C / 4;
-  const int64_t w0 = (int64_t)blockIdx.x * C + wave * WS;
-  __shared__ uint64_t part[4];
+  const int64_t w0 = wg * C + wave * WS;
 
   if (k >= WL) {
     const int64_t span = k < WS ? k : WS;
@@ -189,7 +198,7 @@ __global__ __launch_bounds__(WG) void k_blockmin_keys(const uint64_t* __restrict
       __syncthreads();
       if (threadIdx.x == 0) {
         uint64_t b = umin64(umin64(part[0], part[1]), umin64(part[2], part[3]));
-        if ((int64_t)blockIdx.x * C < m) keys[blockIdx.x] = b;
+        if (wg * C < m) keys[wg] = b;
       }
     }
   } else {
@@ -203,6 +212,22 @@ __global__ __launch_bounds__(WG) void k_blockmin_keys(const uint64_t* __restrict
       if ((lane % g) == g - 1 && blk_start < m) keys[blk_start >> kshift] = key;
     }
   }
+}
+
+template <bool ALIGNED>
+__global__ __launch_bounds__(WG) void k_blockmin_keys(const uint64_t* __restrict__ S, int64_t m,
+                                                      int kshift, uint64_t* __restrict__ keys) {
+  __shared__ uint64_t part[4];
+  blockmin_keys_wg<ALIGNED>(S, m, kshift, keys, blockIdx.x, part);
+}
+
+// Two block levels in a batch: the k-block minima of each such array from
+// its k1-block minima; workgroup w does job w.
+__global__ __launch_bounds__(WG) void k_blockmin_keys_multi(const ChunkJob* __restrict__ jobs) {
+  __shared__ uint64_t part[4];
+  const ChunkJob jb = jobs[blockIdx.x];
+  blockmin_keys_wg<true>(static_cast<const uint64_t*>(jb.src), jb.len, jb.shift, jb.keys,
+                         jb.chunk, part);
 }
 
 }  // namespace
@@ -227,13 +252,19 @@ hipError_t launch_blockmin_i32(const int32_t* A, int64_t n, int kshift, uint64_t
   return hipGetLastError();
 }
 
-hipError_t launch_blockmin_multi(const ArrayDesc* items, const int64_t* wg_prefix, int count,
-                                 int64_t total_wg, hipStream_t stream) {
-  if (total_wg <= 0) return hipSuccess;
-  RMQ_TRY(launch(k_blockmin_multi, dim3((unsigned)total_wg), dim3(WG), 0, stream, items,
-                 wg_prefix, count));
+hipError_t launch_blockmin_multi(const ChunkJob* jobs, int64_t count, hipStream_t stream) {
+  if (count <= 0) return hipSuccess;
+  RMQ_TRY(launch(k_blockmin_multi, dim3((unsigned)count), dim3(WG), 0, stream, jobs));
   return hipSuccess;
 }
+
+hipError_t launch_blockmin_keys_multi(const ChunkJob* jobs, int64_t count, hipStream_t stream) {
+  if (count <= 0) return hipSuccess;
+  RMQ_TRY(launch(k_blockmin_keys_multi, dim3((unsigned)count), dim3(WG), 0, stream, jobs));
+  return hipSuccess;
+}
+
+int64_t blockmin_keys_grid(int64_t m, int kshift) { return blockmin_grid(m, kshift, 2); }
 
 hipError_t launch_blockmin_keys(const uint64_t* S, int64_t m, int kshift, uint64_t* keys,
                                 hipStream_t stream) {

@@ -7,6 +7,7 @@
 #include <atomic>
 #include <mutex>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "index.h"
@@ -866,39 +867,40 @@ rmq_status rmq_timer_destroy(rmq_timer* t) {
 }  // extern "C"
 
 // ---- batches of arrays ----
+// A batched launch's job table on the device (see ChunkJob and friends).
+template <class Job>
+struct JobTable {
+  const Job* jobs = nullptr;
+  int64_t count = 0;
+};
+
 struct rmq_batch_s {
   int device;
   std::vector<rmq_batch_item> items;
   std::vector<Plan> plans;
   std::vector<size_t> ws_off;  // per item, into ws
-  char* ws = nullptr;          // device scratch for every item
+  char* ws = nullptr;          // device scratch for every item, then the job tables
   size_t ws_bytes = 0;
-  // plain-path items, run together by the batched kernels
-  std::vector<int> full_items;
-  ArrayDesc* d_desc = nullptr;  // device copy of their descriptors
-  int64_t* d_prefix = nullptr;  // device prefix tables (see below)
-  int64_t total_wg = 0, total_q = 0;
+  std::vector<int> full_items;  // plain-path items, run together by the batched kernels
+  JobTable<ChunkJob> blockmin, keys;
   int rounds = 0;
-  int64_t round_tiles[ST_MAX_ROUNDS] = {};
-  size_t off_wg = 0, off_q = 0, off_round[ST_MAX_ROUNDS] = {};
+  JobTable<TileJob> round[ST_MAX_ROUNDS];
+  JobTable<WaveJob> queries_two, queries_one;  // arrays with two block levels / one
   hipGraphExec_t graph[2] = {nullptr, nullptr};
 };
 
 namespace {
 
 rmq_status batch_enqueue(rmq_batch b, int mode, hipStream_t s) {
-  if (mode == RMQ_BATCH_FUSED) {
-    const int cnt = (int)b->full_items.size();
-    if (cnt > 0) {
-      hipError_t e = launch_blockmin_multi(b->d_desc, b->d_prefix + b->off_wg, cnt, b->total_wg, s);
-      for (int r = 0; e == hipSuccess && r < b->rounds; ++r)
-        e = launch_sparse_table_multi(b->d_desc, b->d_prefix + b->off_round[r], cnt, r,
-                                      b->round_tiles[r], s);
-      if (e == hipSuccess)
-        e = launch_query_multi(b->d_desc, b->d_prefix + b->off_q, cnt, b->total_q, nullptr,
-                               nullptr, s);
-      if (e != hipSuccess) return from_hip(e);
-    }
+  if (mode == RMQ_BATCH_FUSED && !b->full_items.empty()) {
+    hipError_t e = launch_blockmin_multi(b->blockmin.jobs, b->blockmin.count, s);
+    if (e == hipSuccess) e = launch_blockmin_keys_multi(b->keys.jobs, b->keys.count, s);
+    for (int r = 0; e == hipSuccess && r < b->rounds; ++r)
+      e = launch_sparse_table_multi(b->round[r].jobs, r, b->round[r].count, s);
+    if (e == hipSuccess) e = launch_query_multi(b->queries_two.jobs, b->queries_two.count, true, s);
+    if (e == hipSuccess)
+      e = launch_query_multi(b->queries_one.jobs, b->queries_one.count, false, s);
+    if (e != hipSuccess) return from_hip(e);
   }
   for (size_t i = 0; i < b->items.size(); ++i) {
     const Plan& p = b->plans[i];
@@ -940,8 +942,8 @@ rmq_status rmq_batch_create(const rmq_batch_item* items, int32_t count, rmq_batc
     rmq_options o{};
     o.block_size = items[i].block_size;
     o.path = items[i].path;
-    // one block level: the batched kernels read one level
-    rmq_status st = make_plan(items[i].n, items[i].q, &o, &b->plans[i], false);
+    // the planner's choice, two block levels (Section 3.3) included
+    rmq_status st = make_plan(items[i].n, items[i].q, &o, &b->plans[i]);
     if (st != RMQ_OK) {
       delete b;
       return st;
@@ -953,58 +955,103 @@ rmq_status rmq_batch_create(const rmq_batch_item* items, int32_t count, rmq_batc
   }
   b->ws_bytes = off;
 
-  // descriptors and prefix tables of the plain-path items
-  const int cnt = (int)b->full_items.size();
-  std::vector<ArrayDesc> desc(cnt);
-  std::vector<int64_t> wg(cnt + 1, 0), qp(cnt + 1, 0);
-  std::vector<std::vector<int64_t>> rt(ST_MAX_ROUNDS, std::vector<int64_t>(cnt + 1, 0));
-  for (int c = 0; c < cnt; ++c) {
-    const int i = b->full_items[c];
+  // job tables of the plain-path items (their device addresses are filled
+  // in once the scratch exists; offsets into the scratch until then)
+  std::vector<ChunkJob> jb_min, jb_keys;
+  std::vector<TileJob> jb_round[ST_MAX_ROUNDS];
+  std::vector<WaveJob> jb_q2, jb_q1;
+  std::vector<ArrayDesc> desc;
+  for (int i : b->full_items) {
     const rmq_batch_item& it = items[i];
-    const FullLayout f = full_layout(it.n, b->plans[i].k, -1, 1, false);
-    desc[c] = ArrayDesc{it.A, it.n, b->plans[i].kshift, f.levels, f.nb, nullptr,
-                        it.L, it.R, it.q, it.out, 1, nullptr, 0};
-    wg[c + 1] = wg[c] + blockmin_grid(it.n, b->plans[i].kshift, 4);
-    qp[c + 1] = qp[c] + it.q;
+    const Plan& p = b->plans[i];
+    const FullLayout f = full_layout(it.n, p.k, p.k1shift, 1, false);
+    const bool two = p.k1shift >= 0;
+    desc.push_back(ArrayDesc{it.A, it.n, p.kshift, f.levels, f.nb, nullptr, it.L, it.R, it.q,
+                             it.out, 1, nullptr, 0, nullptr, f.nb1, p.k1shift});
+    const int64_t g = blockmin_grid(it.n, two ? p.k1shift : p.kshift, 4);
+    for (int64_t c = 0; c < g; ++c)
+      jb_min.push_back(ChunkJob{it.A, nullptr, it.n, two ? p.k1shift : p.kshift, (int32_t)c});
+    if (two) {
+      const int64_t gk = blockmin_keys_grid(f.nb1, p.kshift - p.k1shift);
+      for (int64_t c = 0; c < gk; ++c)
+        jb_keys.push_back(ChunkJob{nullptr, nullptr, f.nb1, p.kshift - p.k1shift, (int32_t)c});
+    }
     const int rounds = st_rounds(f.levels);
     if (rounds > ST_MAX_ROUNDS) {
       delete b;
       return RMQ_ERR_INVALID_ARG;
     }
     if (rounds > b->rounds) b->rounds = rounds;
-    for (int r = 0; r < ST_MAX_ROUNDS; ++r)
-      rt[r][c + 1] = rt[r][c] + st_round_tiles(f.nb, f.levels, r);
+    for (int r = 0; r < rounds; ++r) {
+      const int64_t tiles = st_round_tiles(f.nb, f.levels, r);
+      for (int64_t t = 0; t < tiles; ++t)
+        jb_round[r].push_back(TileJob{nullptr, f.nb, f.levels, (int32_t)t});
+    }
+    for (int64_t q0 = 0; q0 < it.q; q0 += 64) (two ? jb_q2 : jb_q1).push_back(WaveJob{{}, q0});
   }
-  b->total_wg = wg[cnt];
-  b->total_q = qp[cnt];
-  for (int r = 0; r < ST_MAX_ROUNDS; ++r) b->round_tiles[r] = rt[r][cnt];
-  const size_t desc_bytes = align_up(sizeof(ArrayDesc) * (size_t)(cnt > 0 ? cnt : 1));
-  const size_t table_len = (size_t)(cnt + 1);
-  b->off_wg = 0;
-  b->off_q = table_len;
-  for (int r = 0; r < ST_MAX_ROUNDS; ++r) b->off_round[r] = (2 + r) * table_len;
-  const size_t prefix_bytes = sizeof(int64_t) * table_len * (2 + ST_MAX_ROUNDS);
+  // where each job's array and pointers are: record the item per job
+  size_t tbytes = 0;
+  auto tsize = [](size_t bytes) { return align_up(bytes ? bytes : 1); };
+  tbytes += tsize(sizeof(ChunkJob) * jb_min.size()) + tsize(sizeof(ChunkJob) * jb_keys.size());
+  for (int r = 0; r < ST_MAX_ROUNDS; ++r) tbytes += tsize(sizeof(TileJob) * jb_round[r].size());
+  tbytes += tsize(sizeof(WaveJob) * jb_q2.size()) + tsize(sizeof(WaveJob) * jb_q1.size());
 
   void* mem = nullptr;
-  hipError_t e = hipMalloc(&mem, b->ws_bytes + desc_bytes + prefix_bytes);
+  hipError_t e = hipMalloc(&mem, b->ws_bytes + tbytes);
   if (e != hipSuccess) {
     delete b;
     return from_hip(e);
   }
   b->ws = static_cast<char*>(mem);
-  b->d_desc = reinterpret_cast<ArrayDesc*>(b->ws + b->ws_bytes);
-  b->d_prefix = reinterpret_cast<int64_t*>(b->ws + b->ws_bytes + desc_bytes);
-  for (int c = 0; c < cnt; ++c)
-    desc[c].st = reinterpret_cast<uint64_t*>(b->ws + b->ws_off[b->full_items[c]]);
-  std::vector<int64_t> prefix(table_len * (2 + ST_MAX_ROUNDS));
-  for (size_t c = 0; c < table_len; ++c) {
-    prefix[b->off_wg + c] = wg[c];
-    prefix[b->off_q + c] = qp[c];
-    for (int r = 0; r < ST_MAX_ROUNDS; ++r) prefix[b->off_round[r] + c] = rt[r][c];
+  // fill in the device pointers: per item its table and k1-block minima
+  {
+    size_t a = 0, k = 0, q2 = 0, q1 = 0;
+    size_t rr[ST_MAX_ROUNDS] = {};
+    for (size_t c = 0; c < b->full_items.size(); ++c) {
+      const int i = b->full_items[c];
+      const Plan& p = b->plans[i];
+      const FullLayout f = full_layout(items[i].n, p.k, p.k1shift, 1, false);
+      char* w = b->ws + b->ws_off[i];
+      ArrayDesc& d = desc[c];
+      d.st = reinterpret_cast<uint64_t*>(w + f.off_st);
+      d.sub = p.k1shift >= 0 ? reinterpret_cast<uint64_t*>(w + f.off_sub) : nullptr;
+      const bool two = d.sub != nullptr;
+      const int64_t g = blockmin_grid(items[i].n, two ? p.k1shift : p.kshift, 4);
+      for (int64_t j = 0; j < g; ++j) jb_min[a++].keys = two ? d.sub : d.st;
+      if (two) {
+        const int64_t gk = blockmin_keys_grid(f.nb1, p.kshift - p.k1shift);
+        for (int64_t j = 0; j < gk; ++j, ++k) {
+          jb_keys[k].src = d.sub;
+          jb_keys[k].keys = d.st;
+        }
+      }
+      for (int r = 0; r < st_rounds(f.levels); ++r) {
+        const int64_t tiles = st_round_tiles(f.nb, f.levels, r);
+        for (int64_t t = 0; t < tiles; ++t) jb_round[r][rr[r]++].st = d.st;
+      }
+      for (int64_t q0 = 0; q0 < items[i].q; q0 += 64) (two ? jb_q2[q2++] : jb_q1[q1++]).d = d;
+    }
   }
-  if (cnt > 0) e = hipMemcpy(b->d_desc, desc.data(), sizeof(ArrayDesc) * cnt, hipMemcpyHostToDevice);
-  if (e == hipSuccess)
-    e = hipMemcpy(b->d_prefix, prefix.data(), prefix_bytes, hipMemcpyHostToDevice);
+  std::vector<char> img(tbytes);
+  size_t at = 0;
+  char* dbase = b->ws + b->ws_bytes;
+  auto place = [&](const void* src, size_t bytes) {
+    if (bytes) memcpy(img.data() + at, src, bytes);
+    const char* dev = dbase + at;
+    at += tsize(bytes);
+    return dev;
+  };
+  auto put = [&](auto& table, const auto& host) {
+    using Job = typename std::remove_reference<decltype(host)>::type::value_type;
+    table.jobs = reinterpret_cast<const Job*>(place(host.data(), sizeof(Job) * host.size()));
+    table.count = (int64_t)host.size();
+  };
+  put(b->blockmin, jb_min);
+  put(b->keys, jb_keys);
+  for (int r = 0; r < ST_MAX_ROUNDS; ++r) put(b->round[r], jb_round[r]);
+  put(b->queries_two, jb_q2);
+  put(b->queries_one, jb_q1);
+  e = hipMemcpy(dbase, img.data(), tbytes, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     hipFree(mem);
     delete b;
@@ -1040,9 +1087,16 @@ rmq_status rmq_batch_run(rmq_batch b, int32_t mode, int32_t use_graph, void* str
 }
 
 rmq_status rmq_batch_item_plan(rmq_batch b, int32_t i, int32_t* block_size, int32_t* path) {
+  return rmq_batch_item_plan_ex(b, i, block_size, path, nullptr);
+}
+
+rmq_status rmq_batch_item_plan_ex(rmq_batch b, int32_t i, int32_t* block_size, int32_t* path,
+                                  int32_t* sub_block_size) {
   if (!b || i < 0 || i >= (int32_t)b->items.size()) return RMQ_ERR_INVALID_ARG;
   if (block_size) *block_size = b->plans[i].k;
   if (path) *path = b->plans[i].path;
+  if (sub_block_size)
+    *sub_block_size = b->plans[i].k1shift >= 0 ? (int32_t)(1 << b->plans[i].k1shift) : 0;
   return RMQ_OK;
 }
 

@@ -54,7 +54,8 @@ inline hipError_t launch(void (*kernel)(KArgs...), dim3 grid, dim3 block, uint32
   } while (0)
 
 // One array of a batch on the device: its input, its block Sparse Table
-// (level-major, levels x nb keys) and its queries.
+// (level-major, levels x nb keys), with two block levels (Section 3.3) its
+// k1-block minima, and its queries.
 struct ArrayDesc {
   const int32_t* A;
   int64_t n;
@@ -69,6 +70,9 @@ struct ArrayDesc {
   int32_t lg;  // table arity l = 2^lg (1: doubling)
   const uint64_t* rec;  // query records of the doubling table, or null
   int32_t rlev;         // levels of the records' table
+  uint64_t* sub;        // two block levels: the k1-block minima, else null
+  int64_t nb1;          // number of k1-blocks
+  int32_t k1shift;      // k1 = 2^k1shift (when sub is set)
 };
 
 // Sparse Table rounds: round r builds levels j0(r)+1 .. j0(r)+t; j0 = 0,
@@ -98,22 +102,45 @@ hipError_t launch_sparse_table_lary(uint64_t* st, int64_t nb, int lg, hipStream_
 hipError_t launch_records(const uint64_t* st, int64_t nb, int levels, uint64_t* rec,
                           hipStream_t stream);
 int64_t blockmin_grid(int64_t n, int kshift, int elems_per_lane_load);
-// Batched forms: one launch per phase for all arrays of a batch.  The
-// prefix tables (count + 1 entries, starting at 0) give each array's first
-// workgroup / tile / query in the launch.
-hipError_t launch_blockmin_multi(const ArrayDesc* items, const int64_t* wg_prefix, int count,
-                                 int64_t total_wg, hipStream_t stream);
-hipError_t launch_sparse_table_multi(const ArrayDesc* items, const int64_t* tile_prefix,
-                                     int count, int round, int64_t total_tiles,
+// Batched forms: one launch per phase for all arrays of a batch.  Every
+// workgroup (block minima, table tiles) or wave (queries) of such a launch
+// reads its whole assignment from one record of a job table built on the
+// host -- a single load before its first load of data.
+struct ChunkJob {            // block minima of one chunk of one array
+  const void* src;           //   int32 A, or uint64 k1-block minima
+  uint64_t* keys;            //   its blocks' minima go here
+  int64_t len;               //   elements of src
+  int32_t shift;             //   blocks of 2^shift elements
+  int32_t chunk;             //   the chunk (workgroup) index within the array
+};
+struct TileJob {             // one tile of a table round
+  uint64_t* st;
+  int64_t nb;
+  int32_t levels;
+  int32_t tile;
+};
+struct WaveJob {             // 64 queries of one array (each array's queries
+  ArrayDesc d;               //   padded to whole waves)
+  int64_t q0;                //   the wave's first query within the array
+};
+// Block minima over int32 arrays (the k1-block minima for arrays with two
+// block levels, else the k-block minima), one workgroup per job.
+hipError_t launch_blockmin_multi(const ChunkJob* jobs, int64_t count, hipStream_t stream);
+// Two block levels: the k-block minima (st level 0) from the k1-block minima.
+hipError_t launch_blockmin_keys_multi(const ChunkJob* jobs, int64_t count, hipStream_t stream);
+hipError_t launch_sparse_table_multi(const TileJob* jobs, int round, int64_t count,
                                      hipStream_t stream);
-hipError_t launch_query_multi(const ArrayDesc* items, const int64_t* q_prefix, int count,
-                              int64_t total_q, int64_t* bad_count, uint64_t* stats,
+// two_level: every array of the jobs has two block levels (else none has).
+hipError_t launch_query_multi(const WaveJob* jobs, int64_t waves, bool two_level,
                               hipStream_t stream);
-// Serving: one launch over a coalesced batch of requests on resident tables.
+// Serving: one launch over a coalesced batch of requests on resident tables
+// (two_level: every table has two block levels, else none has).
 hipError_t launch_query_segments(const ArrayDesc* tables, const int64_t* seg_prefix,
                                  const int32_t* seg_table, int nseg, const int32_t* L,
-                                 const int32_t* R, int32_t* out, int64_t total,
+                                 const int32_t* R, int32_t* out, int64_t total, bool two_level,
                                  hipStream_t stream);
+// Block count of launch_blockmin_keys for m keys and blocks of 2^kshift.
+int64_t blockmin_keys_grid(int64_t m, int kshift);
 // lg: the table's arity l = 2^lg (1: doubling; see launch_sparse_table_lary).
 hipError_t launch_query_full(const int32_t* A, int64_t n, int kshift, const uint64_t* st,
                              int64_t nb, const int32_t* L, const int32_t* R, int64_t q,

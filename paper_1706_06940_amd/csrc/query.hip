@@ -467,30 +467,43 @@ __global__ __launch_bounds__(WG) void k_query(Src src, int64_t src_len, int64_t 
 
 // Every query of a batch of tables (plain path): global query g belongs to
 // the table whose range of the concatenated query list holds it.
-__global__ __launch_bounds__(WG) void k_query_multi(const ArrayDesc* __restrict__ items,
-                                                    const int64_t* __restrict__ q_prefix,
-                                                    int count,
-                                                    unsigned long long* __restrict__ bad_count,
-                                                    unsigned long long* __restrict__ stats) {
-  const int64_t g = (int64_t)blockIdx.x * WG + threadIdx.x;
-  const int64_t total = q_prefix[count];
-  const bool live = g < total;
-  const int64_t gw = (int64_t)blockIdx.x * WG + (threadIdx.x & ~63);  // the wave's first query
-  const int j = find_item_wave(q_prefix, count, gw < total ? gw : total - 1, live ? g : gw);
-  const ArrayDesc& d = items[j];
-  const int64_t i = live ? g - q_prefix[j] : 0;
+// Queries of a batch: wave w does job w, 64 consecutive queries of one
+// array (each array's queries padded to whole waves, so a wave never spans
+// two arrays).  Every array of a launch has two block levels (Src = SrcA2)
+// or none (SrcA).
+template <class Src>
+__device__ __forceinline__ Src array_src(const ArrayDesc& d);
+template <>
+__device__ __forceinline__ SrcA array_src<SrcA>(const ArrayDesc& d) {
+  return SrcA{d.A, d.n};
+}
+template <>
+__device__ __forceinline__ SrcA2 array_src<SrcA2>(const ArrayDesc& d) {
+  return SrcA2{SrcA{d.A, d.n}, d.sub, d.nb1, d.k1shift};
+}
+
+template <class Src>
+__global__ __launch_bounds__(WG) void k_query_multi(const WaveJob* __restrict__ jobs,
+                                                    int64_t waves) {
+  const int64_t w = (int64_t)blockIdx.x * (WG / 64) +
+                    __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const WaveJob& jb = jobs[w < waves ? w : waves - 1];
+  const ArrayDesc& d = jb.d;
+  const int64_t i = jb.q0 + lane_id();
+  const bool live = w < waves && i < d.q;
   int64_t l = 0, r = -1;
   if (live) {
     l = d.L[i];
     r = d.R[i];
   }
-  query_core(SrcA{d.A, d.n}, d.n, d.n, d.kshift, d.st, d.nb, l, r, l, r, live, d.out + i,
-             bad_count, stats, d.lg, d.rec, d.rlev);
+  query_core(array_src<Src>(d), d.n, d.n, d.kshift, d.st, d.nb, l, r, l, r, live,
+             d.out + (live ? i : 0), nullptr, nullptr, d.lg, d.rec, d.rlev);
 }
 
 // A coalesced batch of requests (serving): queries g in
 // [seg_prefix[s], seg_prefix[s+1]) belong to request s, which targets the
 // resident table tables[seg_table[s]].
+template <class Src>
 __global__ __launch_bounds__(WG) void k_query_segments(const ArrayDesc* __restrict__ tables,
                                                        const int64_t* __restrict__ seg_prefix,
                                                        const int32_t* __restrict__ seg_table,
@@ -508,7 +521,7 @@ __global__ __launch_bounds__(WG) void k_query_segments(const ArrayDesc* __restri
     l = L[g];
     r = R[g];
   }
-  query_core(SrcA{d.A, d.n}, d.n, d.n, d.kshift, d.st, d.nb, l, r, l, r, live,
+  query_core(array_src<Src>(d), d.n, d.n, d.kshift, d.st, d.nb, l, r, l, r, live,
              out + (live ? g : 0), nullptr, nullptr, d.lg, d.rec, d.rlev);
 }
 
@@ -549,12 +562,16 @@ __global__ __launch_bounds__(WG) void k_query_lca(Src src, int64_t len, int kshi
 
 hipError_t launch_query_segments(const ArrayDesc* tables, const int64_t* seg_prefix,
                                  const int32_t* seg_table, int nseg, const int32_t* L,
-                                 const int32_t* R, int32_t* out, int64_t total,
+                                 const int32_t* R, int32_t* out, int64_t total, bool two_level,
                                  hipStream_t stream) {
   if (total <= 0) return hipSuccess;
   const int64_t grid = (total + WG - 1) / WG;
-  RMQ_TRY(launch(k_query_segments, dim3((unsigned)grid), dim3(WG), 0, stream, tables, seg_prefix,
-                 seg_table, nseg, L, R, out));
+  if (two_level)
+    RMQ_TRY(launch(k_query_segments<SrcA2>, dim3((unsigned)grid), dim3(WG), 0, stream, tables,
+                   seg_prefix, seg_table, nseg, L, R, out));
+  else
+    RMQ_TRY(launch(k_query_segments<SrcA>, dim3((unsigned)grid), dim3(WG), 0, stream, tables,
+                   seg_prefix, seg_table, nseg, L, R, out));
   return hipSuccess;
 }
 
@@ -628,13 +645,14 @@ hipError_t launch_query_contracted(const uint64_t* aq, int64_t m, int64_t n, int
   return hipGetLastError();
 }
 
-hipError_t launch_query_multi(const ArrayDesc* items, const int64_t* q_prefix, int count,
-                              int64_t total_q, int64_t* bad_count, uint64_t* stats,
+hipError_t launch_query_multi(const WaveJob* jobs, int64_t waves, bool two_level,
                               hipStream_t stream) {
-  if (total_q <= 0) return hipSuccess;
-  const int64_t grid = (total_q + WG - 1) / WG;
-  RMQ_TRY(launch(k_query_multi, dim3((unsigned)grid), dim3(WG), 0, stream, items, q_prefix, count,
-                 (unsigned long long*)bad_count, (unsigned long long*)stats));
+  if (waves <= 0) return hipSuccess;
+  const int64_t grid = (waves + WG / 64 - 1) / (WG / 64);
+  if (two_level)
+    RMQ_TRY(launch(k_query_multi<SrcA2>, dim3((unsigned)grid), dim3(WG), 0, stream, jobs, waves));
+  else
+    RMQ_TRY(launch(k_query_multi<SrcA>, dim3((unsigned)grid), dim3(WG), 0, stream, jobs, waves));
   return hipSuccess;
 }
 

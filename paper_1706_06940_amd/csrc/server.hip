@@ -136,7 +136,7 @@ hipError_t launch_slot(rmq_server_s* S, int si) {
                                   reinterpret_cast<const int64_t*>(sl.h + S->off_prefix),
                                   reinterpret_cast<const int32_t*>(sl.h + S->off_table), nseg, hq,
                                   hq + total, reinterpret_cast<int32_t*>(sl.h + S->off_out), total,
-                                  sl.stream));
+                                  S->cfg.sub_block_size > 0, sl.stream));
     return hipEventRecord(sl.done, sl.stream);
   }
   const size_t seg_bytes = sizeof(int64_t) * (size_t)(nseg + 1);
@@ -150,7 +150,7 @@ hipError_t launch_slot(rmq_server_s* S, int si) {
   RMQ_TRY(launch_query_segments(S->d_tables, reinterpret_cast<const int64_t*>(sl.d + S->off_prefix),
                                 reinterpret_cast<const int32_t*>(sl.d + S->off_table), nseg, dL,
                                 dL + total, reinterpret_cast<int32_t*>(sl.d + S->off_out), total,
-                                sl.stream));
+                                S->cfg.sub_block_size > 0, sl.stream));
   RMQ_TRY(hipMemcpyAsync(sl.h + S->off_out, sl.d + S->off_out, sizeof(int32_t) * (size_t)total,
                          hipMemcpyDeviceToHost, sl.stream));
   return hipEventRecord(sl.done, sl.stream);
@@ -279,6 +279,9 @@ rmq_status rmq_server_create(const rmq_server_config* cfg, rmq_server* out) {
       cfg->max_requests_per_batch < 1 || cfg->budget_bytes < 4096 ||
       (cfg->flags & ~RMQ_SERVER_COPY_QUERIES) != 0)
     return RMQ_ERR_INVALID_ARG;
+  const int32_t k1 = cfg->sub_block_size;
+  if (k1 != 0 && (k1 < RMQ_MIN_BLOCK || k1 >= RMQ_MAX_BLOCK || (k1 & (k1 - 1)) != 0))
+    return RMQ_ERR_INVALID_ARG;
   rmq_server_s* S = new (std::nothrow) rmq_server_s();
   if (!S) return RMQ_ERR_OUT_OF_MEMORY;
   S->cfg = *cfg;
@@ -332,6 +335,7 @@ rmq_status rmq_server_add_array(rmq_server S, const int32_t* A, int64_t n, int32
   if (!S || !table_id) return RMQ_ERR_INVALID_ARG;
   rmq_options o{};
   o.block_size = block_size;
+  o.sub_block_size = S->cfg.sub_block_size;  // every table of the server alike
   const size_t need = rmq_build_bytes(n, &o);
   if (need == 0) return RMQ_ERR_INVALID_ARG;
   {
@@ -360,8 +364,9 @@ rmq_status rmq_server_add_array(rmq_server S, const int32_t* A, int64_t n, int32
   std::lock_guard<std::mutex> lk(S->mu);
   release();
   if (st != RMQ_OK) return st;
-  const ArrayDesc d{ix->A, ix->n, ix->kshift, ix->levels, ix->nb, ix->st,
-                    nullptr, nullptr, 0, nullptr, ix->lg, ix->rec, ix->levels};
+  const ArrayDesc d{ix->A,    ix->n,   ix->kshift, ix->levels, ix->nb, ix->st,
+                    nullptr,  nullptr, 0,          nullptr,    ix->lg, ix->rec,
+                    ix->levels, ix->sub, ix->nb1,  ix->k1shift};
   const int32_t id = (int32_t)S->tables.size();
   e = hipMemcpy(S->d_tables + id, &d, sizeof(ArrayDesc), hipMemcpyHostToDevice);
   if (e != hipSuccess) {

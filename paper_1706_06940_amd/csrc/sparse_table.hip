@@ -122,18 +122,16 @@ __global__ __launch_bounds__(WG) void k_st_levels(uint64_t* __restrict__ st, int
   st_tile(st, nb, j0, t, R, col_tiles, blockIdx.x, lds);
 }
 
-// Round `round` of every table of a batch: workgroup w works on the table
-// whose range of tiles holds w.
-__global__ __launch_bounds__(WG) void k_st_multi(const ArrayDesc* __restrict__ items,
-                                                 const int64_t* __restrict__ tile_prefix,
-                                                 int count, int j0, int R, int tmax) {
+// Round `round` of every table of a batch: workgroup w does job w, one
+// tile of one table.
+__global__ __launch_bounds__(WG) void k_st_multi(const TileJob* __restrict__ jobs, int j0, int R,
+                                                 int tmax) {
   extern __shared__ uint64_t lds[];
-  const int j = find_item(tile_prefix, count, blockIdx.x);
-  const ArrayDesc& d = items[j];
-  const int t = d.levels - 1 - j0 < tmax ? d.levels - 1 - j0 : tmax;
+  const TileJob jb = jobs[blockIdx.x];
+  const int t = jb.levels - 1 - j0 < tmax ? jb.levels - 1 - j0 : tmax;
   const int64_t s = 1ll << j0;
   const int64_t col_tiles = (s + R - 1) / R;
-  st_tile(d.st, d.nb, j0, t, R, col_tiles, blockIdx.x - tile_prefix[j], lds);
+  st_tile(jb.st, jb.nb, j0, t, R, col_tiles, jb.tile, lds);
 }
 
 // Division of a < 2^31 by a divisor fixed for the launch, d >= 1: with
@@ -316,14 +314,12 @@ hipError_t launch_sparse_table(uint64_t* st, int64_t nb, int levels, hipStream_t
   return hipSuccess;
 }
 
-hipError_t launch_sparse_table_multi(const ArrayDesc* items, const int64_t* tile_prefix,
-                                     int count, int round, int64_t total_tiles,
+hipError_t launch_sparse_table_multi(const TileJob* jobs, int round, int64_t count,
                                      hipStream_t stream) {
-  if (total_tiles <= 0) return hipSuccess;
+  if (count <= 0) return hipSuccess;
   const RoundShape sh = round_shape(round);
-  RMQ_TRY(launch(k_st_multi, dim3((unsigned)total_tiles), dim3(WG),
-                 (uint32_t)st_round_lds(round), stream, items, tile_prefix, count, sh.j0, sh.R,
-                 sh.tmax));
+  RMQ_TRY(launch(k_st_multi, dim3((unsigned)count), dim3(WG), (uint32_t)st_round_lds(round),
+                 stream, jobs, sh.j0, sh.R, sh.tmax));
   return hipSuccess;
 }
 

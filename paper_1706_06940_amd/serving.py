@@ -31,7 +31,8 @@ COPY_QUERIES = 1  # queries and answers through device buffers and the copy engi
 class _Config(ctypes.Structure):
     _fields_ = [("num_streams", ctypes.c_int32), ("max_tables", ctypes.c_int32),
                 ("max_requests_per_batch", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("budget_bytes", ctypes.c_size_t), ("hbm_budget_bytes", ctypes.c_size_t)]
+                ("budget_bytes", ctypes.c_size_t), ("hbm_budget_bytes", ctypes.c_size_t),
+                ("sub_block_size", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -100,13 +101,16 @@ def _host_i32(a: np.ndarray, name: str) -> np.ndarray:
 class Server:
     def __init__(self, num_streams: int = 3, max_tables: int = 64,
                  max_requests_per_batch: int = 1024, budget_bytes: int = 256 << 20,
-                 copy_queries: bool = False, hbm_budget_bytes: int = 0):
+                 copy_queries: bool = False, hbm_budget_bytes: int = 0,
+                 sub_block_size: int = 0):
         """budget_bytes: in-flight query buffers (pinned host memory, and as
         much device memory with copy_queries).  hbm_budget_bytes: device
         memory the resident tables and device buffers may take (0: no
-        limit); add_array refuses a table beyond it."""
+        limit); add_array refuses a table beyond it.  sub_block_size > 0:
+        every table has two block levels (Section 3.3) with that k1."""
         cfg = _Config(num_streams, max_tables, max_requests_per_batch,
-                      COPY_QUERIES if copy_queries else 0, budget_bytes, hbm_budget_bytes)
+                      COPY_QUERIES if copy_queries else 0, budget_bytes, hbm_budget_bytes,
+                      sub_block_size)
         h = ctypes.c_void_p()
         _check("rmq_server_create", _lib().rmq_server_create(ctypes.byref(cfg), ctypes.byref(h)))
         self.handle = h

@@ -119,3 +119,39 @@ def test_batch_equals_plain_calls(orc):
         plain = rmq.query_batch(At[j], Qt[j][0], Qt[j][1])
         assert torch.equal(plain, b.outs[j])
     b.free()
+
+
+@pytest.mark.parametrize("mode", ["fused", "per_item"])
+def test_batch_two_level_items(orc, mode):
+    """Items the planner gives two block levels (Section 3.3) run through the
+    batched k1-block minima, the k-blocks from them and the two-level query
+    launch, beside one-level items; every answer vs the oracle, eagerly and
+    on graph replays."""
+    d = need_gpu()
+    say("batch_two_level", mode)
+    arrays, queries = make_batch(40, 2e3, 3e5, 1, 4e3, 51)
+    # every array near 1e5 elements takes k = 8192 over k1 = 256, near 1e4
+    # one level with k = 256
+    rmq.set_plan_table([(10 ** 5, 10 ** 3, 8192, "full", 256, 512),
+                        (10 ** 4, 10 ** 3, 256, "full")])
+    try:
+        At, Qt = to_dev(arrays, queries, d)
+        b = rmq.Batch(At, Qt)
+        plans = [b.plan_ex(j) for j in range(len(arrays))]
+        two = [j for j, (k, p, k1) in enumerate(plans) if k1 > 0]
+        assert 0 < len(two) < len(arrays)
+        for j in two:
+            k, p, k1 = plans[j]
+            assert p == "full" and k1 == 256 and k == 8192
+        s = torch.cuda.Stream(device=d)
+        for graph in (False, True, True):
+            for o in b.outs:
+                o.fill_(-3)
+            torch.cuda.synchronize()
+            with torch.cuda.stream(s):
+                b.run(mode, graph=graph, stream=s)
+            s.synchronize()
+            check_outs(orc, arrays, queries, b.outs, f"{mode} graph={graph}")
+        b.free()
+    finally:
+        rmq.set_plan_table([])

@@ -111,3 +111,23 @@ def test_admission_and_invalid_queries(orc, copy):
         check(orc, arrays, reqs)
         st = srv.stats()
         assert st["queries"] == sum(r[1].shape[0] for r in reqs)
+
+
+@pytest.mark.parametrize("copy", [False, True])
+def test_two_level_tables_serve_exactly(orc, copy):
+    """Every resident table with two block levels (Section 3.3): coalesced
+    batches answered by the two-level query launch, vs the oracle."""
+    d = need_gpu()
+    say("serve_two_level", copy)
+    arrays = arrays_for(6, 43, 2e4, 4e5)
+    with serving.Server(num_streams=3, max_tables=8, copy_queries=copy,
+                        sub_block_size=256) as srv:
+        for A in arrays:
+            srv.add_array(dev(A, d))
+        reqs = serving.make_requests([a.shape[0] for a in arrays], 200, 1, 6e3, 47)
+        t0 = serving.clock() + 1e-3
+        serving.run_schedule(srv, reqs, serving.poisson_schedule(len(reqs), 1e5, 53, t0))
+        check(orc, arrays, reqs)
+        # the tables hold the k1-block minima beside the block table
+        st = srv.stats()
+        assert st["index_bytes"] == sum(rmq.build_bytes(a.shape[0], 0, 256) for a in arrays)
