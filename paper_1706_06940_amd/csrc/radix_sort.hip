@@ -146,6 +146,10 @@ __device__ __forceinline__ uint64_t finish_item(uint64_t raw, int64_t n, int64_t
 __device__ __forceinline__ uint32_t digit_of(uint64_t item, int shift, uint32_t mask) {
   return ((uint32_t)(item >> 32) >> shift) & mask;
 }
+// The same, with the digit width instead of its mask (one bit-field extract).
+__device__ __forceinline__ uint32_t digit_bits(uint64_t item, int shift, int bits) {
+  return __builtin_amdgcn_ubfe((uint32_t)(item >> 32), (uint32_t)shift, (uint32_t)bits);
+}
 
 constexpr int MAX_PASSES = 4;
 // Tiles per histogram workgroup: one while the grid is small (every tile's
@@ -154,7 +158,10 @@ int hist_tiles(int64_t num_tiles) {
   const int64_t t = num_tiles / 1024;
   return t < 1 ? 1 : (t > 8 ? 8 : (int)t);
 }
-constexpr int LOOKBACK = 4;  // predecessors read per look-back step
+#ifndef RMQ_SORT_LOOKBACK
+#define RMQ_SORT_LOOKBACK 4
+#endif
+constexpr int LOOKBACK = RMQ_SORT_LOOKBACK;  // predecessors read per look-back step
 constexpr uint64_t ST_AGG = 1ull << 62;
 constexpr uint64_t ST_INC = 2ull << 62;
 constexpr uint64_t ST_VAL = (1ull << 62) - 1;
@@ -321,7 +328,7 @@ __device__ __forceinline__ uint64_t same_digit_lanes(uint32_t d, uint64_t valid_
   uint32_t xlo = 0, xhi = 0;
 #pragma unroll
   for (int b = 0; b < BITS; ++b) {
-    const uint32_t x = (uint32_t)((int32_t)(d << (31 - b)) >> 31);  // bit b, spread
+    const uint32_t x = (uint32_t)__builtin_amdgcn_sbfe((int32_t)d, b, 1);  // bit b, spread
     const uint64_t m = ballot(x != 0);
     xlo |= (uint32_t)m ^ x;
     xhi |= (uint32_t)(m >> 32) ^ x;
@@ -354,9 +361,13 @@ __device__ __forceinline__ void os_pass(const uint64_t* __restrict__ items_in,
                                         int32_t* __restrict__ LR, uint64_t* __restrict__ pairs,
                                         uint16_t* __restrict__ pre, int nwin) {
   constexpr int TILE = WG * ROUNDS;
-  __shared__ uint32_t wave_cnt[WG / 64][RADIX];
-  __shared__ uint32_t local_start[RADIX];
-  __shared__ uint32_t global_start[RADIX];
+  // per wave and digit: the wave's count, then the tile-local slot of its
+  // first item of that digit
+  // (16 bits: a tile has fewer than 2^16 items, so that a workgroup over a
+  // large tile takes under half of a CU's LDS and two share a CU)
+  __shared__ uint16_t wave_cnt[WG / 64][RADIX];
+  // per digit: global slot minus tile-local slot of the digit's items
+  __shared__ uint32_t shift_to_global[RADIX];
   __shared__ uint32_t tmp[WG / 64];
   __shared__ uint64_t s_item[TILE];
   __shared__ uint32_t s_tile;
@@ -381,32 +392,72 @@ __device__ __forceinline__ void os_pass(const uint64_t* __restrict__ items_in,
   if (status_next) status_next[tile * RADIX + threadIdx.x] = 0;  // for the next pass
 
   // this wave's items: tile0 + wave * 64 * ROUNDS + round * 64 + lane, the
-  // first nval of them inside the list
+  // first nval of them inside the list (all of them but in the last tile)
   const int64_t wbase = tile0 + (int64_t)wave * (64 * ROUNDS);
-  const int nval = N - wbase <= 0 ? 0 : (N - wbase >= 64 * ROUNDS ? 64 * ROUNDS : (int)(N - wbase));
-  uint64_t item[ROUNDS];
+  const bool full = tile0 + TILE <= N;  // workgroup-uniform
+  const int nval = full ? 64 * ROUNDS
+                        : (N - wbase <= 0 ? 0
+                                          : (N - wbase >= 64 * ROUNDS ? 64 * ROUNDS
+                                                                      : (int)(N - wbase)));
+  // the items (position << 32 | tag); from the queries (first pass) the tag
+  // is the item's own index, so only the positions are kept
+  constexpr bool FROM_Q = MODE == QUERIES;
+  uint64_t item[FROM_Q ? 1 : ROUNDS];
+  uint32_t qpos[FROM_Q ? ROUNDS : 1];
+  auto key_hi = [&](int rd) -> uint32_t {
+    if constexpr (FROM_Q) return qpos[rd];
+    else return (uint32_t)(item[rd] >> 32);
+  };
+  auto item_at = [&](int rd) -> uint64_t {
+    if constexpr (FROM_Q)
+      return ((uint64_t)qpos[rd] << 32) | (uint32_t)(wbase + rd * 64 + lane);
+    else return item[rd];
+  };
   uint32_t rank[ROUNDS];
-  // all loads of the tile first, so they are in flight together
+  // all loads of the tile first, so they are in flight together (a full
+  // tile reads at fixed offsets from one base, no index clamping)
+  if constexpr (FROM_Q) {
+    if (full) {
+      // item j = wbase + 64 rd + lane is an end of query j / 2 (wbase even)
+      const int32_t* src = ((lane & 1) ? R : L) + (wbase >> 1) + (lane >> 1);
 #pragma unroll
-  for (int rd = 0; rd < ROUNDS; ++rd)
-    item[rd] = load_raw<MODE>(items_in, L, R, N, wbase + rd * 64 + lane);
+      for (int rd = 0; rd < ROUNDS; ++rd) qpos[rd] = (uint32_t)src[rd * 32];
+    } else {
 #pragma unroll
-  for (int rd = 0; rd < ROUNDS; ++rd)
-    item[rd] = finish_item<MODE>(item[rd], n, wbase + rd * 64 + lane);
+      for (int rd = 0; rd < ROUNDS; ++rd)
+        qpos[rd] = (uint32_t)load_raw<MODE>(items_in, L, R, N, wbase + rd * 64 + lane);
+    }
+#pragma unroll
+    for (int rd = 0; rd < ROUNDS; ++rd)
+      qpos[rd] = (uint32_t)(finish_item<MODE>(qpos[rd], n, wbase + rd * 64 + lane) >> 32);
+  } else {
+    if (full) {
+      const uint64_t* src = items_in + wbase + lane;
+#pragma unroll
+      for (int rd = 0; rd < ROUNDS; ++rd) item[rd] = src[rd * 64];
+    } else {
+#pragma unroll
+      for (int rd = 0; rd < ROUNDS; ++rd)
+        item[rd] = load_raw<MODE>(items_in, L, R, N, wbase + rd * 64 + lane);
+    }
+#pragma unroll
+    for (int rd = 0; rd < ROUNDS; ++rd)
+      item[rd] = finish_item<MODE>(item[rd], n, wbase + rd * 64 + lane);
+  }
 #pragma unroll
   for (int rd = 0; rd < ROUNDS; ++rd) {
-    const bool valid = rd * 64 + lane < nval;
-    const uint32_t d = digit_of(item[rd], shift, mask);
+    const uint32_t d = __builtin_amdgcn_ubfe(key_hi(rd), (uint32_t)shift, (uint32_t)bits);
     // lanes holding digit d: those whose every digit bit equals this lane's,
     // i.e. outside the OR over the bits of (ballot of the bit) XOR (own bit
     // spread over the word); bits above `bits` are zero in every lane and
     // add nothing
-    const uint64_t match = same_digit_lanes<BITS>(d, ballot(valid));
+    const uint64_t match =
+        same_digit_lanes<BITS>(d, full ? ~0ull : ballot(rd * 64 + lane < nval));
     const uint32_t before = wave_cnt[wave][d];
     rank[rd] = before + (uint32_t)__popcll(match & lt);
     // every lane of a digit group stores the same new count (an invalid
     // lane's group holds the valid lanes of its digit, or none)
-    wave_cnt[wave][d] = before + (uint32_t)__popcll(match);
+    wave_cnt[wave][d] = (uint16_t)(before + (uint32_t)__popcll(match));
   }
   __syncthreads();
 
@@ -418,7 +469,7 @@ __device__ __forceinline__ void os_pass(const uint64_t* __restrict__ items_in,
 #pragma unroll
   for (int w = 0; w < WG / 64; ++w) {
     const uint32_t c = wave_cnt[w][d];
-    wave_cnt[w][d] = run;
+    wave_cnt[w][d] = (uint16_t)run;
     run += c;
   }
   uint64_t* mine = status + tile * RADIX + d;
@@ -426,25 +477,24 @@ __device__ __forceinline__ void os_pass(const uint64_t* __restrict__ items_in,
   // publish nor look back (no tile ever reads those words)
   const bool used_digit = d <= (int)mask;
   if (used_digit) store_status(mine, (tile == 0 ? ST_INC : ST_AGG) | run);
-  {
-    uint32_t excl;
-    block_exclusive_scan(run, tmp, excl);
-    local_start[d] = excl;
-  }
+  uint32_t local_start;  // tile-local slot of digit d's first item
+  block_exclusive_scan(run, tmp, local_start);
+#pragma unroll
+  for (int w = 0; w < WG / 64; ++w) wave_cnt[w][d] = (uint16_t)(wave_cnt[w][d] + local_start);
   __syncthreads();
 #pragma unroll
   for (int rd = 0; rd < ROUNDS; ++rd) {
-    if (rd * 64 + lane < nval) {
-      const uint32_t dd = digit_of(item[rd], shift, mask);
-      const uint32_t lp = local_start[dd] + wave_cnt[wave][dd] + rank[rd];
-      if (lp < (uint32_t)TILE) s_item[lp] = item[rd];  // always true for consistent ranks
+    if (full || rd * 64 + lane < nval) {
+      const uint32_t dd = __builtin_amdgcn_ubfe(key_hi(rd), (uint32_t)shift, (uint32_t)bits);
+      const uint32_t lp = wave_cnt[wave][dd] + rank[rd];
+      if (lp < (uint32_t)TILE) s_item[lp] = item_at(rd);  // always true for consistent ranks
     }
   }
 
   // digit d's count in all earlier tiles
   const uint64_t before = tile > 0 && used_digit ? look_back(status, tile, d, abort_word) : 0;
   if (tile > 0 && used_digit) store_status(mine, ST_INC | (before + run));
-  global_start[d] = digit_base + (uint32_t)before;
+  shift_to_global[d] = digit_base + (uint32_t)before - local_start;
   __syncthreads();
 
   const int64_t tile_n = N - tile0 < TILE ? N - tile0 : TILE;
@@ -452,8 +502,7 @@ __device__ __forceinline__ void os_pass(const uint64_t* __restrict__ items_in,
   if (!WINDOWS) {
     for (int t = threadIdx.x; t < tile_n; t += WG) {
       const uint64_t x = s_item[t];
-      const uint32_t dd = digit_of(x, shift, mask);
-      const uint32_t dst = global_start[dd] + (uint32_t)t - local_start[dd];
+      const uint32_t dst = shift_to_global[digit_bits(x, shift, bits)] + (uint32_t)t;
       if ((int64_t)dst < N) {  // always true for consistent counts
         if (LR) {
           // last pass of the endpoint sort: the remap, LR[tag] = slot
@@ -480,8 +529,7 @@ __device__ __forceinline__ void os_pass(const uint64_t* __restrict__ items_in,
     pr_at[i] = TILE;
     if (t >= tile_n) continue;
     const uint64_t x = s_item[t];
-    const uint32_t dd = digit_of(x, shift, mask);
-    const uint32_t dst = global_start[dd] + (uint32_t)t - local_start[dd];
+    const uint32_t dst = shift_to_global[digit_bits(x, shift, bits)] + (uint32_t)t;
     if ((int64_t)dst >= N) continue;  // never, for consistent counts
     pos_out[dst] = (int32_t)(x >> 32);  // the position alone (the tag is used up)
     const uint32_t g = (uint32_t)x;
@@ -528,8 +576,9 @@ __device__ __forceinline__ void os_pass(const uint64_t* __restrict__ items_in,
   }
 }
 
+// (at most 128 VGPRs: two 8-wave workgroups share a CU, with their LDS)
 template <int MODE, int ROUNDS, int BITS>
-__global__ __launch_bounds__(WG) void k_os_pass(const uint64_t* __restrict__ items_in,
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) void k_os_pass(const uint64_t* __restrict__ items_in,
                                                 const int32_t* __restrict__ L,
                                                 const int32_t* __restrict__ R, int64_t N,
                                                 int64_t n, int shift, int bits,
@@ -568,7 +617,7 @@ hipError_t launch_pass(dim3 grid, hipStream_t stream, int bits, const uint64_t* 
 // LR windows.  Its own kernel, so that the registers the pairs take do not
 // lower the occupancy of the other passes.
 template <int MODE, int BITS>
-__global__ __launch_bounds__(WG) void k_os_pass_windows(
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) void k_os_pass_windows(
     const uint64_t* __restrict__ items_in, const int32_t* __restrict__ L,
     const int32_t* __restrict__ R, int64_t N, int64_t n, int shift, int bits,
     const uint32_t* __restrict__ hist, uint64_t* status, uint32_t* ticket, uint32_t* abort_word,
