@@ -8,15 +8,19 @@
 //
 // One sweep per digit of the position (ceil(log2 n) bits in all):
 //   k_os_clear  -- clears digit totals, tickets and the first status words;
-//   k_os_hist   -- one read of the input: digit totals of every pass at once
-//                  (per workgroup in LDS, then global atomics);
+//   k_os_hist   -- one read of the input: digit totals of every pass at once,
+//                  by range of tiles (per workgroup in LDS, then global
+//                  atomics);
 //   k_os_pass   -- per pass, one workgroup (one thread per digit value) per
-//                  tile of 1024, 2048 or 8192 items (by list length), tiles
-//                  taken in order from an atomic ticket.  The tile ranks its items
-//                  stably (one wave ballot per digit bit gives the lanes that
-//                  share a digit), publishes its per-digit counts at once,
-//                  stages the tile in LDS in digit order, and meanwhile finds
-//                  the number of same-digit items in all earlier tiles by a
+//                  tile of 1024, 2048 or 8192 items (by list length), taken
+//                  in order from an atomic ticket (in the first pass, the
+//                  tiles form 8 ranges of contiguous tiles with a ticket
+//                  each).  The tile ranks its items stably (one wave ballot
+//                  per digit bit gives the lanes that share a digit),
+//                  publishes its per-digit counts at once, stages the tile in
+//                  LDS in digit order, and meanwhile finds the number of
+//                  same-digit items in the earlier tiles (of its range; the
+//                  earlier ranges' counts come from the histogram) by a
 //                  decoupled look-back over their published words (count +
 //                  "aggregate" or "inclusive" flag in one 64-bit word, read
 //                  four predecessors at a time).  It then writes runs of
@@ -152,6 +156,38 @@ __device__ __forceinline__ uint32_t digit_bits(uint64_t item, int shift, int bit
 }
 
 constexpr int MAX_PASSES = 4;
+// Copies of the digit totals, one per range of tiles (below): a histogram
+// workgroup adds into the copy of the range its tiles lie in, and a pass
+// sums the copies.  Device-scope atomics on one address are serialised;
+// with a single copy every address takes one add per workgroup (1221 of
+// them at 2e7 items) and the adds, not the reads, set the histogram's time
+// (38 us against 26 us with 8 copies at 2e7 items).
+constexpr int HCOPIES = 8;
+constexpr int HSTRIDE = MAX_PASSES * RADIX;  // words between copies
+// The first pass's tiles form CHAINS ranges of contiguous tiles, each with
+// its own ticket counter and its own look-back: range x (tiles
+// x * range_tiles ..) is taken by the workgroups with blockIdx % CHAINS ==
+// x, and its items of digit d start after those of every earlier range, a
+// count the histogram gives by range (copy x of the totals holds range x's).
+// With one chain over all tiles a tile's look-back walks back about 28
+// tiles (7 reads of four predecessors, ~0.9 us each, at 2e7 items): the
+// nearest tile with an inclusive count is as far back as the tiles issued
+// meanwhile, and with eight chains each issues an eighth of them.  The
+// later passes read the previous pass's output, whose per-range digit
+// counts nothing has counted, so they run as one chain.
+constexpr int CHAINS = HCOPIES;
+struct Chains {
+  uint32_t* tickets;    // nchains counters of this pass
+  int64_t range_tiles;  // tiles per range (a multiple of the histogram's tiles per group)
+  int64_t num_tiles;
+  int nchains;          // CHAINS in the first pass, else 1 (range_tiles = num_tiles)
+};
+Chains first_pass_chains(uint32_t* tickets, int64_t range_tiles, int64_t num_tiles) {
+  return Chains{tickets, range_tiles, num_tiles, CHAINS};
+}
+Chains one_chain(uint32_t* tickets, int64_t num_tiles) {
+  return Chains{tickets, num_tiles, num_tiles, 1};
+}
 // Tiles per histogram workgroup: one while the grid is small (every tile's
 // loads then start at once), up to 8 for long lists (fewer global atomics).
 int hist_tiles(int64_t num_tiles) {
@@ -210,21 +246,23 @@ __global__ __launch_bounds__(WG) void k_os_clear(uint32_t* __restrict__ hist,
   const int64_t i0 = (int64_t)blockIdx.x * WG + threadIdx.x;
   if (blockIdx.x == 0) {
 #pragma unroll
-    for (int p = 0; p < MAX_PASSES; ++p) hist[p * RADIX + threadIdx.x] = 0;
-    if (threadIdx.x < MAX_PASSES) tickets[threadIdx.x] = 0;
+    for (int p = 0; p < HCOPIES * MAX_PASSES; ++p) hist[p * RADIX + threadIdx.x] = 0;
+    if (threadIdx.x < CHAINS + MAX_PASSES) tickets[threadIdx.x] = 0;
     if (threadIdx.x == 0) *abort_word = preset;
   }
   for (int64_t i = i0; i < status_words; i += (int64_t)gridDim.x * WG) status0[i] = 0;
 }
 
 // Digit totals of every pass: per-wave counts in LDS over per_group tiles
-// (the four waves do not contend for one set of counters), summed per
-// workgroup, then one global atomic add per digit.
+// (pairs of waves share a set of counters), summed per workgroup, then one
+// global atomic add per digit into the copy of the group's range.  From the queries,
+// a whole tile of 16-byte aligned L and R is read four queries per load.
 template <int MODE, int ROUNDS>
 __global__ __launch_bounds__(WG) void k_os_hist(const uint64_t* __restrict__ items_in,
                                                 const int32_t* __restrict__ L,
                                                 const int32_t* __restrict__ R, int64_t N,
                                                 int64_t n, Digits dg, int per_group,
+                                                int64_t range_tiles,
                                                 uint32_t* __restrict__ hist) {
   constexpr int TILE = WG * ROUNDS;
   constexpr int HSETS = 4;  // counter sets, one per pair of waves
@@ -235,9 +273,39 @@ __global__ __launch_bounds__(WG) void k_os_hist(const uint64_t* __restrict__ ite
 #pragma unroll
     for (int p = 0; p < MAX_PASSES; ++p) h[w][p][threadIdx.x] = 0;
   __syncthreads();
+  auto count = [&](uint64_t item) {
+#pragma unroll
+    for (int p = 0; p < MAX_PASSES; ++p)
+      if (p < dg.passes) atomicAdd(&h[hs][p][digit_bits(item, dg.shift[p], dg.bits[p])], 1u);
+  };
+  const bool vec = MODE == QUERIES && ROUNDS % 8 == 0 && (((uintptr_t)L | (uintptr_t)R) & 15) == 0;
   for (int t = 0; t < per_group; ++t) {
     const int64_t tile0 = ((int64_t)blockIdx.x * per_group + t) * TILE;
     if (tile0 >= N) break;
+    if constexpr (MODE == QUERIES && ROUNDS % 8 == 0) {
+      if (vec && tile0 + TILE <= N) {
+        // queries tile0/2 .. (tile0 + TILE)/2 - 1, four per thread and step
+        constexpr int STEPS = ROUNDS / 8;
+        const int64_t q0 = tile0 >> 1;
+        v4i32 l[STEPS], r[STEPS];
+#pragma unroll
+        for (int st = 0; st < STEPS; ++st) {
+          const int64_t qi = q0 + (int64_t)st * (WG * 4) + threadIdx.x * 4;
+          l[st] = *reinterpret_cast<const v4i32*>(L + qi);
+          r[st] = *reinterpret_cast<const v4i32*>(R + qi);
+        }
+#pragma unroll
+        for (int st = 0; st < STEPS; ++st)
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const int32_t lo = l[st][k], hi = r[st][k];
+            const bool ok = 0 <= lo && lo <= hi && (int64_t)hi < n;  // as finish_item
+            count((uint64_t)(ok ? (uint32_t)lo : 0u) << 32);
+            count((uint64_t)(ok ? (uint32_t)hi : 0u) << 32);
+          }
+        continue;
+      }
+    }
     uint64_t it[ROUNDS];
 #pragma unroll
     for (int rd = 0; rd < ROUNDS; ++rd)
@@ -247,17 +315,17 @@ __global__ __launch_bounds__(WG) void k_os_hist(const uint64_t* __restrict__ ite
       it[rd] = finish_item<MODE>(it[rd], n, item_index<ROUNDS>(tile0, wave, rd, lane));
 #pragma unroll
     for (int rd = 0; rd < ROUNDS; ++rd) {
-      if (item_index<ROUNDS>(tile0, wave, rd, lane) < N)
-        for (int p = 0; p < dg.passes; ++p)
-          atomicAdd(&h[hs][p][digit_of(it[rd], dg.shift[p], (1u << dg.bits[p]) - 1u)], 1u);
+      if (item_index<ROUNDS>(tile0, wave, rd, lane) < N) count(it[rd]);
     }
   }
   __syncthreads();
+  // the copy of the range holding this group's tiles
+  uint32_t* mine = hist + (((int64_t)blockIdx.x * per_group) / range_tiles) * HSTRIDE;
   for (int p = 0; p < dg.passes; ++p) {
     uint32_t c = 0;
 #pragma unroll
     for (int w = 0; w < HSETS; ++w) c += h[w][p][threadIdx.x];
-    if (c) atomicAdd(&hist[p * RADIX + threadIdx.x], c);
+    if (c) atomicAdd(&mine[p * RADIX + threadIdx.x], c);
   }
 }
 
@@ -280,14 +348,15 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* t
 }
 
 // Decoupled look-back for digit d of `tile`: the number of digit-d items in
-// all earlier tiles.  Reads LOOKBACK predecessors' words at once, newest
-// first, and takes values up to the first inclusive one, or stops at an
-// unpublished one and reads again.  A tile only waits on tiles that took
+// the earlier tiles of its range (`first` .. tile - 1; tile `first`
+// publishes an inclusive word at once).  Reads LOOKBACK predecessors' words
+// at once, newest first, and takes values up to the first inclusive one, or
+// stops at an unpublished one and reads again.  A tile only waits on tiles that took
 // their ticket earlier; the wait is bounded, and an exceeded bound (or an
 // abort word already set) ends it with a partial count and sets the abort
 // word, which ends every other wait at once.
-__device__ __forceinline__ uint64_t look_back(const uint64_t* status, int64_t tile, int d,
-                                              uint32_t* abort_word) {
+__device__ __forceinline__ uint64_t look_back(const uint64_t* status, int64_t tile,
+                                              int64_t first, int d, uint32_t* abort_word) {
   uint64_t before = 0;
   int64_t j = tile - 1;
   uint32_t spins = 0;
@@ -295,7 +364,7 @@ __device__ __forceinline__ uint64_t look_back(const uint64_t* status, int64_t ti
     uint64_t w[LOOKBACK];
 #pragma unroll
     for (int i = 0; i < LOOKBACK; ++i)
-      w[i] = j - i >= 0 ? load_status(status + (j - i) * RADIX + d) : 0;
+      w[i] = j - i >= first ? load_status(status + (j - i) * RADIX + d) : 0;
     bool done = false;
     int used = 0;
 #pragma unroll
@@ -356,7 +425,7 @@ __device__ __forceinline__ void os_pass(const uint64_t* __restrict__ items_in,
                                         const int32_t* __restrict__ R, int64_t N, int64_t n,
                                         int shift, int bits, const uint32_t* __restrict__ hist,
                                         uint64_t* status, uint64_t* status_next,
-                                        uint32_t* ticket, uint32_t* abort_word,
+                                        Chains ch, uint32_t* abort_word,
                                         uint64_t* __restrict__ items_out,
                                         int32_t* __restrict__ LR, uint64_t* __restrict__ pairs,
                                         uint16_t* __restrict__ pre, int nwin) {
@@ -374,21 +443,35 @@ __device__ __forceinline__ void os_pass(const uint64_t* __restrict__ items_in,
   __shared__ uint32_t s_wcnt[WINDOWS ? MAX_WINDOWS : 1];  // pairs per window, then offsets
 
   const int lane = lane_id(), wave = threadIdx.x >> 6;
-  const uint32_t total = hist[threadIdx.x];  // in flight with the ticket
-  if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
+  const int chain = (int)(blockIdx.x % (unsigned)ch.nchains);
+  if (threadIdx.x == 0) s_tile = atomicAdd(ch.tickets + chain, 1u);
+  // the digit's total, and its items in the earlier ranges
+  uint32_t total = 0, below = 0;
+#pragma unroll
+  for (int c = 0; c < HCOPIES; ++c) {
+    const uint32_t h = hist[c * HSTRIDE + threadIdx.x];
+    total += h;
+    below += c < chain ? h : 0u;
+  }
 #pragma unroll
   for (int w = 0; w < WG / 64; ++w) wave_cnt[w][threadIdx.x] = 0;
   if (WINDOWS) {
 #pragma unroll
     for (int i = 0; i < MAX_WINDOWS / WG; ++i) s_wcnt[i * WG + threadIdx.x] = 0;
   }
-  // digit offsets of this pass: exclusive scan of the digit totals
+  // digit offsets of this pass: exclusive scan of the digit totals, plus
+  // the digit's items in the earlier ranges
   uint32_t digit_base;
   block_exclusive_scan(total, tmp, digit_base);
-  const int64_t tile = s_tile;  // tiles in the order workgroups started
+  digit_base += below;
+  // tiles of a range in the order its workgroups started
+  const int64_t first = (int64_t)chain * ch.range_tiles;
+  const int64_t tile = first + (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)s_tile);
+  const int64_t range_end = first + ch.range_tiles < ch.num_tiles ? first + ch.range_tiles
+                                                                   : ch.num_tiles;
+  if (tile >= range_end) return;  // the whole workgroup: a padding ticket
   const int64_t tile0 = tile * TILE;
   const uint32_t mask = (1u << bits) - 1u;
-  const uint64_t lt = (1ull << lane) - 1ull;
   if (status_next) status_next[tile * RADIX + threadIdx.x] = 0;  // for the next pass
 
   // this wave's items: tile0 + wave * 64 * ROUNDS + round * 64 + lane, the
@@ -399,24 +482,27 @@ __device__ __forceinline__ void os_pass(const uint64_t* __restrict__ items_in,
                         : (N - wbase <= 0 ? 0
                                           : (N - wbase >= 64 * ROUNDS ? 64 * ROUNDS
                                                                       : (int)(N - wbase)));
-  // the items (position << 32 | tag); from the queries (first pass) the tag
-  // is the item's own index, so only the positions are kept
-  constexpr bool FROM_Q = MODE == QUERIES;
-  uint64_t item[FROM_Q ? 1 : ROUNDS];
-  uint32_t qpos[FROM_Q ? ROUNDS : 1];
-  auto key_hi = [&](int rd) -> uint32_t {
-    if constexpr (FROM_Q) return qpos[rd];
-    else return (uint32_t)(item[rd] >> 32);
-  };
+  // the items (position << 32 | tag) as positions in registers and tags:
+  // from the queries or a list's tags the tag is the item's own index; the
+  // tags of general items wait in the first half of s_item while the tile
+  // is ranked (in registers they pushed the kernel past its register
+  // budget) and come back before it is staged
+  constexpr bool OWN_TAG = MODE != ITEMS;
+  uint32_t qpos[ROUNDS];
+  uint32_t tag[OWN_TAG ? 1 : ROUNDS];
+  uint32_t* const s_tag = reinterpret_cast<uint32_t*>(s_item) + wave * (64 * ROUNDS) + lane;
+  auto key_hi = [&](int rd) -> uint32_t { return qpos[rd]; };
   auto item_at = [&](int rd) -> uint64_t {
-    if constexpr (FROM_Q)
+    if constexpr (OWN_TAG)
       return ((uint64_t)qpos[rd] << 32) | (uint32_t)(wbase + rd * 64 + lane);
-    else return item[rd];
+    else return ((uint64_t)qpos[rd] << 32) | tag[rd];
   };
-  uint32_t rank[ROUNDS];
+  // each item's rank among the wave's items of its digit so far (below
+  // 2^16: two to a register, so that the items stay in registers)
+  uint32_t rank2[(ROUNDS + 1) / 2];
   // all loads of the tile first, so they are in flight together (a full
   // tile reads at fixed offsets from one base, no index clamping)
-  if constexpr (FROM_Q) {
+  if constexpr (MODE == QUERIES) {
     if (full) {
       // item j = wbase + 64 rd + lane is an end of query j / 2 (wbase even)
       const int32_t* src = ((lane & 1) ? R : L) + (wbase >> 1) + (lane >> 1);
@@ -431,18 +517,26 @@ __device__ __forceinline__ void os_pass(const uint64_t* __restrict__ items_in,
     for (int rd = 0; rd < ROUNDS; ++rd)
       qpos[rd] = (uint32_t)(finish_item<MODE>(qpos[rd], n, wbase + rd * 64 + lane) >> 32);
   } else {
-    if (full) {
-      const uint64_t* src = items_in + wbase + lane;
+    // the wave's items through one buffer resource over its part of the
+    // list: reads past the list's end return zero, so full and partial
+    // tiles take the same loads, each a lane offset plus a constant from one
+    // scalar base (per-load 64-bit addresses pushed the kernel past its
+    // register budget)
+    const int64_t wuni = tile0 + (int64_t)__builtin_amdgcn_readfirstlane(wave) * (64 * ROUNDS);
+    const int64_t wlen = N - wuni;
+    const int bytes = wlen <= 0 ? 0 : (wlen >= 64 * ROUNDS ? 64 * ROUNDS * 8 : (int)wlen * 8);
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint64_t*>(items_in + (wlen > 0 ? wuni : 0)), (short)0, bytes, 0x00020000);
 #pragma unroll
-      for (int rd = 0; rd < ROUNDS; ++rd) item[rd] = src[rd * 64];
-    } else {
-#pragma unroll
-      for (int rd = 0; rd < ROUNDS; ++rd)
-        item[rd] = load_raw<MODE>(items_in, L, R, N, wbase + rd * 64 + lane);
+    for (int rd = 0; rd < ROUNDS; ++rd) {
+      const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, lane * 8, rd * 512, 0);
+      if constexpr (MODE == E_TAGS) {
+        qpos[rd] = v[0];  // the list's low half becomes the key
+      } else {
+        qpos[rd] = v[1];
+        s_tag[rd * 64] = v[0];
+      }
     }
-#pragma unroll
-    for (int rd = 0; rd < ROUNDS; ++rd)
-      item[rd] = finish_item<MODE>(item[rd], n, wbase + rd * 64 + lane);
   }
 #pragma unroll
   for (int rd = 0; rd < ROUNDS; ++rd) {
@@ -454,7 +548,11 @@ __device__ __forceinline__ void os_pass(const uint64_t* __restrict__ items_in,
     const uint64_t match =
         same_digit_lanes<BITS>(d, full ? ~0ull : ballot(rd * 64 + lane < nval));
     const uint32_t before = wave_cnt[wave][d];
-    rank[rd] = before + (uint32_t)__popcll(match & lt);
+    // + this lane's predecessors in the group (set bits of match below it)
+    const uint32_t r = before + __builtin_amdgcn_mbcnt_hi(
+                                    (uint32_t)(match >> 32),
+                                    __builtin_amdgcn_mbcnt_lo((uint32_t)match, 0u));
+    rank2[rd >> 1] = (rd & 1) ? (rank2[rd >> 1] | (r << 16)) : r;
     // every lane of a digit group stores the same new count (an invalid
     // lane's group holds the valid lanes of its digit, or none)
     wave_cnt[wave][d] = (uint16_t)(before + (uint32_t)__popcll(match));
@@ -472,28 +570,37 @@ __device__ __forceinline__ void os_pass(const uint64_t* __restrict__ items_in,
     wave_cnt[w][d] = (uint16_t)run;
     run += c;
   }
-  uint64_t* mine = status + tile * RADIX + d;
+  // this tile's row of status words (a wave-uniform base; digit d's word
+  // is row[d], a 32-bit offset, so that no 64-bit address stays live)
+  uint64_t* const row = status + tile * RADIX;
   // digits at or above 2^bits occur in no item: their threads neither
   // publish nor look back (no tile ever reads those words)
   const bool used_digit = d <= (int)mask;
-  if (used_digit) store_status(mine, (tile == 0 ? ST_INC : ST_AGG) | run);
+  if (used_digit) store_status(row + d, (tile == first ? ST_INC : ST_AGG) | run);
   uint32_t local_start;  // tile-local slot of digit d's first item
   block_exclusive_scan(run, tmp, local_start);
 #pragma unroll
   for (int w = 0; w < WG / 64; ++w) wave_cnt[w][d] = (uint16_t)(wave_cnt[w][d] + local_start);
+  if constexpr (!OWN_TAG) {
+    // back from LDS; the barrier below separates these reads from the
+    // staging stores into s_item
+#pragma unroll
+    for (int rd = 0; rd < ROUNDS; ++rd) tag[rd] = s_tag[rd * 64];
+  }
   __syncthreads();
 #pragma unroll
   for (int rd = 0; rd < ROUNDS; ++rd) {
     if (full || rd * 64 + lane < nval) {
       const uint32_t dd = __builtin_amdgcn_ubfe(key_hi(rd), (uint32_t)shift, (uint32_t)bits);
-      const uint32_t lp = wave_cnt[wave][dd] + rank[rd];
+      const uint32_t lp = wave_cnt[wave][dd] + ((rank2[rd >> 1] >> ((rd & 1) * 16)) & 0xFFFFu);
       if (lp < (uint32_t)TILE) s_item[lp] = item_at(rd);  // always true for consistent ranks
     }
   }
 
   // digit d's count in all earlier tiles
-  const uint64_t before = tile > 0 && used_digit ? look_back(status, tile, d, abort_word) : 0;
-  if (tile > 0 && used_digit) store_status(mine, ST_INC | (before + run));
+  const uint64_t before =
+      tile > first && used_digit ? look_back(status, tile, first, d, abort_word) : 0;
+  if (tile > first && used_digit) store_status(row + d, ST_INC | (before + run));
   shift_to_global[d] = digit_base + (uint32_t)before - local_start;
   __syncthreads();
 
@@ -584,11 +691,11 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) void k_
                                                 int64_t n, int shift, int bits,
                                                 const uint32_t* __restrict__ hist,
                                                 uint64_t* status, uint64_t* status_next,
-                                                uint32_t* ticket, uint32_t* abort_word,
+                                                Chains ch, uint32_t* abort_word,
                                                 uint64_t* __restrict__ items_out,
                                                 int32_t* __restrict__ LR) {
   os_pass<MODE, ROUNDS, false, BITS>(items_in, L, R, N, n, shift, bits, hist, status,
-                                     status_next, ticket, abort_word, items_out, LR, nullptr,
+                                     status_next, ch, abort_word, items_out, LR, nullptr,
                                      nullptr, 1);
 }
 
@@ -598,18 +705,18 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) void k_
 template <int MODE, int ROUNDS>
 hipError_t launch_pass(dim3 grid, hipStream_t stream, int bits, const uint64_t* in,
                        const int32_t* L, const int32_t* R, int64_t N, int64_t n, int shift,
-                       const uint32_t* hist, uint64_t* st, uint64_t* st_next, uint32_t* ticket,
+                       const uint32_t* hist, uint64_t* st, uint64_t* st_next, Chains ch,
                        uint32_t* abort_word, uint64_t* dst, int32_t* lr) {
   switch (bits) {
     case RADIX_BITS - 2:
       return launch(k_os_pass<MODE, ROUNDS, RADIX_BITS - 2>, grid, dim3(WG), 0, stream, in, L, R,
-                    N, n, shift, bits, hist, st, st_next, ticket, abort_word, dst, lr);
+                    N, n, shift, bits, hist, st, st_next, ch, abort_word, dst, lr);
     case RADIX_BITS - 1:
       return launch(k_os_pass<MODE, ROUNDS, RADIX_BITS - 1>, grid, dim3(WG), 0, stream, in, L, R,
-                    N, n, shift, bits, hist, st, st_next, ticket, abort_word, dst, lr);
+                    N, n, shift, bits, hist, st, st_next, ch, abort_word, dst, lr);
     default:
       return launch(k_os_pass<MODE, ROUNDS, RADIX_BITS>, grid, dim3(WG), 0, stream, in, L, R, N,
-                    n, shift, bits, hist, st, st_next, ticket, abort_word, dst, lr);
+                    n, shift, bits, hist, st, st_next, ch, abort_word, dst, lr);
   }
 }
 
@@ -620,30 +727,29 @@ template <int MODE, int BITS>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) void k_os_pass_windows(
     const uint64_t* __restrict__ items_in, const int32_t* __restrict__ L,
     const int32_t* __restrict__ R, int64_t N, int64_t n, int shift, int bits,
-    const uint32_t* __restrict__ hist, uint64_t* status, uint32_t* ticket, uint32_t* abort_word,
+    const uint32_t* __restrict__ hist, uint64_t* status, Chains ch, uint32_t* abort_word,
     uint64_t* __restrict__ items_out, uint64_t* __restrict__ pairs, uint16_t* __restrict__ pre,
     int nwin) {
   os_pass<MODE, BIG_ROUNDS, true, BITS>(items_in, L, R, N, n, shift, bits, hist, status, nullptr,
-                                        ticket,
-                          abort_word, items_out, nullptr, pairs, pre, nwin);
+                                        ch, abort_word, items_out, nullptr, pairs, pre, nwin);
 }
 
 template <int MODE>
 hipError_t launch_win_pass(dim3 grid, hipStream_t stream, const uint64_t* in, const int32_t* L,
                            const int32_t* R, int64_t N, int64_t n, int shift, int bits,
-                           const uint32_t* hist, uint64_t* st, uint32_t* ticket,
+                           const uint32_t* hist, uint64_t* st, Chains ch,
                            uint32_t* abort_word, uint64_t* dst, uint64_t* pairs, uint16_t* pre,
                            int nwin) {
   switch (bits) {
     case RADIX_BITS - 2:
       return launch(k_os_pass_windows<MODE, RADIX_BITS - 2>, grid, dim3(WG), 0, stream, in, L, R,
-                    N, n, shift, bits, hist, st, ticket, abort_word, dst, pairs, pre, nwin);
+                    N, n, shift, bits, hist, st, ch, abort_word, dst, pairs, pre, nwin);
     case RADIX_BITS - 1:
       return launch(k_os_pass_windows<MODE, RADIX_BITS - 1>, grid, dim3(WG), 0, stream, in, L, R,
-                    N, n, shift, bits, hist, st, ticket, abort_word, dst, pairs, pre, nwin);
+                    N, n, shift, bits, hist, st, ch, abort_word, dst, pairs, pre, nwin);
     default:
       return launch(k_os_pass_windows<MODE, RADIX_BITS>, grid, dim3(WG), 0, stream, in, L, R, N,
-                    n, shift, bits, hist, st, ticket, abort_word, dst, pairs, pre, nwin);
+                    n, shift, bits, hist, st, ch, abort_word, dst, pairs, pre, nwin);
   }
 }
 
@@ -791,6 +897,7 @@ int bit_length(uint64_t x) {
 
 struct SortLayout {
   int64_t N, num_tiles, hist_groups;
+  int64_t range_tiles;  // tiles per chain's range; a pass launches CHAINS * range_tiles groups
   int hist_per_group;
   int rounds;  // items per thread of a tile
   int nwin;    // LR windows of the remap, 0 = scattered remap stores
@@ -808,6 +915,9 @@ SortLayout sort_layout_items(int64_t N) {
   s.num_tiles = (s.N + tile - 1) / tile;
   s.hist_per_group = hist_tiles(s.num_tiles);
   s.hist_groups = (s.num_tiles + s.hist_per_group - 1) / s.hist_per_group;
+  // ranges of whole histogram groups, so that a group counts into one copy
+  const int64_t groups_per_range = (s.hist_groups + CHAINS - 1) / CHAINS;
+  s.range_tiles = groups_per_range * s.hist_per_group;
   size_t o = 0;
   auto take = [&o](size_t bytes) {
     const size_t at = o;
@@ -817,8 +927,8 @@ SortLayout sort_layout_items(int64_t N) {
   s.off_items = take(sizeof(uint64_t) * (size_t)s.N);
   s.off_status0 = take(sizeof(uint64_t) * (size_t)RADIX * (size_t)s.num_tiles);
   s.off_status1 = take(sizeof(uint64_t) * (size_t)RADIX * (size_t)s.num_tiles);
-  s.off_hist = take(sizeof(uint32_t) * (size_t)MAX_PASSES * RADIX);
-  s.off_tickets = take(sizeof(uint32_t) * MAX_PASSES);
+  s.off_hist = take(sizeof(uint32_t) * (size_t)HCOPIES * HSTRIDE);
+  s.off_tickets = take(sizeof(uint32_t) * (CHAINS + MAX_PASSES));
   s.off_abort = take(sizeof(uint32_t));
   const int64_t nwin = (N + WIN - 1) / WIN;
   s.nwin = N >= WIN_MIN_N && s.rounds == BIG_ROUNDS && s.num_tiles <= WIN_MAX_TILES &&
@@ -868,7 +978,7 @@ hipError_t onesweep_r(const uint64_t* src, const int32_t* L, const int32_t* R, i
   const bool windows = LR && pairs && lay.nwin > 0 && ROUNDS == BIG_ROUNDS;
   RMQ_TRY(clear(lay, b, stream));
   RMQ_TRY(launch(k_os_hist<MODE, ROUNDS>, dim3((unsigned)lay.hist_groups), dim3(WG), 0, stream,
-                 src, L, R, N, n, dg, lay.hist_per_group, b.hist));
+                 src, L, R, N, n, dg, lay.hist_per_group, lay.range_tiles, b.hist));
   const uint64_t* in = src;
   for (int p = 0; p < dg.passes; ++p) {
     const bool to_out = ((dg.passes - 1 - p) % 2) == 0;
@@ -876,15 +986,17 @@ hipError_t onesweep_r(const uint64_t* src, const int32_t* L, const int32_t* R, i
     uint64_t* st = b.status[p & 1];
     uint64_t* st_next = p + 1 < dg.passes ? b.status[(p + 1) & 1] : nullptr;
     int32_t* lr = p + 1 < dg.passes ? nullptr : LR;
-    const dim3 grid((unsigned)lay.num_tiles), block(WG);
+    const Chains ch = p == 0 ? first_pass_chains(b.tickets, lay.range_tiles, lay.num_tiles)
+                             : one_chain(b.tickets + CHAINS + p, lay.num_tiles);
+    const dim3 grid((unsigned)(ch.nchains * ch.range_tiles)), block(WG);
     if (windows && p + 1 == dg.passes) {
       if (p == 0)
         RMQ_TRY((launch_win_pass<MODE>)(grid, stream, in, L, R, N, n, dg.shift[p], dg.bits[p],
-                                        b.hist + p * RADIX, st, b.tickets + p, b.abort_word,
+                                        b.hist + p * RADIX, st, ch, b.abort_word,
                                         dst, pairs, b.pre, lay.nwin));
       else
         RMQ_TRY((launch_win_pass<ITEMS>)(grid, stream, in, L, R, N, n, dg.shift[p], dg.bits[p],
-                                         b.hist + p * RADIX, st, b.tickets + p, b.abort_word,
+                                         b.hist + p * RADIX, st, ch, b.abort_word,
                                          dst, pairs, b.pre, lay.nwin));
       // lanes per tile: the power of two at or above the mean run length
       // (4096 * WIN / N pairs), between 4 and 64
@@ -896,11 +1008,11 @@ hipError_t onesweep_r(const uint64_t* src, const int32_t* L, const int32_t* R, i
                      lay.num_tiles, lay.nwin, lpt_shift, N, LR));
     } else if (p == 0)
       RMQ_TRY((launch_pass<MODE, ROUNDS>)(grid, stream, dg.bits[p], in, L, R, N, n, dg.shift[p],
-                                        b.hist + p * RADIX, st, st_next, b.tickets + p,
+                                        b.hist + p * RADIX, st, st_next, ch,
                                         b.abort_word, dst, lr));
     else
       RMQ_TRY((launch_pass<ITEMS, ROUNDS>)(grid, stream, dg.bits[p], in, L, R, N, n, dg.shift[p],
-                                         b.hist + p * RADIX, st, st_next, b.tickets + p,
+                                         b.hist + p * RADIX, st, st_next, ch,
                                          b.abort_word, dst, lr));
     in = dst;
   }
@@ -926,10 +1038,11 @@ hipError_t tag_sweep(const uint64_t* E, const SortLayout& lay, const SortBufs& b
   RMQ_TRY(clear(lay, b, stream));
   RMQ_TRY(launch(k_os_hist<E_TAGS, ROUNDS>, dim3((unsigned)lay.hist_groups), dim3(WG), 0, stream,
                  E, static_cast<const int32_t*>(nullptr), static_cast<const int32_t*>(nullptr),
-                 lay.N, (int64_t)0, dg, lay.hist_per_group, b.hist));
-  RMQ_TRY((launch_pass<E_TAGS, ROUNDS>)(dim3((unsigned)lay.num_tiles), stream, dg.bits[0], E,
-                                       nullptr, nullptr, lay.N, 0, dg.shift[0], b.hist,
-                                       b.status[0], nullptr, b.tickets, b.abort_word, sorted,
+                 lay.N, (int64_t)0, dg, lay.hist_per_group, lay.range_tiles, b.hist));
+  const Chains ch = first_pass_chains(b.tickets, lay.range_tiles, lay.num_tiles);
+  RMQ_TRY((launch_pass<E_TAGS, ROUNDS>)(dim3((unsigned)(CHAINS * lay.range_tiles)), stream,
+                                       dg.bits[0], E, nullptr, nullptr, lay.N, 0, dg.shift[0],
+                                       b.hist, b.status[0], nullptr, ch, b.abort_word, sorted,
                                        nullptr));
   return hipSuccess;
 }
