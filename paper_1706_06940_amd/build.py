@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import concurrent.futures as cf
 import os
+import re
 import shutil
 import subprocess
 
@@ -48,12 +49,35 @@ def hipcc() -> str:
     return os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 
 
+def scratch_kernels(remarks: str) -> list[tuple[str, int]]:
+    """Kernels that the compiler's resource-usage remarks show using scratch
+    (per-lane private memory: register spills or private arrays)."""
+    found, name = [], None
+    for line in remarks.splitlines():
+        m = re.search(r"remark: Function Name: (\S+)", line)
+        if m:
+            name = m.group(1)
+            continue
+        m = re.search(r"remark:\s+ScratchSize \[bytes/lane\]: (\d+)", line)
+        if m and name and int(m.group(1)) > 0:
+            found.append((name, int(m.group(1))))
+    return found
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc(), *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [hipcc(), *FLAGS, "-Rpass-analysis=kernel-resource-usage", "-c",
+           os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
+    # No kernel may use scratch: every one is sized to keep its state in
+    # registers and LDS, and a spill (which can come from a small change, as
+    # a run-time shift count once did) costs a pass several times its time.
+    spills = scratch_kernels(r.stderr)
+    if spills:
+        raise RuntimeError(f"kernels of {src} use scratch: " +
+                           ", ".join(f"{k} ({b} bytes/lane)" for k, b in spills))
     return obj
 
 

@@ -406,16 +406,19 @@ __device__ __forceinline__ uint64_t same_digit_lanes(uint32_t d, uint64_t valid_
 }
 
 // The remap through LR windows (the last pass of long endpoint sorts): tags
-// fall into windows of 2^WIN_SHIFT consecutive tags (128 KiB of LR); the
-// last pass writes each tile's (tag << 32 | slot) pairs grouped by window
-// into the tile's own range of a pair buffer, with the window offsets in a
-// row of `pre`, and k_remap_windows then builds each window of LR in LDS
-// and writes it out whole.
-constexpr int WIN_SHIFT = 15;
+// fall into windows of 2^win_shift consecutive tags (at most 2^15, 128 KiB
+// of LR); the last pass writes each tile's (tag << 32 | slot) pairs grouped
+// by window into the tile's own range of a pair buffer, with the window
+// offsets in a row of `pre`, and k_remap_windows then builds each window of
+// LR in LDS and writes it out whole.  The window is the largest that still
+// gives 256 windows (one workgroup each), down to 2^12 tags.
+constexpr int WIN_SHIFT = 15;  // the largest window
 constexpr int WIN = 1 << WIN_SHIFT;
+constexpr int MIN_WIN_SHIFT = 12;
 constexpr int MAX_WINDOWS = 1024;       // windows of one sort (LDS counters of the pass)
 constexpr int WIN_MAX_TILES = 6144;     // tiles whose runs a window workgroup keeps in LDS
-constexpr int64_t WIN_MIN_N = 1 << 22;  // shorter lists keep the scattered stores
+// Shorter lists keep the scattered stores (their LR stays in the L2s).
+constexpr int64_t WIN_MIN_N = 1 << 20;
 
 // One pass over a tile (see the top of this file).  WINDOWS: the last pass
 // of a long endpoint sort, which also writes the tile's remap pairs.
@@ -428,7 +431,7 @@ __device__ __forceinline__ void os_pass(const uint64_t* __restrict__ items_in,
                                         Chains ch, uint32_t* abort_word,
                                         uint64_t* __restrict__ items_out,
                                         int32_t* __restrict__ LR, uint64_t* __restrict__ pairs,
-                                        uint16_t* __restrict__ pre, int nwin) {
+                                        uint16_t* __restrict__ pre, int nwin, int win_shift) {
   constexpr int TILE = WG * ROUNDS;
   // per wave and digit: the wave's count, then the tile-local slot of its
   // first item of that digit
@@ -628,21 +631,24 @@ __device__ __forceinline__ void os_pass(const uint64_t* __restrict__ items_in,
   // ---- WINDOWS: the items as above, and each item's (tag, slot) pair
   // ranked inside its window by an LDS counter ----
   uint64_t pr[ROUNDS];     // (tag << 32) | slot
-  uint32_t pr_at[ROUNDS];  // rank inside the window; TILE = not placed
+  // window << 16 | rank inside the window (both found once: a second
+  // shift by the run-time window width pushed the kernel into scratch);
+  // ~0 = not placed
+  uint32_t pr_at[ROUNDS];
 #pragma unroll
   for (int i = 0; i < ROUNDS; ++i) {
     const int t = i * WG + threadIdx.x;
     pr[i] = 0;
-    pr_at[i] = TILE;
+    pr_at[i] = ~0u;
     if (t >= tile_n) continue;
     const uint64_t x = s_item[t];
     const uint32_t dst = shift_to_global[digit_bits(x, shift, bits)] + (uint32_t)t;
     if ((int64_t)dst >= N) continue;  // never, for consistent counts
     pos_out[dst] = (int32_t)(x >> 32);  // the position alone (the tag is used up)
     const uint32_t g = (uint32_t)x;
-    const uint32_t w = min(g >> WIN_SHIFT, (uint32_t)nwin - 1u);
+    const uint32_t w = min(g >> win_shift, (uint32_t)nwin - 1u);
     pr[i] = ((uint64_t)g << 32) | dst;
-    pr_at[i] = atomicAdd(&s_wcnt[w], 1u);
+    pr_at[i] = (w << 16) | atomicAdd(&s_wcnt[w], 1u);
   }
   __syncthreads();  // counts final; s_item free again
   // window offsets inside the tile: thread u scans windows 4u .. 4u + 3
@@ -670,9 +676,8 @@ __device__ __forceinline__ void os_pass(const uint64_t* __restrict__ items_in,
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < ROUNDS; ++i) {
-    if (pr_at[i] >= (uint32_t)TILE) continue;
-    const uint32_t w = min((uint32_t)(pr[i] >> 32) >> WIN_SHIFT, (uint32_t)nwin - 1u);
-    const uint32_t at = s_wcnt[w] + pr_at[i];
+    if (pr_at[i] == ~0u) continue;
+    const uint32_t at = s_wcnt[pr_at[i] >> 16] + (pr_at[i] & 0xFFFFu);
     if (at < (uint32_t)TILE) s_item[at] = pr[i];  // always true
   }
   __syncthreads();
@@ -696,7 +701,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) void k_
                                                 int32_t* __restrict__ LR) {
   os_pass<MODE, ROUNDS, false, BITS>(items_in, L, R, N, n, shift, bits, hist, status,
                                      status_next, ch, abort_word, items_out, LR, nullptr,
-                                     nullptr, 1);
+                                     nullptr, 1, WIN_SHIFT);
 }
 
 // Launch of a pass whose digits have `bits` bits: the ranking takes one
@@ -729,9 +734,10 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) void k_
     const int32_t* __restrict__ R, int64_t N, int64_t n, int shift, int bits,
     const uint32_t* __restrict__ hist, uint64_t* status, Chains ch, uint32_t* abort_word,
     uint64_t* __restrict__ items_out, uint64_t* __restrict__ pairs, uint16_t* __restrict__ pre,
-    int nwin) {
+    int nwin, int win_shift) {
   os_pass<MODE, BIG_ROUNDS, true, BITS>(items_in, L, R, N, n, shift, bits, hist, status, nullptr,
-                                        ch, abort_word, items_out, nullptr, pairs, pre, nwin);
+                                        ch, abort_word, items_out, nullptr, pairs, pre, nwin,
+                                        win_shift);
 }
 
 template <int MODE>
@@ -739,23 +745,23 @@ hipError_t launch_win_pass(dim3 grid, hipStream_t stream, const uint64_t* in, co
                            const int32_t* R, int64_t N, int64_t n, int shift, int bits,
                            const uint32_t* hist, uint64_t* st, Chains ch,
                            uint32_t* abort_word, uint64_t* dst, uint64_t* pairs, uint16_t* pre,
-                           int nwin) {
+                           int nwin, int win_shift) {
   switch (bits) {
     case RADIX_BITS - 2:
       return launch(k_os_pass_windows<MODE, RADIX_BITS - 2>, grid, dim3(WG), 0, stream, in, L, R,
-                    N, n, shift, bits, hist, st, ch, abort_word, dst, pairs, pre, nwin);
+                    N, n, shift, bits, hist, st, ch, abort_word, dst, pairs, pre, nwin, win_shift);
     case RADIX_BITS - 1:
       return launch(k_os_pass_windows<MODE, RADIX_BITS - 1>, grid, dim3(WG), 0, stream, in, L, R,
-                    N, n, shift, bits, hist, st, ch, abort_word, dst, pairs, pre, nwin);
+                    N, n, shift, bits, hist, st, ch, abort_word, dst, pairs, pre, nwin, win_shift);
     default:
       return launch(k_os_pass_windows<MODE, RADIX_BITS>, grid, dim3(WG), 0, stream, in, L, R, N,
-                    n, shift, bits, hist, st, ch, abort_word, dst, pairs, pre, nwin);
+                    n, shift, bits, hist, st, ch, abort_word, dst, pairs, pre, nwin, win_shift);
   }
 }
 
-// LR window w (tags [w * WIN, (w + 1) * WIN)) from the pairs of every tile:
-// tile j's run for the window is pairs[j * 4096 + pre[w][j] .. j * 4096 +
-// pre[w + 1][j]).  The runs' bounds (two contiguous columns of pre) go to
+// LR window w (tags [w << win_shift, (w + 1) << win_shift)) from the pairs
+// of every tile: tile j's run for the window is pairs[j * T + pre[w][j] ..
+// j * T + pre[w + 1][j]) (T items per tile).  The runs' bounds (two contiguous columns of pre) go to
 // LDS first; then each wave takes 64 / lpt tiles per load, lpt lanes per
 // tile (lpt: a power of two near the mean run length), U such loads in
 // flight per lane, and writes the entries into the LDS image of the window;
@@ -767,7 +773,8 @@ constexpr int AWG = 1024;  // threads of a window workgroup
 constexpr int WIN_TILE = BIG_TILE;
 __global__ __launch_bounds__(AWG) void k_remap_windows(const uint64_t* __restrict__ pairs,
                                                        const uint16_t* __restrict__ pre,
-                                                       int64_t num_tiles, int nwin, int lpt_shift,
+                                                       int64_t num_tiles, int nwin, int win_shift,
+                                                       int lpt_shift,
                                                        int64_t N, int32_t* __restrict__ LR) {
   __shared__ int32_t win[WIN];
   __shared__ uint32_t runs[WIN_MAX_TILES];  // start | end << 16
@@ -777,7 +784,8 @@ __global__ __launch_bounds__(AWG) void k_remap_windows(const uint64_t* __restric
   const int64_t wx = xcd_tile(nwin);
   if (wx < 0) return;  // whole workgroup
   const int w = (int)wx;
-  const int64_t wbase = (int64_t)w << WIN_SHIFT;
+  const int64_t wbase = (int64_t)w << win_shift;
+  const int wsize = 1 << win_shift;
   {
     constexpr int PER = (WIN_MAX_TILES + AWG - 1) / AWG;
     const uint16_t* c0 = pre + (int64_t)w * num_tiles;
@@ -802,7 +810,7 @@ __global__ __launch_bounds__(AWG) void k_remap_windows(const uint64_t* __restric
   auto put = [&](uint64_t x) {
     const uint32_t t = (uint32_t)(x >> 32), slot = (uint32_t)x;
     const int64_t at = (int64_t)t - wbase;
-    if (at >= 0 && at < WIN) win[at] = (t & 1u) ? (int32_t)slot - 1 : (int32_t)slot;
+    if (at >= 0 && at < wsize) win[at] = (t & 1u) ? (int32_t)slot - 1 : (int32_t)slot;
   };
   constexpr int U = 8;
   const int64_t stride = (AWG / 64) * per_load;     // tiles per round of the block's waves
@@ -838,7 +846,7 @@ __global__ __launch_bounds__(AWG) void k_remap_windows(const uint64_t* __restric
     }
   }
   __syncthreads();
-  const int64_t len = N - wbase < WIN ? N - wbase : WIN;
+  const int64_t len = N - wbase < wsize ? N - wbase : wsize;
   for (int64_t i = threadIdx.x; i < len; i += AWG) LR[wbase + i] = win[i];
 }
 
@@ -901,6 +909,7 @@ struct SortLayout {
   int hist_per_group;
   int rounds;  // items per thread of a tile
   int nwin;    // LR windows of the remap, 0 = scattered remap stores
+  int win_shift;  // log2 of the tags per window
   size_t off_items, off_status0, off_status1, off_hist, off_tickets, off_abort, off_pre, bytes;
 };
 
@@ -930,7 +939,9 @@ SortLayout sort_layout_items(int64_t N) {
   s.off_hist = take(sizeof(uint32_t) * (size_t)HCOPIES * HSTRIDE);
   s.off_tickets = take(sizeof(uint32_t) * (CHAINS + MAX_PASSES));
   s.off_abort = take(sizeof(uint32_t));
-  const int64_t nwin = (N + WIN - 1) / WIN;
+  s.win_shift = WIN_SHIFT;
+  while (s.win_shift > MIN_WIN_SHIFT && (N >> s.win_shift) < 256) --s.win_shift;
+  const int64_t nwin = (N + ((int64_t)1 << s.win_shift) - 1) >> s.win_shift;
   s.nwin = N >= WIN_MIN_N && s.rounds == BIG_ROUNDS && s.num_tiles <= WIN_MAX_TILES &&
                    nwin <= MAX_WINDOWS
                ? (int)nwin
@@ -993,19 +1004,19 @@ hipError_t onesweep_r(const uint64_t* src, const int32_t* L, const int32_t* R, i
       if (p == 0)
         RMQ_TRY((launch_win_pass<MODE>)(grid, stream, in, L, R, N, n, dg.shift[p], dg.bits[p],
                                         b.hist + p * RADIX, st, ch, b.abort_word,
-                                        dst, pairs, b.pre, lay.nwin));
+                                        dst, pairs, b.pre, lay.nwin, lay.win_shift));
       else
         RMQ_TRY((launch_win_pass<ITEMS>)(grid, stream, in, L, R, N, n, dg.shift[p], dg.bits[p],
                                          b.hist + p * RADIX, st, ch, b.abort_word,
-                                         dst, pairs, b.pre, lay.nwin));
+                                         dst, pairs, b.pre, lay.nwin, lay.win_shift));
       // lanes per tile: the power of two at or above the mean run length
-      // (4096 * WIN / N pairs), between 4 and 64
-      const double mean_run = (double)WIN_TILE * WIN / (double)N;
+      // (tile items * window tags / N pairs), between 4 and 64
+      const double mean_run = (double)WIN_TILE * (double)(1 << lay.win_shift) / (double)N;
       int lpt_shift = 2;
       while (lpt_shift < 6 && (double)(1 << lpt_shift) < mean_run) ++lpt_shift;
       RMQ_TRY(launch(k_remap_windows, dim3((unsigned)xcd_grid(lay.nwin)), dim3(AWG), 0, stream,
                      static_cast<const uint64_t*>(pairs), static_cast<const uint16_t*>(b.pre),
-                     lay.num_tiles, lay.nwin, lpt_shift, N, LR));
+                     lay.num_tiles, lay.nwin, lay.win_shift, lpt_shift, N, LR));
     } else if (p == 0)
       RMQ_TRY((launch_pass<MODE, ROUNDS>)(grid, stream, dg.bits[p], in, L, R, N, n, dg.shift[p],
                                         b.hist + p * RADIX, st, st_next, ch,

@@ -174,15 +174,20 @@ def test_workspace_and_timer(orc):
 
 
 # The contracted path's remap for long endpoint lists goes through LR windows
-# of 32768 tags built in LDS (2q >= 2^22, up to 6144 tiles of 4096 items);
-# shorter lists write LR with scattered stores.  Both sides of the switch,
-# a ragged last window, the single-pass sort (n <= 256: the first pass is
-# also the last), and both sides of the longest list the windows take.
-@pytest.mark.parametrize("n,q", [(3_000_017, 2_097_151), (3_000_017, 2_097_152),
+# built in LDS (2q >= 2^20, up to 6144 tiles of 8192 items); the window is
+# the largest of 2^12 .. 2^15 tags that gives 256 windows, so it grows at
+# 2q = 2^21, 2^22 and 2^23.  Shorter lists write LR with scattered stores.
+# Both sides of the switch and of each window change, a ragged last window,
+# the single-pass sort (n <= 256: the first pass is also the last), and both
+# sides of the longest list the windows take.
+@pytest.mark.parametrize("n,q", [(3_000_017, 524_287), (3_000_017, 524_288),
+                                 (3_000_017, 1_048_575), (3_000_017, 1_048_576),
+                                 (3_000_017, 2_097_151), (3_000_017, 2_097_152),
                                  (10_000_019, 2_100_007), (200, 2_200_001),
+                                 (10_000_019, 4_194_303), (10_000_019, 4_194_304),
                                  (50_000_017, 12_000_007),
-                                 # 6144 tiles of 4096 items exactly, and one item more
-                                 (30_000_001, 12_582_912), (30_000_001, 12_582_913)])
+                                 # 6144 tiles of 8192 items exactly, and one item more
+                                 (30_000_001, 25_165_824), (30_000_001, 25_165_825)])
 def test_contracted_remap_windows(orc, n, q):
     d = need_gpu()
     say("remap_windows", n, q)
