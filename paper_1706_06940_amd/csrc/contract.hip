@@ -17,8 +17,10 @@
 //   tiles, the next tile's values and first endpoints in flight while it
 //   works on the current one, and carries the area that is still open at a
 //   tile's end into the next tile (no barrier: waves share nothing).
-//   * a tile without endpoints lies inside the open area: its min (32-bit
-//     compares, leftmost on ties) joins the carried value;
+//   * a tile without endpoints lies inside the open area: each lane keeps
+//     its min over a run of such tiles (32-bit compares, leftmost on ties),
+//     and the wave's min over the run joins the carried value when the run
+//     ends;
 //   * otherwise the tile is staged in LDS, its endpoints set head bits, and
 //     lane l takes elements 16l .. 16l+15 with a running min that restarts
 //     at heads; a segmented min-scan over the lanes' last runs gives each
@@ -128,7 +130,7 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-constexpr int TPW = 8;   // tiles per wave
+constexpr int TPW = 8;   // tiles per wave (2 or 4 were slower at every density)
 constexpr int KREG = 4;  // endpoint slots per lane of a tile held in registers (256 a tile)
 
 // The tile's values, coalesced: lane l holds elements 256 c + 4 l + (0..3);
@@ -179,9 +181,14 @@ __global__ __launch_bounds__(WG) void k_contract(const int32_t* __restrict__ A, 
   const int lane = lane_id();
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int64_t tb = ((int64_t)blockIdx.x * WAVES + wave) * TPW;
-  if (tb >= num_tiles || (fail && *fail)) return;  // the whole wave
+  if (tb >= num_tiles) return;  // the whole wave
   const int cnt = (int)(num_tiles - tb < TPW ? num_tiles - tb : TPW);
   const bool aligned = ((uintptr_t)A & 15) == 0;
+  // the first tile's values go out before anything else is read: they are
+  // in flight while the wave reads the abort word and its table entries
+  v4i32 xv[4];
+  load_tile(A, n, tb << TSHIFT, aligned, lane, xv);
+  if (fail && *fail) return;
   // slots and areas as 32-bit unsigned (M <= 2^31); area j - 1 of slot 0
   // wraps above the last area, M - 2
   const uint32_t Mu = (uint32_t)M;
@@ -196,11 +203,12 @@ __global__ __launch_bounds__(WG) void k_contract(const int32_t* __restrict__ A, 
     if (lane >= dlt && up > ts_lane) ts_lane = up;
   }
   auto ts = [&](int i) { return (uint32_t)__builtin_amdgcn_readlane((int)ts_lane, i); };
+  // a wave without endpoints outside the areas (before E_0 or after
+  // E_{M-1}) has nothing to do
+  if (ts(0) == ts(cnt) && (ts(0) == 0u || ts(0) >= Mu)) return;
   int32_t* xs = s_x[wave];
 
-  v4i32 xv[4];
   int32_t en[KREG];
-  load_tile(A, n, tb << TSHIFT, aligned, lane, xv);
   load_ends(E, ts(0), ts(1), (uint32_t)(tb << TSHIFT), lane, en);
   // the area open at the current tile's start: its index, its min over the
   // part already seen in this wave, and whether it opened before the wave
@@ -208,6 +216,22 @@ __global__ __launch_bounds__(WG) void k_contract(const int32_t* __restrict__ A, 
   uint32_t open_area = ts(0) - 1u;
   uint64_t acc = KEY_NONE;
   bool shared = true;
+  // endpoint-free tiles in a row: each lane's own min over them (value and
+  // position, leftmost on ties), folded across the wave into acc only when
+  // the run ends (an endpoint tile, or the wave's last tile), so that such a
+  // tile costs the lane's compares alone
+  int32_t rv = INT32_MAX;
+  uint32_t ro = ~0u;  // none yet (positions are below 2^31)
+  bool pend = false;  // wave-uniform: the lanes hold values not yet in acc
+  auto flush = [&]() {
+    if (pend) {
+      const uint64_t m = group_min_u64<64>(ro != ~0u ? make_key(rv, ro) : KEY_NONE);
+      acc = umin64(acc, (uint64_t)readlane64((int64_t)m, 63));
+      rv = INT32_MAX;
+      ro = ~0u;
+      pend = false;
+    }
+  };
 
   for (int i = 0; i < cnt; ++i) {
     const int64_t t0l = (tb + i) << TSHIFT;
@@ -222,32 +246,35 @@ __global__ __launch_bounds__(WG) void k_contract(const int32_t* __restrict__ A, 
     if (jlo == jend) {
       // no endpoint inside: the tile lies in the open area (none before E_0
       // or after E_{M-1})
+      // the next tile's loads go out first, so that they are in flight
+      // while this tile is compared
+      v4i32 cur[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) cur[c] = xv[c];
+      if (more) {
+        load_tile(A, n, t0l + T, aligned, lane, xv);
+        load_ends(E, jend, ts(i + 2), t0 + T, lane, en);
+      }
       if (jlo != 0 && jlo < Mu) {
-        int32_t cv = INT32_MAX;
-        int co = T;  // none yet
+        pend = true;
+        // the lane's elements in increasing position: < keeps the leftmost
 #pragma unroll
         for (int c = 0; c < 4; ++c)
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
             const int a = c * 256 + lane * 4 + k;
-            const bool take = tile_n == T ? (xv[c][k] < cv || (c == 0 && k == 0))
-                                          : (a < tile_n && (xv[c][k] < cv || co == T));
-            cv = take ? xv[c][k] : cv;
-            co = take ? a : co;
+            const bool take = tile_n == T ? (cur[c][k] < rv || (c == 0 && k == 0 && ro == ~0u))
+                                          : (a < tile_n && (cur[c][k] < rv || ro == ~0u));
+            rv = take ? cur[c][k] : rv;
+            ro = take ? t0 + (uint32_t)a : ro;
           }
-        const uint64_t m =
-            group_min_u64<64>(co < T ? make_key(cv, t0 + (uint32_t)co) : KEY_NONE);
-        acc = umin64(acc, (uint64_t)readlane64((int64_t)m, 63));
-      }
-      if (more) {  // the next tile's loads go out now
-        load_tile(A, n, t0l + T, aligned, lane, xv);
-        load_ends(E, jend, ts(i + 2), t0 + T, lane, en);
       }
       continue;
     }
 
     // ---- a tile with endpoints: staged in LDS, then the registers take
     // the next tile's loads ----
+    flush();  // the area entering the tile has all its earlier values in acc
 #pragma unroll
     for (int c = 0; c < 4; ++c)
       *reinterpret_cast<v4i32*>(xs + stage_index(c * 256 + lane * 4)) = xv[c];
@@ -353,6 +380,7 @@ __global__ __launch_bounds__(WG) void k_contract(const int32_t* __restrict__ A, 
     shared = false;
   }
   // the area still open after the wave's last tile continues in later waves
+  flush();
   if (lane == 0 && open_area <= last_area && acc != KEY_NONE)
     atomicMin((unsigned long long*)&aq[open_area], (unsigned long long)acc);
 }
