@@ -407,7 +407,7 @@ __device__ __forceinline__ void query_core(const Src& src, int64_t src_len, int6
     n_elems += (uint64_t)reads;
   }
 
-  if (live) *outp = ok ? (int32_t)src.pos_of(best) : -1;
+  if (live) __builtin_nontemporal_store(ok ? (int32_t)src.pos_of(best) : -1, outp);
 
   if (bad_count) {
     const uint64_t bad = ballot(live && !ok);
@@ -450,12 +450,14 @@ __global__ __launch_bounds__(WG) void k_query(Src src, int64_t src_len, int64_t 
   const bool failed = fail && *fail != 0;  // uniform: one scalar load
   int64_t l = 0, r = -1, li = 0, ri = -1;
   if (live && !failed) {
-    l = L[i];
-    r = R[i];
+    // the query streams are read once: non-temporal, so that they do not
+    // push the table (gathered at random) out of the caches
+    l = __builtin_nontemporal_load(L + i);
+    r = __builtin_nontemporal_load(R + i);
     if (LR) {
-      const int2 c = reinterpret_cast<const int2*>(LR)[i];
-      li = c.x;
-      ri = c.y;
+      const int64_t c = __builtin_nontemporal_load(reinterpret_cast<const int64_t*>(LR) + i);
+      li = (int32_t)(uint32_t)c;
+      ri = (int32_t)(uint32_t)(c >> 32);
     } else {
       li = l;
       ri = r;
