@@ -386,13 +386,16 @@ rmq_status rmq_contract(const int32_t *A, int64_t n, const int32_t *pos, const i
  * Batches of arrays.  Many independent arrays, each with its own batch of
  * queries, answered together: the planner picks each array's block size,
  * method and block levels (the automated choice of k left open in Section
- * 5; two block levels, Section 3.3, where its measured table chooses them),
- * and the arrays that take the plain method (Section 3.2) run as ONE launch
- * per phase for all of them -- block minima, the k-block minima from the
- * k1-block minima (arrays with two levels), each round of Sparse Table
- * levels, queries (one launch for the arrays with two levels, one for the
- * others) -- instead of a few launches per array.  A batch owns its device scratch and a
- * device table describing the arrays; inputs and outputs stay the caller's.
+ * 5; two block levels, Section 3.3, where its measured table chooses
+ * them), and the arrays that take the plain method (Section 3.2) run as ONE
+ * launch per phase for all of them -- block minima, the k-block minima from
+ * the k1-block minima (arrays with two levels), each round of Sparse Table
+ * levels, queries -- instead of a few launches per array.  For those
+ * launches an item that fixes neither block size nor method gets blocks of
+ * at least n / 1024 elements (one Sparse Table round then builds every
+ * table), and 1024-element sub-blocks under blocks of more than 4096.  A
+ * batch owns its device scratch and a device table describing the arrays;
+ * inputs and outputs stay the caller's.
  * Pointers in the items must stay valid, and the arrays unmodified, for the
  * batch's life: runs reuse them. */
 typedef struct rmq_batch_item {

@@ -119,6 +119,12 @@ int32_t default_block_two_level(int64_t n, int32_t k1) {
 // sub-block lookup only adds a dependent load before each scan.
 int32_t default_sub_block_contracted(int64_t) { return 0; }
 
+// Batched items: blocks per array, the largest one-level block, and the k1
+// given above it.
+constexpr int64_t BATCH_MAX_BLOCKS = 1024;
+constexpr int64_t BATCH_ONE_LEVEL_MAX_K = 4096;
+constexpr int64_t BATCH_SUB_BLOCK = 1024;
+
 rmq_status make_plan(int64_t n, int64_t q, const rmq_options* opt, Plan* p,
                      bool allow_two_level = true) {
   int32_t path = opt ? opt->path : RMQ_PATH_AUTO;
@@ -885,7 +891,8 @@ struct rmq_batch_s {
   JobTable<ChunkJob> blockmin, keys;
   int rounds = 0;
   JobTable<TileJob> round[ST_MAX_ROUNDS];
-  JobTable<WaveJob> queries_two, queries_one;  // arrays with two block levels / one
+  // query waves: those of arrays with two block levels first, then the others
+  JobTable<WaveJob> queries;
   hipGraphExec_t graph[2] = {nullptr, nullptr};
 };
 
@@ -897,9 +904,7 @@ rmq_status batch_enqueue(rmq_batch b, int mode, hipStream_t s) {
     if (e == hipSuccess) e = launch_blockmin_keys_multi(b->keys.jobs, b->keys.count, s);
     for (int r = 0; e == hipSuccess && r < b->rounds; ++r)
       e = launch_sparse_table_multi(b->round[r].jobs, r, b->round[r].count, s);
-    if (e == hipSuccess) e = launch_query_multi(b->queries_two.jobs, b->queries_two.count, true, s);
-    if (e == hipSuccess)
-      e = launch_query_multi(b->queries_one.jobs, b->queries_one.count, false, s);
+    if (e == hipSuccess) e = launch_query_multi(b->queries.jobs, b->queries.count, s);
     if (e != hipSuccess) return from_hip(e);
   }
   for (size_t i = 0; i < b->items.size(); ++i) {
@@ -947,6 +952,24 @@ rmq_status rmq_batch_create(const rmq_batch_item* items, int32_t count, rmq_batc
     if (st != RMQ_OK) {
       delete b;
       return st;
+    }
+    // Two adjustments of the plain-method plans for one launch per phase,
+    // unless the caller fixed the block size or the path:
+    // * at most 2^10 blocks per array: then the first Sparse Table round
+    //   (levels 1 .. 10) builds every table and the batch needs no second
+    //   round launch;
+    // * in one launch a wave reads its lanes' partial blocks one range at a
+    //   time, so an item over large one-level blocks sets the launch's tail:
+    //   blocks over 4096 elements get the k1-block level (scans then stay
+    //   within k1 elements).
+    Plan& pl = b->plans[i];
+    if (items[i].block_size == 0 && items[i].path == RMQ_PATH_AUTO &&
+        pl.path == RMQ_PATH_FULL) {
+      while ((((int64_t)items[i].n + pl.k - 1) >> pl.kshift) > BATCH_MAX_BLOCKS) {
+        pl.k *= 2;
+        pl.kshift += 1;
+      }
+      if (pl.k1shift < 0 && pl.k > BATCH_ONE_LEVEL_MAX_K) pl.k1shift = ilog2_i64(BATCH_SUB_BLOCK);
     }
     b->plans[i].records = false;  // the batched kernels read the level-major table
     b->ws_off[i] = off;
@@ -1049,8 +1072,8 @@ rmq_status rmq_batch_create(const rmq_batch_item* items, int32_t count, rmq_batc
   put(b->blockmin, jb_min);
   put(b->keys, jb_keys);
   for (int r = 0; r < ST_MAX_ROUNDS; ++r) put(b->round[r], jb_round[r]);
-  put(b->queries_two, jb_q2);
-  put(b->queries_one, jb_q1);
+  jb_q2.insert(jb_q2.end(), jb_q1.begin(), jb_q1.end());
+  put(b->queries, jb_q2);
   e = hipMemcpy(dbase, img.data(), tbytes, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     hipFree(mem);

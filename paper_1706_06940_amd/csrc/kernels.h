@@ -130,9 +130,8 @@ hipError_t launch_blockmin_multi(const ChunkJob* jobs, int64_t count, hipStream_
 hipError_t launch_blockmin_keys_multi(const ChunkJob* jobs, int64_t count, hipStream_t stream);
 hipError_t launch_sparse_table_multi(const TileJob* jobs, int round, int64_t count,
                                      hipStream_t stream);
-// two_level: every array of the jobs has two block levels (else none has).
-hipError_t launch_query_multi(const WaveJob* jobs, int64_t waves, bool two_level,
-                              hipStream_t stream);
+// Each wave's array may have two block levels or one (its job says which).
+hipError_t launch_query_multi(const WaveJob* jobs, int64_t waves, hipStream_t stream);
 // Serving: one launch over a coalesced batch of requests on resident tables
 // (two_level: every table has two block levels, else none has).
 hipError_t launch_query_segments(const ArrayDesc* tables, const int64_t* seg_prefix,

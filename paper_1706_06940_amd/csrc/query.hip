@@ -471,8 +471,7 @@ __global__ __launch_bounds__(WG) void k_query(Src src, int64_t src_len, int64_t 
 // the table whose range of the concatenated query list holds it.
 // Queries of a batch: wave w does job w, 64 consecutive queries of one
 // array (each array's queries padded to whole waves, so a wave never spans
-// two arrays).  Every array of a launch has two block levels (Src = SrcA2)
-// or none (SrcA).
+// two arrays).  An array has two block levels (SrcA2) or one (SrcA).
 template <class Src>
 __device__ __forceinline__ Src array_src(const ArrayDesc& d);
 template <>
@@ -484,7 +483,8 @@ __device__ __forceinline__ SrcA2 array_src<SrcA2>(const ArrayDesc& d) {
   return SrcA2{SrcA{d.A, d.n}, d.sub, d.nb1, d.k1shift};
 }
 
-template <class Src>
+// One launch for the waves of every array: a wave's job says whether its
+// array has two block levels (the branch is uniform over the wave).
 __global__ __launch_bounds__(WG) void k_query_multi(const WaveJob* __restrict__ jobs,
                                                     int64_t waves) {
   const int64_t w = (int64_t)blockIdx.x * (WG / 64) +
@@ -495,11 +495,15 @@ __global__ __launch_bounds__(WG) void k_query_multi(const WaveJob* __restrict__ 
   const bool live = w < waves && i < d.q;
   int64_t l = 0, r = -1;
   if (live) {
-    l = d.L[i];
-    r = d.R[i];
+    l = __builtin_nontemporal_load(d.L + i);
+    r = __builtin_nontemporal_load(d.R + i);
   }
-  query_core(array_src<Src>(d), d.n, d.n, d.kshift, d.st, d.nb, l, r, l, r, live,
-             d.out + (live ? i : 0), nullptr, nullptr, d.lg, d.rec, d.rlev);
+  if (d.sub)
+    query_core(array_src<SrcA2>(d), d.n, d.n, d.kshift, d.st, d.nb, l, r, l, r, live,
+               d.out + (live ? i : 0), nullptr, nullptr, d.lg, d.rec, d.rlev);
+  else
+    query_core(array_src<SrcA>(d), d.n, d.n, d.kshift, d.st, d.nb, l, r, l, r, live,
+               d.out + (live ? i : 0), nullptr, nullptr, d.lg, d.rec, d.rlev);
 }
 
 // A coalesced batch of requests (serving): queries g in
@@ -647,14 +651,10 @@ hipError_t launch_query_contracted(const uint64_t* aq, int64_t m, int64_t n, int
   return hipGetLastError();
 }
 
-hipError_t launch_query_multi(const WaveJob* jobs, int64_t waves, bool two_level,
-                              hipStream_t stream) {
+hipError_t launch_query_multi(const WaveJob* jobs, int64_t waves, hipStream_t stream) {
   if (waves <= 0) return hipSuccess;
   const int64_t grid = (waves + WG / 64 - 1) / (WG / 64);
-  if (two_level)
-    RMQ_TRY(launch(k_query_multi<SrcA2>, dim3((unsigned)grid), dim3(WG), 0, stream, jobs, waves));
-  else
-    RMQ_TRY(launch(k_query_multi<SrcA>, dim3((unsigned)grid), dim3(WG), 0, stream, jobs, waves));
+  RMQ_TRY(launch(k_query_multi, dim3((unsigned)grid), dim3(WG), 0, stream, jobs, waves));
   return hipSuccess;
 }
 
