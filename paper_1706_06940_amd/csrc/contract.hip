@@ -114,13 +114,21 @@ __global__ __launch_bounds__(WG) void k_tiles_scatter(const int32_t* __restrict_
   }
 }
 
-// LDS staging of a tile's values: the 16 elements of lane l at words
-// 20 l .. 20 l + 15, so that lane l reading its 16 values (16 bytes at a
-// time) and lanes writing 4-element pieces of the coalesced load stay spread
-// over the banks.
-constexpr int BLOCK_WORDS = 20;
+// LDS staging of a tile's values: the 16 elements of lane l (block l) at
+// words 16 l .. 16 l + 15, their four 4-word groups in the order g ^ s(l),
+// s(l) = ((l >> 1) ^ (l >> 2)) & 3.  A 16-byte LDS access serves 8 lanes a
+// cycle over 32 banks (16 over 64): the lanes reading one group of their
+// own blocks then hit different banks (s differs among blocks that share
+// banks), and the lanes storing 4-element pieces of the coalesced load fill
+// whole blocks, which share no banks.  (A 20-word row per lane kept the
+// reads apart but made those stores wrap onto the same banks.)
+constexpr int BLOCK_WORDS = 16;
 constexpr int XWORDS = 64 * BLOCK_WORDS;
-__device__ __forceinline__ int stage_index(int e) { return (e >> 4) * BLOCK_WORDS + (e & 15); }
+__device__ __forceinline__ int group_swizzle(int block) { return ((block >> 1) ^ (block >> 2)) & 3; }
+__device__ __forceinline__ int stage_index(int e) {
+  const int b = e >> 4;
+  return b * BLOCK_WORDS + ((((e >> 2) & 3) ^ group_swizzle(b)) << 2) + (e & 3);
+}
 
 // Completes this wave's LDS operations before the next ones (the waves of a
 // workgroup never share LDS here, so no workgroup barrier is needed).
@@ -320,7 +328,7 @@ __global__ __launch_bounds__(WG) void k_contract(const int32_t* __restrict__ A, 
     uint32_t co = 0;
 #pragma unroll
     for (int c = 0; c < EPL; c += 4) {
-      const v4i32 v = *reinterpret_cast<const v4i32*>(xs + lane * BLOCK_WORDS + c);
+      const v4i32 v = *reinterpret_cast<const v4i32*>(xs + stage_index(lane * EPL + c));
       uint32_t pair = 0;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
