@@ -131,15 +131,30 @@ __global__ __launch_bounds__(WG) void k_blockmin_i32(const int32_t* __restrict__
 }
 
 // Block minima of every array of a batch in one launch: workgroup w does
-// job w, one chunk of one array.
-__global__ __launch_bounds__(WG) void k_blockmin_multi(const ChunkJob* __restrict__ jobs) {
-  __shared__ uint64_t part[4];
-  const ChunkJob jb = jobs[blockIdx.x];
-  const int32_t* A = static_cast<const int32_t*>(jb.src);
-  if (((uintptr_t)A & 15) == 0)
-    blockmin_i32_wg<true>(A, jb.len, jb.shift, jb.keys, jb.chunk, part);
-  else
-    blockmin_i32_wg<false>(A, jb.len, jb.shift, jb.keys, jb.chunk, part);
+// jobs 2w and 2w + 1, one chunk of one array each.  Both job records are
+// read at once, so a workgroup waits for one record read per two chunks
+// (one job per workgroup: 0.81 of the HBM peak on the batched workload,
+// against 0.85 for one array's pass, whose workgroups find their chunk from
+// their index).
+constexpr int MULTI_JOBS = 2;
+__global__ __launch_bounds__(WG) void k_blockmin_multi(const ChunkJob* __restrict__ jobs,
+                                                       int64_t count) {
+  __shared__ uint64_t part[MULTI_JOBS][4];  // one set per job: no barrier between them
+  ChunkJob jb[MULTI_JOBS];
+#pragma unroll
+  for (int u = 0; u < MULTI_JOBS; ++u) {
+    const int64_t j = (int64_t)blockIdx.x * MULTI_JOBS + u;
+    jb[u] = jobs[j < count ? j : count - 1];
+  }
+#pragma unroll
+  for (int u = 0; u < MULTI_JOBS; ++u) {
+    if ((int64_t)blockIdx.x * MULTI_JOBS + u >= count) break;  // uniform
+    const int32_t* A = static_cast<const int32_t*>(jb[u].src);
+    if (((uintptr_t)A & 15) == 0)
+      blockmin_i32_wg<true>(A, jb[u].len, jb[u].shift, jb[u].keys, jb[u].chunk, part[u]);
+    else
+      blockmin_i32_wg<false>(A, jb[u].len, jb[u].shift, jb[u].keys, jb[u].chunk, part[u]);
+  }
 }
 
 // ---------------------------------------------------------------- uint64 keys
@@ -254,7 +269,8 @@ hipError_t launch_blockmin_i32(const int32_t* A, int64_t n, int kshift, uint64_t
 
 hipError_t launch_blockmin_multi(const ChunkJob* jobs, int64_t count, hipStream_t stream) {
   if (count <= 0) return hipSuccess;
-  RMQ_TRY(launch(k_blockmin_multi, dim3((unsigned)count), dim3(WG), 0, stream, jobs));
+  const int64_t grid = (count + MULTI_JOBS - 1) / MULTI_JOBS;
+  RMQ_TRY(launch(k_blockmin_multi, dim3((unsigned)grid), dim3(WG), 0, stream, jobs, count));
   return hipSuccess;
 }
 
