@@ -285,9 +285,9 @@ using SrcKeys2 = Src2<SrcKeys>;
 // entries).  All 64 lanes of the wave must call this together: the partial
 // scans are done by the whole wave.  Lanes may belong to different tables
 // (batched launches); `live` is false for padding lanes.
-template <class Src>
+template <class Src, class TablePtr = const uint64_t*>
 __device__ __forceinline__ void query_core(const Src& src, int64_t src_len, int64_t n,
-                                           int kshift, const uint64_t* __restrict__ st,
+                                           int kshift, TablePtr __restrict__ st,
                                            int64_t nb, int64_t l, int64_t r, int64_t li,
                                            int64_t ri, bool live, int32_t* outp,
                                            unsigned long long* __restrict__ bad_count,
@@ -325,7 +325,7 @@ __device__ __forceinline__ void query_core(const Src& src, int64_t src_len, int6
     } else {
       if (inner > 0) {
         if (lg <= 1) {  // doubling (Section 2): two overlapping windows
-          const uint64_t* lev = st + (size_t)t * nb;
+          const TablePtr lev = st + (size_t)t * nb;
           best = rec ? umin64(pl.y, pr.y) : umin64(lev[bl + 1], lev[br - (1ll << t)]);
         } else {
           // l-ary table (Section 3.1), l = 2^lg: level i holds windows of
@@ -333,9 +333,9 @@ __device__ __forceinline__ void query_core(const Src& src, int64_t src_len, int6
           // the last inner block -- at most l of them.  The whole windows
           // share a residue class mod s, so they are adjacent entries.
           const int sh = (t / lg) * lg;
-          const uint64_t* lev = st + (size_t)(t / lg) * nb;
+          const TablePtr lev = st + (size_t)(t / lg) * nb;
           const int64_t whole = inner >> sh;
-          const uint64_t* w = lev + lary_addr(bl + 1, nb, sh);
+          const TablePtr w = lev + lary_addr(bl + 1, nb, sh);
 #pragma unroll 8
           for (int64_t j = 0; j < whole; ++j) best = umin64(best, w[j]);
           if (inner & ((1ll << sh) - 1))
@@ -467,6 +467,76 @@ __global__ __launch_bounds__(WG) void k_query(Src src, int64_t src_len, int64_t 
              bad_count, stats, lg, rec, rlev);
 }
 
+// Large batches over a small doubling table (plain method): the table
+// gathers are the launch's cost -- four 8-byte loads per query at random
+// blocks, each wave load touching up to 64 lines, bound by the L2 request
+// rate (n = 1e8, q = 1e7, k = 65536: 100 of the kernel's 110 us without its
+// partial scans).  Here one 1024-thread workgroup per CU copies the whole
+// table (at most LDS_TABLE_BYTES) into LDS once and then walks the query
+// waves w, w + stride, ...; the table reads become LDS reads and each wave's
+// L and R two rounds ahead are in flight while it answers the current ones.
+// Partial scans still read A (and the k1-block minima) from memory.  Below
+// 2^21 queries the copy per CU costs more than it saves (q = 1e6: 16-21 us
+// against 16 us gathering).
+constexpr int LWG = 1024;
+constexpr int64_t LDS_TABLE_BYTES = 144 * 1024;
+template <class Src>
+__global__ __launch_bounds__(LWG) void k_query_lds(Src src, int64_t n, int kshift,
+                                                   const uint64_t* __restrict__ st, int64_t nb,
+                                                   int64_t words, const int32_t* __restrict__ L,
+                                                   const int32_t* __restrict__ R, int64_t q,
+                                                   int32_t* __restrict__ out,
+                                                   unsigned long long* __restrict__ bad_count,
+                                                   unsigned long long* __restrict__ stats) {
+  __shared__ __align__(16) uint64_t s_st[LDS_TABLE_BYTES / 8];
+  const int lane = lane_id();
+  const int64_t total = (q + 63) >> 6;
+  const int64_t stride = (int64_t)gridDim.x * (LWG / 64);
+  int64_t w = (int64_t)blockIdx.x * (LWG / 64) +
+              __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  // this wave's queries two rounds ahead are in flight while it answers
+  // the current ones (the first two go out before the table copy)
+  int32_t l1 = 0, r1 = -1, l2 = 0, r2 = -1;
+  auto fetch = [&](int64_t ww, int32_t& l, int32_t& r) {
+    const int64_t i = ww * 64 + lane;
+    const bool in = ww < total && i < q;
+    l = in ? __builtin_nontemporal_load(L + i) : 0;
+    r = in ? __builtin_nontemporal_load(R + i) : -1;
+  };
+  fetch(w, l1, r1);
+  fetch(w + stride, l2, r2);
+  // the table, 16 bytes a load, all of a thread's loads in flight together
+  // (the table starts on a 256-byte boundary)
+  constexpr int PER = (int)(LDS_TABLE_BYTES / 16 / LWG);
+  const int64_t pairs = words >> 1;
+  v2u64 t[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int64_t idx = threadIdx.x + (int64_t)u * LWG;
+    if (idx < pairs) t[u] = reinterpret_cast<const v2u64*>(st)[idx];
+  }
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int64_t idx = threadIdx.x + (int64_t)u * LWG;
+    if (idx < pairs) reinterpret_cast<v2u64*>(s_st)[idx] = t[u];
+  }
+  if ((words & 1) && threadIdx.x == 0) s_st[words - 1] = st[words - 1];
+  __syncthreads();
+  // the table reads in the LDS address space (ds loads, not flat ones)
+  using LdsPtr = const __attribute__((address_space(3))) uint64_t*;
+  const LdsPtr lds_table = (LdsPtr)s_st;
+  for (; w < total; w += stride) {  // the same trip count for the whole wave
+    const int64_t i = w * 64 + lane;
+    const bool live = i < q;
+    const int64_t l = l1, r = r1;
+    l1 = l2;
+    r1 = r2;
+    fetch(w + 2 * stride, l2, r2);
+    query_core(src, n, n, kshift, lds_table, nb, l, r, l, r, live, out + (live ? i : 0),
+               bad_count, stats);
+  }
+}
+
 // Every query of a batch of tables (plain path): global query g belongs to
 // the table whose range of the concatenated query list holds it.
 // Queries of a batch: wave w does job w, 64 consecutive queries of one
@@ -581,11 +651,48 @@ hipError_t launch_query_segments(const ArrayDesc* tables, const int64_t* seg_pre
   return hipSuccess;
 }
 
+// Whether a plain-method batch takes k_query_lds: a doubling table of at
+// most LDS_TABLE_BYTES, and enough queries to pay for one copy of it per CU.
+// Returns the table's words (levels x nb), else 0.
+constexpr int64_t LDS_MIN_QUERIES = 1 << 21;
+int64_t lds_table_words(int64_t nb, int lg, int64_t q) {
+  if (lg != 1 || q < LDS_MIN_QUERIES || nb < 1) return 0;
+  int levels = 1;  // floor(log2(nb - 2)) + 1 levels (one for nb <= 3)
+  if (nb > 3) {
+    levels = 0;
+    for (int64_t x = nb - 2; x; x >>= 1) ++levels;
+  }
+  const int64_t words = nb * levels;
+  return words * 8 <= LDS_TABLE_BYTES ? words : 0;
+}
+
+int lds_grid(int64_t q) {
+  static int cus[64] = {};
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  if (dev < 0 || dev >= 64) dev = 0;
+  if (!cus[dev]) {
+    int c = 0;
+    if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c < 1)
+      c = 256;
+    cus[dev] = c;
+  }
+  const int64_t waves = (q + 63) / 64;
+  const int64_t need = (waves + LWG / 64 - 1) / (LWG / 64);
+  return (int)(need < cus[dev] ? need : cus[dev]);
+}
+
 hipError_t launch_query_full(const int32_t* A, int64_t n, int kshift, const uint64_t* st,
                              int64_t nb, const int32_t* L, const int32_t* R, int64_t q,
                              int32_t* out, int64_t* bad_count, uint64_t* stats,
                              hipStream_t stream, int lg, const uint64_t* rec, int rlev) {
   if (q <= 0) return hipSuccess;
+  if (const int64_t words = lds_table_words(nb, lg, q)) {
+    RMQ_TRY(launch(k_query_lds<SrcA>, dim3((unsigned)lds_grid(q)), dim3(LWG), 0,
+                   stream, SrcA{A, n}, n, kshift, st, nb, words, L, R, q,
+                   out, (unsigned long long*)bad_count, (unsigned long long*)stats));
+    return hipGetLastError();
+  }
   const int64_t grid = (q + WG - 1) / WG;
   RMQ_TRY(launch(k_query<SrcA>, dim3((unsigned)grid), dim3(WG), 0, stream, SrcA{A, n}, n, n,
                  kshift, st, nb, L, R, static_cast<const int32_t*>(nullptr), q, out,
@@ -600,8 +707,15 @@ hipError_t launch_query_full2(const int32_t* A, int64_t n, int kshift, const uin
                               uint64_t* stats, hipStream_t stream, int lg, const uint64_t* rec,
                               int rlev) {
   if (q <= 0) return hipSuccess;
-  const int64_t grid = (q + WG - 1) / WG;
   const int64_t nsub = (n + (1ll << k1shift) - 1) >> k1shift;
+  if (const int64_t words = lds_table_words(nb, lg, q)) {
+    RMQ_TRY(launch(k_query_lds<SrcA2>, dim3((unsigned)lds_grid(q)), dim3(LWG), 0,
+                   stream, SrcA2{SrcA{A, n}, sub, nsub, k1shift}, n,
+                   kshift, st, nb, words, L, R, q, out, (unsigned long long*)bad_count,
+                   (unsigned long long*)stats));
+    return hipGetLastError();
+  }
+  const int64_t grid = (q + WG - 1) / WG;
   RMQ_TRY(launch(k_query<SrcA2>, dim3((unsigned)grid), dim3(WG), 0, stream,
                  SrcA2{SrcA{A, n}, sub, nsub, k1shift}, n, n, kshift, st, nb, L, R,
                  static_cast<const int32_t*>(nullptr), q, out, (unsigned long long*)bad_count,
