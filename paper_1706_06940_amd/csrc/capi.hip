@@ -109,15 +109,36 @@ int32_t default_block_two_level(int64_t n, int32_t k1) {
   return (int32_t)k;
 }
 
-// The contracted method's default is one block level over A_Q; two levels
-// (sub_block_size) are taken only when asked.  Measured at n = 1e8 with
-// k1 = 512 under k = 8 times the one-level block size, whole jobs: uniform
-// queries gain from q = 1e6 (q = 1e7: 1.114 vs 1.142 ms; the permutation
-// array 1.120 vs 1.143), but the skewed mix at n = 1e9 (half ranges of at
-// most 1024 elements, q = 1e7) loses (3.58 vs 3.25 ms): a short range is a
-// few entries of A_Q, whose k1-block minimum rarely lies inside it, so the
-// sub-block lookup only adds a dependent load before each scan.
-int32_t default_sub_block_contracted(int64_t) { return 0; }
+// The contracted method's default is one block level over A_Q below
+// q = 2^22 queries.  From there it takes two levels, k1 = 256 under blocks
+// of at least 16384 entries, as few as keep the block table within the LDS
+// of the query kernel that copies it (see launch_query_contracted).
+// Measured at n = 1e8, q = 1e7, whole jobs: uniform queries 0.839 ms (one
+// level, k = 2048, gathered table and query records) -> 0.760 ms
+// ((16384, 256), table in LDS); (16384, 512) 0.759, (32768, 512) 0.783,
+// (8192, 256) 0.806 (table too large for LDS).  A mix with half the ranges of
+// at most 1024 elements loses: 1.610 -> 1.730 ms (short ranges are a few
+// entries of A_Q whose block minimum rarely lies inside them, so they are
+// scanned through the k1-block minima); callers with such mixes can pass
+// block_size and sub_block_size.  (Earlier, with the gathered table: k1 = 512
+// under k = 8 times the one-level size gained 1.142 -> 1.114 ms at q = 1e7
+// and lost on the skewed mix at n = 1e9, 3.25 -> 3.58 ms.)
+constexpr int64_t CONTRACTED_TWO_LEVEL_Q = 1 << 22;
+int32_t default_sub_block_contracted(int64_t q) { return q >= CONTRACTED_TWO_LEVEL_Q ? 256 : 0; }
+int32_t default_block_two_level_contracted(int64_t q) {
+  const int64_t m = 2 * q;  // entries of A_Q, at most
+  int64_t k = 16384;
+  for (;;) {
+    const int64_t nb = (m + k - 1) / k;
+    int levels = 1;
+    if (nb > 3) {
+      levels = 0;
+      for (int64_t x = nb - 2; x; x >>= 1) ++levels;
+    }
+    if (nb * levels * 8 <= 144 * 1024 || k >= RMQ_MAX_BLOCK) return (int32_t)k;
+    k *= 2;
+  }
+}
 
 // Batched items: blocks per array, the largest one-level block, and the k1
 // given above it.
@@ -143,7 +164,9 @@ rmq_status make_plan(int64_t n, int64_t q, const rmq_options* opt, Plan* p,
     // two block levels (k1 < k): over A, or over A_Q for the contracted method
     if (!is_pow2_block(k1)) return RMQ_ERR_INVALID_ARG;
     const bool con = path == RMQ_PATH_CONTRACTED;
-    if (k == 0) k = default_block_two_level(con ? 2 * q : n, k1);
+    if (k == 0)
+      k = con && k1 == default_sub_block_contracted(q) ? default_block_two_level_contracted(q)
+                                                       : default_block_two_level(con ? 2 * q : n, k1);
     if (k1 >= k) return RMQ_ERR_INVALID_ARG;
     p->path = con ? RMQ_PATH_CONTRACTED : RMQ_PATH_FULL;
     p->k = k;
@@ -527,7 +550,7 @@ int32_t rmq_default_block(int64_t n, int64_t q, int32_t path) {
   if (path == RMQ_PATH_FULL) return default_block_full(n);
   if (path == RMQ_PATH_CONTRACTED) {
     const int32_t k1 = default_sub_block_contracted(q);
-    return k1 ? default_block_two_level(2 * q, k1) : default_block_contracted(q);
+    return k1 ? default_block_two_level_contracted(q) : default_block_contracted(q);
   }
   return 0;
 }

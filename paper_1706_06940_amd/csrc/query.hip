@@ -480,31 +480,43 @@ __global__ __launch_bounds__(WG) void k_query(Src src, int64_t src_len, int64_t 
 // against 16 us gathering).
 constexpr int LWG = 1024;
 constexpr int64_t LDS_TABLE_BYTES = 144 * 1024;
+// src_len: source entries (n, or 2q - 1 for A_Q); LR: the contracted ranges
+// (null for the plain method); fail: the endpoint sort's abort word (null,
+// or when set every query is answered -1 and counted invalid).
 template <class Src>
-__global__ __launch_bounds__(LWG) void k_query_lds(Src src, int64_t n, int kshift,
-                                                   const uint64_t* __restrict__ st, int64_t nb,
-                                                   int64_t words, const int32_t* __restrict__ L,
-                                                   const int32_t* __restrict__ R, int64_t q,
+__global__ __launch_bounds__(LWG) void k_query_lds(Src src, int64_t src_len, int64_t n,
+                                                   int kshift, const uint64_t* __restrict__ st,
+                                                   int64_t nb, int64_t words,
+                                                   const int32_t* __restrict__ L,
+                                                   const int32_t* __restrict__ R,
+                                                   const int32_t* __restrict__ LR, int64_t q,
                                                    int32_t* __restrict__ out,
                                                    unsigned long long* __restrict__ bad_count,
-                                                   unsigned long long* __restrict__ stats) {
+                                                   unsigned long long* __restrict__ stats,
+                                                   const uint32_t* __restrict__ fail) {
   __shared__ __align__(16) uint64_t s_st[LDS_TABLE_BYTES / 8];
   const int lane = lane_id();
   const int64_t total = (q + 63) >> 6;
   const int64_t stride = (int64_t)gridDim.x * (LWG / 64);
   int64_t w = (int64_t)blockIdx.x * (LWG / 64) +
               __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const bool failed = fail && *fail != 0;  // uniform: one scalar load
   // this wave's queries two rounds ahead are in flight while it answers
   // the current ones (the first two go out before the table copy)
-  int32_t l1 = 0, r1 = -1, l2 = 0, r2 = -1;
-  auto fetch = [&](int64_t ww, int32_t& l, int32_t& r) {
-    const int64_t i = ww * 64 + lane;
-    const bool in = ww < total && i < q;
-    l = in ? __builtin_nontemporal_load(L + i) : 0;
-    r = in ? __builtin_nontemporal_load(R + i) : -1;
+  struct Q {
+    int32_t l, r;
+    int64_t c;  // the contracted range pair (li low, ri high)
   };
-  fetch(w, l1, r1);
-  fetch(w + stride, l2, r2);
+  Q q1{0, -1, 0}, q2{0, -1, 0};
+  auto fetch = [&](int64_t ww, Q& x) {
+    const int64_t i = ww * 64 + lane;
+    const bool in = ww < total && i < q && !failed;
+    x.l = in ? __builtin_nontemporal_load(L + i) : 0;
+    x.r = in ? __builtin_nontemporal_load(R + i) : -1;
+    x.c = in && LR ? __builtin_nontemporal_load(reinterpret_cast<const int64_t*>(LR) + i) : 0;
+  };
+  fetch(w, q1);
+  fetch(w + stride, q2);
   // the table, 16 bytes a load, all of a thread's loads in flight together
   // (the table starts on a 256-byte boundary)
   constexpr int PER = (int)(LDS_TABLE_BYTES / 16 / LWG);
@@ -528,12 +540,13 @@ __global__ __launch_bounds__(LWG) void k_query_lds(Src src, int64_t n, int kshif
   for (; w < total; w += stride) {  // the same trip count for the whole wave
     const int64_t i = w * 64 + lane;
     const bool live = i < q;
-    const int64_t l = l1, r = r1;
-    l1 = l2;
-    r1 = r2;
-    fetch(w + 2 * stride, l2, r2);
-    query_core(src, n, n, kshift, lds_table, nb, l, r, l, r, live, out + (live ? i : 0),
-               bad_count, stats);
+    const int64_t l = q1.l, r = q1.r;
+    const int64_t li = LR ? (int64_t)(int32_t)(uint32_t)q1.c : l;
+    const int64_t ri = LR ? (int64_t)(int32_t)(uint32_t)(q1.c >> 32) : r;
+    q1 = q2;
+    fetch(w + 2 * stride, q2);
+    query_core(src, src_len, n, kshift, lds_table, nb, l, r, li, ri, live,
+               out + (live ? i : 0), bad_count, stats);
   }
 }
 
@@ -688,9 +701,10 @@ hipError_t launch_query_full(const int32_t* A, int64_t n, int kshift, const uint
                              hipStream_t stream, int lg, const uint64_t* rec, int rlev) {
   if (q <= 0) return hipSuccess;
   if (const int64_t words = lds_table_words(nb, lg, q)) {
-    RMQ_TRY(launch(k_query_lds<SrcA>, dim3((unsigned)lds_grid(q)), dim3(LWG), 0,
-                   stream, SrcA{A, n}, n, kshift, st, nb, words, L, R, q,
-                   out, (unsigned long long*)bad_count, (unsigned long long*)stats));
+    RMQ_TRY(launch(k_query_lds<SrcA>, dim3((unsigned)lds_grid(q)), dim3(LWG), 0, stream,
+                   SrcA{A, n}, n, n, kshift, st, nb, words, L, R,
+                   static_cast<const int32_t*>(nullptr), q, out, (unsigned long long*)bad_count,
+                   (unsigned long long*)stats, static_cast<const uint32_t*>(nullptr)));
     return hipGetLastError();
   }
   const int64_t grid = (q + WG - 1) / WG;
@@ -709,10 +723,10 @@ hipError_t launch_query_full2(const int32_t* A, int64_t n, int kshift, const uin
   if (q <= 0) return hipSuccess;
   const int64_t nsub = (n + (1ll << k1shift) - 1) >> k1shift;
   if (const int64_t words = lds_table_words(nb, lg, q)) {
-    RMQ_TRY(launch(k_query_lds<SrcA2>, dim3((unsigned)lds_grid(q)), dim3(LWG), 0,
-                   stream, SrcA2{SrcA{A, n}, sub, nsub, k1shift}, n,
-                   kshift, st, nb, words, L, R, q, out, (unsigned long long*)bad_count,
-                   (unsigned long long*)stats));
+    RMQ_TRY(launch(k_query_lds<SrcA2>, dim3((unsigned)lds_grid(q)), dim3(LWG), 0, stream,
+                   SrcA2{SrcA{A, n}, sub, nsub, k1shift}, n, n, kshift, st, nb, words, L, R,
+                   static_cast<const int32_t*>(nullptr), q, out, (unsigned long long*)bad_count,
+                   (unsigned long long*)stats, static_cast<const uint32_t*>(nullptr)));
     return hipGetLastError();
   }
   const int64_t grid = (q + WG - 1) / WG;
@@ -750,6 +764,20 @@ hipError_t launch_query_contracted(const uint64_t* aq, int64_t m, int64_t n, int
                                    int lg, const uint64_t* rec, int rlev, const uint64_t* sub,
                                    int k1shift, const uint32_t* fail) {
   if (q <= 0) return hipSuccess;
+  if (const int64_t words = lds_table_words(nb, lg, q)) {
+    if (sub) {
+      const int64_t nsub = (m + (1ll << k1shift) - 1) >> k1shift;
+      RMQ_TRY(launch(k_query_lds<SrcKeys2>, dim3((unsigned)lds_grid(q)), dim3(LWG), 0, stream,
+                     SrcKeys2{SrcKeys{aq, m}, sub, nsub, k1shift}, m, n, kshift, st, nb, words, L,
+                     R, LR, q, out, (unsigned long long*)bad_count, (unsigned long long*)stats,
+                     fail));
+    } else {
+      RMQ_TRY(launch(k_query_lds<SrcKeys>, dim3((unsigned)lds_grid(q)), dim3(LWG), 0, stream,
+                     SrcKeys{aq, m}, m, n, kshift, st, nb, words, L, R, LR, q, out,
+                     (unsigned long long*)bad_count, (unsigned long long*)stats, fail));
+    }
+    return hipGetLastError();
+  }
   const int64_t grid = (q + WG - 1) / WG;
   if (sub) {
     const int64_t nsub = (m + (1ll << k1shift) - 1) >> k1shift;

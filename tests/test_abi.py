@@ -197,17 +197,30 @@ def test_contracted_default_block_and_workspace():
 
 
 def test_contracted_default_plan():
-    """The contracted method's default is one block level (two only when
-    sub_block_size is given), with k about sqrt(2q)/2."""
+    """The contracted method's default: one block level with k about sqrt(2q)/2
+    below 2^22 queries; from there two levels, k1 = 256 under the smallest
+    block from 16384 whose table over the 2q - 1 entries of A_Q fits 144 KiB
+    (levels = floor(log2(nb - 2)) + 1 of 8-byte keys)."""
     n = 10 ** 8
-    for q in (1, 1000, 10 ** 6, 10 ** 7):
+    for q in (1, 1000, 10 ** 6, (1 << 22) - 1):
         assert rmq.default_sub_block(n, q, "contracted") == 0
+    for q in (1, 1000, 10 ** 6, 10 ** 7):
         assert rmq.default_sub_block(n, q, "full") == 0
     assert rmq.default_block(n, 10 ** 6, "contracted") == 512
-    assert rmq.default_block(n, 10 ** 7, "contracted") == 2048
+    for q in (1 << 22, 10 ** 7, 5 * 10 ** 7, 3 * 10 ** 8):
+        assert rmq.default_sub_block(n, q, "contracted") == 256
+        k = rmq.default_block(n, q, "contracted")
+        nb = -(-2 * q // k)
+        levels = 1 if nb <= 3 else (nb - 2).bit_length()
+        assert k >= 16384 and nb * levels * 8 <= 144 * 1024
+        if k > 16384:  # the smallest such block
+            nb2 = -(-2 * q // (k // 2))
+            assert nb2 * (nb2 - 2).bit_length() * 8 > 144 * 1024
+    assert rmq.default_block(n, 10 ** 7, "contracted") == 16384
     k = rmq.default_block(n, 10 ** 7, "contracted")
+    k1 = rmq.default_sub_block(n, 10 ** 7, "contracted")
     assert rmq.workspace_bytes(n, 10 ** 7, "contracted") == \
-        rmq.workspace_bytes(n, 10 ** 7, "contracted", k)
+        rmq.workspace_bytes(n, 10 ** 7, "contracted", k, sub_block_size=k1)
 
 
 def test_build_bytes_is_the_index_footprint():

@@ -27,9 +27,11 @@ def forced_abort():
 
 
 # list lengths 2q on both sides of the tile-size switches (1e5, 4e5 items)
-# and of the remap-window path (2q >= 2^22)
+# and of the remap-window path (2q >= 2^20), and a batch of 2^22 queries or
+# more, whose default table over A_Q the query kernel keeps in LDS
 @pytest.mark.parametrize("n,q", [(1000, 1), (100_003, 20_000), (1_000_003, 150_000),
-                                 (3_000_017, 1_000_000), (10_000_019, 2_200_000)])
+                                 (3_000_017, 1_000_000), (10_000_019, 2_200_000),
+                                 (10_000_019, 4_300_000)])
 def test_contracted_batch_reports_every_query(orc, forced_abort, n, q):
     d = need_gpu()
     say("sort_abort_contracted", n, q)
