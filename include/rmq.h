@@ -236,9 +236,10 @@ int32_t rmq_default_block(int64_t n, int64_t q, int32_t path);
  * CONTRACTED 0 below 2^22 queries and 256 from there (then rmq_default_block
  * gives the smallest block from 16384 whose table over A_Q fits 144 KiB, so
  * that the query kernel keeps it in LDS).  Two levels over A_Q gain for
- * uniform queries but lose on mixes of short ranges (n = 1e8, q = 1e7:
- * 0.84 -> 0.76 ms uniform, 1.61 -> 1.73 ms with half short ranges); such
- * callers can pass the block sizes.  0 on invalid arguments. */
+ * uniform queries and can lose on mixes of short ranges (q = 1e7; n = 1e8:
+ * 0.84 -> 0.76 ms uniform, 1.61 -> 1.73 ms with half short ranges; n = 1e9
+ * with half short ranges: 2.48 -> 1.89 ms); such callers can pass the block
+ * sizes.  0 on invalid arguments. */
 int32_t rmq_default_sub_block(int64_t n, int64_t q, int32_t path);
 
 /* ----------------------------------------------------------------------------
