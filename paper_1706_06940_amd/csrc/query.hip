@@ -81,6 +81,39 @@ struct SrcA {
     }
     return best;
   }
+  // Queued pieces are read several at a time, each by a group of G lanes
+  // (grouped_scans); an entry is 4 bytes.
+  static constexpr bool kGroupScans = true;
+  static constexpr int kEntryShift = 2;
+  // This lane's share of the min key over A[lo..hi] when G lanes read it
+  // together: four 16-byte loads per lane in flight, 16 G elements a pass
+  // (positions fit 32 bits: n < 2^31).
+  template <int G>
+  __device__ uint64_t group_part(uint32_t lo, uint32_t hi, int gl) const {
+    uint64_t best = KEY_NONE;
+    if (((uintptr_t)A & 15) == 0) {
+      for (uint32_t base = lo & ~3u; base <= hi; base += 16 * G) {
+        v4i32 x[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) x[u] = load4(base + (uint32_t)(u * G + gl) * 4, hi);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const uint32_t e = base + (uint32_t)(u * G + gl) * 4 + c;
+            if (e >= lo && e <= hi) best = umin64(best, make_key(x[u][c], e));
+          }
+      }
+    } else {
+      for (uint32_t e = lo + gl; e <= hi; e += G) best = umin64(best, make_key(A[e], e));
+    }
+    return best;
+  }
+  // lane src_lane's source, per lane (lanes may take different sources)
+  __device__ __forceinline__ SrcA gather(int src_lane) const {
+    return {reinterpret_cast<const int32_t*>(__shfl((long long)(uintptr_t)A, src_lane)),
+            (int64_t)__shfl((long long)len, src_lane)};
+  }
   // This lane's source as seen by the whole wave (for a wave-wide scan).
   static constexpr bool kIndexIsPos = true;  // entry index = position in A
   // the source bound to one query's range in A (used by two-level sources)
@@ -144,6 +177,36 @@ struct SrcKeys {
       for (int u = 0; u < 8; ++u) best = umin64(best, x[u]);
     }
     return best;
+  }
+  static constexpr bool kGroupScans = true;  // as for the plain array; 8-byte entries
+  static constexpr int kEntryShift = 3;
+  // This lane's share of the min over S[lo..hi] when G lanes read it
+  // together: four 16-byte loads per lane in flight, 8 G entries a pass
+  // (indices fit 32 bits: A_Q has fewer than 2^31 entries).
+  template <int G>
+  __device__ uint64_t group_part(uint32_t lo, uint32_t hi, int gl) const {
+    uint64_t best = KEY_NONE;
+    if (((uintptr_t)S & 15) == 0) {
+      for (uint32_t base = lo & ~1u; base <= hi; base += 8 * G) {
+        v2u64 x[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) x[u] = load2(base + (uint32_t)(u * G + gl) * 2, hi);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            const uint32_t e = base + (uint32_t)(u * G + gl) * 2 + c;
+            if (e >= lo && e <= hi) best = umin64(best, x[u][c]);
+          }
+      }
+    } else {
+      for (uint32_t e = lo + gl; e <= hi; e += G) best = umin64(best, S[e]);
+    }
+    return best;
+  }
+  __device__ __forceinline__ SrcKeys gather(int src_lane) const {
+    return {reinterpret_cast<const uint64_t*>(__shfl((long long)(uintptr_t)S, src_lane)),
+            (int64_t)__shfl((long long)len, src_lane)};
   }
   static constexpr bool kIndexIsPos = false;  // keys carry positions in A
   __device__ __forceinline__ SrcKeys with_query(int64_t, int64_t) const { return *this; }
@@ -233,6 +296,7 @@ struct Src2 {
   // minima and at most two pieces of at most k1 elements (only while k1 <=
   // 256: longer pieces read by one lane cost more than wave-wide scans).
   static constexpr bool kLaneScans = true;
+  static constexpr bool kGroupScans = false;  // its pieces are read in two steps
   __device__ __forceinline__ int64_t lane_cost(int64_t lo, int64_t hi) const {
     if (s1 > 8) return INT64_MAX;
     const int64_t elems = hi - lo + 1, two = 2ll << s1;
@@ -280,6 +344,64 @@ using SrcA2 = Src2<SrcA>;
 using SrcKeys2 = Src2<SrcKeys>;
 
 // --- the query step ----------------------------------------------------------
+// The queued partial-block pieces of a wave (pl: lanes with a left piece
+// [loL, hiL], pr: with a right piece [loR, hiR]) read 64 / G at a time: group
+// g (lanes gG .. gG + G - 1) reads the g-th queued piece, then the group's
+// minimum goes to the lane that queued it.  One round of loads serves up to
+// 64 / G pieces where a wave-wide scan serves one (G = 16 or 32: pieces of at
+// most 1 or 2 KB).
+template <int G, class Src>
+__device__ __forceinline__ void grouped_scans(const Src& src, uint64_t pl, uint64_t pr,
+                                              uint32_t loL, uint32_t hiL, uint32_t loR,
+                                              uint32_t hiR, int lane, uint64_t& best,
+                                              uint64_t& n_scans, uint64_t& n_elems) {
+  constexpr int S = 64 / G;
+  const int gi = lane / G, gl = lane % G;
+  while (pl | pr) {
+    int who[S];
+    bool right[S];
+#pragma unroll
+    for (int g = 0; g < S; ++g) {
+      who[g] = -1;
+      right[g] = false;
+      if (pl) {
+        who[g] = __builtin_ctzll(pl);
+        pl &= pl - 1;
+      } else if (pr) {
+        who[g] = __builtin_ctzll(pr);
+        pr &= pr - 1;
+        right[g] = true;
+      }
+    }
+    int mine = who[0];
+    bool mr = right[0];
+#pragma unroll
+    for (int g = 1; g < S; ++g)
+      if (gi == g) {
+        mine = who[g];
+        mr = right[g];
+      }
+    const int sl = mine < 0 ? lane : mine;
+    const uint32_t l_lo = (uint32_t)__shfl((int)loL, sl), l_hi = (uint32_t)__shfl((int)hiL, sl);
+    const uint32_t r_lo = (uint32_t)__shfl((int)loR, sl), r_hi = (uint32_t)__shfl((int)hiR, sl);
+    uint32_t lo = mr ? r_lo : l_lo, hi = mr ? r_hi : l_hi;
+    if (mine < 0) {  // no piece for this group: a range no pass enters
+      lo = 4;
+      hi = 0;
+    }
+    uint64_t m = src.gather(sl).template group_part<G>(lo, hi, gl);
+    m = group_min_u64<G>(m);
+#pragma unroll
+    for (int g = 0; g < S; ++g) {
+      if (who[g] < 0) break;
+      const uint64_t r = (uint64_t)readlane64((int64_t)m, g * G + G - 1);
+      if (lane == who[g]) best = umin64(best, r);
+      n_scans += 1;
+      n_elems += (uint32_t)__builtin_amdgcn_readlane((int)(hi - lo + 1), g * G);
+    }
+  }
+}
+
 // One lane's query [l, r] (positions in A, validated here) over source
 // entries [li, ri] of its table (st: level-major, nb blocks of 2^kshift
 // entries).  All 64 lanes of the wave must call this together: the partial
@@ -371,6 +493,29 @@ __device__ __forceinline__ void query_core(const Src& src, int64_t src_len, int6
       best = umin64(best, qsrc.lane_scan(loL, hiL, best, lane_reads));
       lane_scans += 1;
       needL = false;
+    }
+  }
+  if constexpr (Src::kGroupScans) {
+    const uint64_t pl = ballot(needL), pr = ballot(needR);
+    if (pl | pr) {
+      // the widest queued piece sets the group size: G lanes read 64 G bytes
+      // a pass; pieces over 2 KB are read wave-wide below
+      uint32_t len = 0;
+      if (needL) len = (uint32_t)(hiL - loL + 1);
+      if (needR && (uint32_t)(hiR - loR + 1) > len) len = (uint32_t)(hiR - loR + 1);
+      for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t o = (uint32_t)__shfl_xor((int)len, d);
+        len = o > len ? o : len;
+      }
+      const uint64_t bytes = (uint64_t)len << Src::kEntryShift;
+      const uint32_t a = (uint32_t)loL, b = (uint32_t)hiL, c = (uint32_t)loR, e = (uint32_t)hiR;
+      if (bytes <= 2048) {
+        if (bytes <= 1024)
+          grouped_scans<16>(qsrc, pl, pr, a, b, c, e, lane, best, n_scans, n_elems);
+        else
+          grouped_scans<32>(qsrc, pl, pr, a, b, c, e, lane, best, n_scans, n_elems);
+        needL = needR = false;
+      }
     }
   }
   uint64_t pend = ballot(needL);
