@@ -159,19 +159,21 @@ __device__ __forceinline__ void load_tile(const int32_t* __restrict__ A, int64_t
   }
 }
 
-// Tile offsets of the endpoint slots j = jlo + lane + 64 k (k < KREG) of
-// the tile starting at t0, T for slots past jend; only the rounds the tile
-// has are loaded.
+// Positions of the endpoint slots j = jlo + lane + 64 k (k < KREG) of the
+// tile starting at t0, t0 + T for slots past jend; only the rounds the tile
+// has are loaded.  The values are used as loaded (the tile offset is taken
+// where the tile is processed), so that no wait for these loads -- and with
+// it for the next tile's values, loaded just before -- comes here.
 __device__ __forceinline__ void load_ends(const int32_t* __restrict__ E, uint32_t jlo,
                                           uint32_t jend, uint32_t t0, int lane,
-                                          int32_t (&ep)[KREG]) {
+                                          uint32_t (&ep)[KREG]) {
   const uint32_t rounds = (jend - jlo + 63u) >> 6;  // wave-uniform
 #pragma unroll
   for (int k = 0; k < KREG; ++k) {
-    int32_t v = T;
+    uint32_t v = t0 + (uint32_t)T;
     if ((uint32_t)k < rounds) {
       const uint32_t j = jlo + (uint32_t)lane + 64u * k;
-      if (j < jend) v = (int32_t)((uint32_t)E[j] - t0);
+      if (j < jend) v = (uint32_t)E[j];
     }
     ep[k] = v;
   }
@@ -216,7 +218,7 @@ __global__ __launch_bounds__(WG) void k_contract(const int32_t* __restrict__ A, 
   if (ts(0) == ts(cnt) && (ts(0) == 0u || ts(0) >= Mu)) return;
   int32_t* xs = s_x[wave];
 
-  int32_t en[KREG];
+  uint32_t en[KREG];  // the next tile's endpoint positions (load_ends)
   load_ends(E, ts(0), ts(1), (uint32_t)(tb << TSHIFT), lane, en);
   // the area open at the current tile's start: its index, its min over the
   // part already seen in this wave, and whether it opened before the wave
@@ -249,7 +251,13 @@ __global__ __launch_bounds__(WG) void k_contract(const int32_t* __restrict__ A, 
     const bool more = i + 1 < cnt;
     int32_t ep[KREG];
 #pragma unroll
-    for (int k = 0; k < KREG; ++k) ep[k] = en[k];
+    for (int k = 0; k < KREG; ++k) {
+      ep[k] = (int32_t)(en[k] - t0);  // tile offsets
+      // taken here, while the only loads in flight are this tile's: moved
+      // down to their use, the subtraction would wait for the next tile's
+      // loads as well
+      __asm__ volatile("" : "+v"(ep[k]));
+    }
 
     if (jlo == jend) {
       // no endpoint inside: the tile lies in the open area (none before E_0
