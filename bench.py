@@ -539,7 +539,8 @@ def bench_small(d, warm_reps=20, flushed_reps=7):
 def bench_permutation(d, qs, reps=5):
     """The paper's own array workload: 1..n after n/2 random pair swaps (no
     ties), n = 1e8, with uniform swapped queries over the same q sweep; both
-    methods with the planner's block sizes; whole offline jobs (mean of
+    methods with the planner's block sizes, and the comparison system
+    ST-RMQ_CON (Section 2, Fig. 1's baseline); whole offline jobs (mean of
     `reps`)."""
     import torch
 
@@ -561,9 +562,12 @@ def bench_permutation(d, qs, reps=5):
         if path_f != "full":
             k, k1 = rmq.default_block(n, q, "full"), 0
         outs = {}
-        for path in ("full", "contracted"):
-            kk = k if path == "full" else rmq.default_block(n, q, "contracted")
-            kk1 = k1 if path == "full" else rmq.default_sub_block(n, q, "contracted")
+        for path in ("full", "contracted", "st_con"):
+            if path == "st_con":  # the comparison system: no blocks
+                kk, kk1 = 0, 0
+            else:
+                kk = k if path == "full" else rmq.default_block(n, q, "contracted")
+                kk1 = k1 if path == "full" else rmq.default_sub_block(n, q, "contracted")
             out = torch.empty(q, dtype=torch.int32, device=d)
             run = lambda: rmq.query_batch(A, L, R, path=path, block_size=kk, sub_block_size=kk1,
                                           out=out)
@@ -573,10 +577,18 @@ def bench_permutation(d, qs, reps=5):
                                     "block_size": kk, "sub_block_size": kk1}
         res[f"full/q={q}"]["same_answers_as_contracted"] = bool(
             torch.equal(outs["full"], outs["contracted"]))
+        res[f"st_con/q={q}"]["same_answers_as_contracted"] = bool(
+            torch.equal(outs["st_con"], outs["contracted"]))
+        # the paper's Fig. 1 ratio (BbST_CON over ST-RMQ_CON), and the plain method's
+        st_ms = res[f"st_con/q={q}"]["ms"]
+        res[f"st_con/q={q}"]["contracted_speedup"] = round(st_ms / res[f"contracted/q={q}"]["ms"], 2)
+        res[f"st_con/q={q}"]["full_speedup"] = round(st_ms / res[f"full/q={q}"]["ms"], 2)
     del A
     torch.cuda.empty_cache()
     return {"workload": "n=1e8: 1..n after n/2 uniform pair swaps (the paper's array), "
-                        f"q={qs} uniform swapped queries", "results": res}
+                        f"q={qs} uniform swapped queries; st_con: the comparison system "
+                        "ST-RMQ_CON re-created on this GPU, with each method's speedup over it",
+            "results": res}
 
 
 def bench_skewed(d, reps=5):

@@ -83,7 +83,24 @@ typedef enum rmq_status {
 typedef enum rmq_path {
     RMQ_PATH_AUTO = 0,        /* planner picks FULL or CONTRACTED            */
     RMQ_PATH_FULL = 1,        /* Section 3.2                                 */
-    RMQ_PATH_CONTRACTED = 2   /* Section 3.1                                 */
+    RMQ_PATH_CONTRACTED = 2,  /* Section 3.1                                 */
+    RMQ_PATH_ST_CON = 3       /* Section 2: the comparison system
+                                 ST-RMQ_CON (Alzamel et al.'s contraction and
+                                 a Sparse Table over every entry), for
+                                 measuring the paper's method against it.
+                                 Its A_Q keeps each endpoint's element and
+                                 the region between neighbouring endpoints
+                                 (4q - 1 entries, from the sorted endpoints
+                                 instead of marks in A's top bits), the
+                                 table has floor(log2(4q - 1)) + 1 levels of
+                                 4q - 1 keys (the full table, not the cited
+                                 work's level-by-level reuse of one array),
+                                 and a query reads two entries.  Only
+                                 rmq_query_batch_ex / _noalloc and
+                                 rmq_workspace_bytes take it, with
+                                 block_size, sub_block_size and
+                                 table_arity_log2 0 and q <= 2^29; the
+                                 planner never picks it.                 */
 } rmq_path;
 
 /* Block sizes k are powers of two in [RMQ_MIN_BLOCK, RMQ_MAX_BLOCK]. */

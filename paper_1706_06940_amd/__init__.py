@@ -27,7 +27,7 @@ OK = 0
 STATUS = {0: "ok", 1: "invalid argument", 2: "out of device memory", 3: "HIP runtime error",
           4: "workspace too small", 5: "misaligned device pointer",
           6: "needs more than the fixed scratch array"}
-PATHS = {"auto": 0, "full": 1, "contracted": 2}
+PATHS = {"auto": 0, "full": 1, "contracted": 2, "st_con": 3}
 MIN_BLOCK = 16
 MAX_BLOCK = 1 << 24
 NUM_STAGES = 4

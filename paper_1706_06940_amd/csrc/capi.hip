@@ -146,11 +146,27 @@ constexpr int64_t BATCH_MAX_BLOCKS = 1024;
 constexpr int64_t BATCH_ONE_LEVEL_MAX_K = 4096;
 constexpr int64_t BATCH_SUB_BLOCK = 1024;
 
+// ST-RMQ_CON (Section 2) takes at most 2^29 queries: its doubled endpoint
+// list (4q entries) must index in 32 bits.
+constexpr int64_t ST_CON_MAX_Q = 1ll << 29;
+
 rmq_status make_plan(int64_t n, int64_t q, const rmq_options* opt, Plan* p,
-                     bool allow_two_level = true) {
+                     bool allow_two_level = true, bool allow_st_con = false) {
   int32_t path = opt ? opt->path : RMQ_PATH_AUTO;
   int32_t k = opt ? opt->block_size : 0;
   int32_t k1 = opt ? opt->sub_block_size : 0;
+  if (path == RMQ_PATH_ST_CON) {
+    // the comparison system: no blocks, one element table (doubling)
+    if (!allow_st_con || k != 0 || k1 != 0 || arity_lg(opt) != 1 || q > ST_CON_MAX_Q)
+      return RMQ_ERR_INVALID_ARG;
+    p->path = RMQ_PATH_ST_CON;
+    p->k = 1;
+    p->kshift = 0;
+    p->k1shift = -1;
+    p->lg = 1;
+    p->records = false;
+    return RMQ_OK;
+  }
   if (path == RMQ_PATH_CONTRACTED && k == 0 && k1 == 0 && allow_two_level)
     k1 = default_sub_block_contracted(q);
   if (path != RMQ_PATH_AUTO && path != RMQ_PATH_FULL && path != RMQ_PATH_CONTRACTED)
@@ -258,7 +274,40 @@ ConLayout con_layout(int64_t n, int64_t q, int64_t k, int k1shift, int lg, bool 
   return c;
 }
 
+// ST-RMQ_CON: the sorted endpoints (as for the contracted method), their
+// remap, the doubled list, the contraction's tile table and the element
+// table, whose level 0 is A_Q itself (and, before the contraction, the
+// remap's pair scratch: 2q items in 4q - 1 keys).
+struct StConLayout {
+  int64_t M, m;
+  int levels;
+  size_t off_E, off_sort, off_lr, off_E2, off_tiles, off_st, bytes;
+};
+
+StConLayout st_con_layout(int64_t n, int64_t q) {
+  StConLayout c{};
+  c.M = 2 * q;
+  c.m = 2 * c.M - 1;
+  c.levels = ilog2_i64(c.m) + 1;  // windows of every length up to m
+  size_t o = 0;
+  c.off_E = o;
+  o = align_up(o + sizeof(uint64_t) * (size_t)c.M);
+  c.off_sort = o;
+  o = align_up(o + sort_workspace_bytes(q));
+  c.off_lr = o;
+  o = align_up(o + sizeof(int32_t) * (size_t)c.M);
+  c.off_E2 = o;
+  o = align_up(o + sizeof(int32_t) * 2 * (size_t)c.M);
+  c.off_tiles = o;
+  o = align_up(o + contract_tile_start_bytes(n));
+  c.off_st = o;
+  o = align_up(o + sizeof(uint64_t) * (size_t)c.m * (size_t)c.levels);
+  c.bytes = o;
+  return c;
+}
+
 size_t plan_bytes(int64_t n, int64_t q, const Plan& p) {
+  if (p.path == RMQ_PATH_ST_CON) return st_con_layout(n, q).bytes;
   if (p.path == RMQ_PATH_FULL) return full_layout(n, p.k, p.k1shift, p.lg, p.records).bytes;
   return con_layout(n, q, p.k, p.k1shift, p.lg, p.records).bytes;
 }
@@ -438,6 +487,43 @@ rmq_status run_contracted(const int32_t* A, int64_t n, const int32_t* L, const i
   return RMQ_OK;
 }
 
+// ST-RMQ_CON (Section 2), re-created with this library's parts: the sort
+// and remap of the endpoints, the contraction over the doubled list (its
+// A_Q of 4q - 1 entries), the Sparse Table over every entry, two reads per
+// query.  Stages as for the contracted method.
+rmq_status run_st_con(const int32_t* A, int64_t n, const int32_t* L, const int32_t* R, int64_t q,
+                      int32_t* out, hipStream_t s, const rmq_options* opt, char* ws) {
+  rmq_timer* t = opt ? opt->timer : nullptr;
+  const StConLayout c = st_con_layout(n, q);
+  uint64_t* E = reinterpret_cast<uint64_t*>(ws + c.off_E);
+  int32_t* LR = reinterpret_cast<int32_t*>(ws + c.off_lr);
+  int32_t* E2 = reinterpret_cast<int32_t*>(ws + c.off_E2);
+  int32_t* tiles = reinterpret_cast<int32_t*>(ws + c.off_tiles);
+  uint64_t* st = reinterpret_cast<uint64_t*>(ws + c.off_st);
+  const uint32_t* fail = sort_abort_word(ws + c.off_sort, q);
+  ClockGuard guard;
+  stage_begin(t, 0);
+  hipError_t e =
+      launch_sort_endpoints(L, R, q, n, E, LR, st, ws + c.off_sort, sort_workspace_bytes(q), s);
+  if (e != hipSuccess) return from_hip(e);
+  stage_end(t, 0, s);
+  stage_begin(t, 1);
+  e = launch_double_ends(reinterpret_cast<const int32_t*>(E), c.M, E2, s);
+  if (e == hipSuccess) e = launch_contract(A, n, E2, c.M, st, tiles, s, fail);
+  if (e != hipSuccess) return from_hip(e);
+  stage_end(t, 1, s);
+  stage_begin(t, 2);
+  e = launch_sparse_table(st, c.m, c.levels, s);
+  if (e != hipSuccess) return from_hip(e);
+  stage_end(t, 2, s);
+  stage_begin(t, 3);
+  e = launch_query_st_elements(st, c.m, c.levels, L, R, LR, q, n, out,
+                               opt ? opt->bad_count : nullptr, s, fail);
+  if (e != hipSuccess) return from_hip(e);
+  stage_end(t, 3, s);
+  return RMQ_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -559,7 +645,7 @@ size_t rmq_workspace_bytes(int64_t n, int64_t q, const rmq_options* opt) {
   if (n < 1 || n > RMQ_MAX_N || q < 0 || q > RMQ_MAX_Q) return 0;
   if (q == 0) return 0;
   Plan p;
-  if (make_plan(n, q, opt, &p) != RMQ_OK) return 0;
+  if (make_plan(n, q, opt, &p, true, true) != RMQ_OK) return 0;
   return plan_bytes(n, q, p);
 }
 
@@ -571,7 +657,7 @@ rmq_status rmq_query_batch_ex(const int32_t* A, int64_t n, const int32_t* L, con
     return RMQ_ERR_MISALIGNED;
   if (opt && opt->workspace && !aligned_to(opt->workspace, ALIGN)) return RMQ_ERR_MISALIGNED;
   Plan p;
-  rmq_status st = make_plan(n, q, opt, &p);
+  rmq_status st = make_plan(n, q, opt, &p, true, true);
   if (st != RMQ_OK) return st;
   if (q == 0) return RMQ_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -589,8 +675,9 @@ rmq_status rmq_query_batch_ex(const int32_t* A, int64_t n, const int32_t* L, con
     ws = static_cast<char*>(w);
     own = true;
   }
-  st = p.path == RMQ_PATH_FULL ? run_full(A, n, L, R, q, out, s, opt, p, ws)
-                               : run_contracted(A, n, L, R, q, out, s, opt, p, ws);
+  st = p.path == RMQ_PATH_FULL       ? run_full(A, n, L, R, q, out, s, opt, p, ws)
+       : p.path == RMQ_PATH_ST_CON ? run_st_con(A, n, L, R, q, out, s, opt, ws)
+                                   : run_contracted(A, n, L, R, q, out, s, opt, p, ws);
   if (own) hipFreeAsync(ws, s);
   return st;
 }

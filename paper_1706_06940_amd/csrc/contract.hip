@@ -422,6 +422,33 @@ hipError_t launch_contract(const int32_t* A, int64_t n, const int32_t* E, int64_
   return hipSuccess;
 }
 
+// The comparison system ST-RMQ_CON (Section 2) marks the positions of A
+// that end a query and keeps, in A_Q, each marked element and, between two
+// marked positions, one entry for the region that separates them.  With
+// every sorted endpoint listed twice, the closed areas between neighbouring
+// entries of the list alternate between a marked element ([p, p]) and the
+// region up to the next marked position ([p, p'], which holds both marked
+// ends: that changes no answer, since every query that covers the region's
+// entry also covers the two element entries beside it), so the contraction
+// above builds that A_Q, 4q - 1 entries, from the doubled list.
+namespace {
+typedef int32_t v2i32 __attribute__((ext_vector_type(2)));
+__global__ __launch_bounds__(WG) void k_double_ends(const int32_t* __restrict__ E, int64_t M,
+                                                    int32_t* __restrict__ E2) {
+  const int64_t j = (int64_t)blockIdx.x * WG + threadIdx.x;
+  if (j >= M) return;
+  const int32_t p = E[j];
+  reinterpret_cast<v2i32*>(E2)[j] = v2i32{p, p};
+}
+}  // namespace
+
+hipError_t launch_double_ends(const int32_t* E, int64_t M, int32_t* E2, hipStream_t stream) {
+  if (M <= 0) return hipSuccess;
+  RMQ_TRY(launch(k_double_ends, dim3((unsigned)((M + WG - 1) / WG)), dim3(WG), 0, stream, E, M,
+                 E2));
+  return hipSuccess;
+}
+
 size_t contract_tile_start_bytes(int64_t n) {
   return sizeof(int32_t) * (size_t)((n + T - 1) / T + 1);
 }

@@ -203,6 +203,16 @@ size_t contract_tile_start_bytes(int64_t n);
 hipError_t launch_contract(const int32_t* A, int64_t n, const int32_t* E, int64_t q,
                            uint64_t* aq, int32_t* tile_start, hipStream_t stream,
                            const uint32_t* fail);
+// ST-RMQ_CON (Section 2): the 2q sorted endpoint positions E, each written
+// twice into E2 (4q entries, 8-byte aligned).
+hipError_t launch_double_ends(const int32_t* E, int64_t M, int32_t* E2, hipStream_t stream);
+// ST-RMQ_CON's queries: st is the Sparse Table over every entry of its A_Q
+// (m = 4q - 1 entries, `levels` levels); query i reads entries 2 LR[2i] ..
+// 2 LR[2i + 1] + 2.  fail as below.
+hipError_t launch_query_st_elements(const uint64_t* st, int64_t m, int levels, const int32_t* L,
+                                    const int32_t* R, const int32_t* LR, int64_t q, int64_t n,
+                                    int32_t* out, int64_t* bad_count, hipStream_t stream,
+                                    const uint32_t* fail);
 // fail: the endpoint sort's abort word; when it is set every query is
 // answered -1 and counted in bad_count.
 hipError_t launch_query_contracted(const uint64_t* aq, int64_t m, int64_t n, int kshift,

@@ -695,6 +695,46 @@ __global__ __launch_bounds__(LWG) void k_query_lds(Src src, int64_t src_len, int
   }
 }
 
+typedef uint32_t v2u32 __attribute__((ext_vector_type(2)));
+
+// ST-RMQ_CON's queries (Section 2; the comparison system): its A_Q holds,
+// for sorted endpoint slot s, the marked element at entry 2s and the region
+// up to slot s + 1 at entry 2s + 1, so query i (left end at slot LR[2i],
+// right end at slot LR[2i + 1] + 1) covers entries 2 LR[2i] .. 2 LR[2i + 1]
+// + 2, and the Sparse Table over every entry (Bender and Farach's doubling)
+// answers it with two reads, of the windows of 2^t entries at both ends.
+__global__ __launch_bounds__(WG) void k_query_st_elements(
+    const uint64_t* __restrict__ st, int64_t m, int levels, const int32_t* __restrict__ L,
+    const int32_t* __restrict__ R, const int32_t* __restrict__ LR, int64_t q, int64_t n,
+    int32_t* __restrict__ out, unsigned long long* __restrict__ bad_count,
+    const uint32_t* __restrict__ fail) {
+  const int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
+  const bool live = i < q;
+  const bool failed = fail && *fail != 0;
+  bool ok = false;
+  uint64_t best = KEY_NONE;
+  if (live) {
+    const int64_t l = __builtin_nontemporal_load(L + i), r = __builtin_nontemporal_load(R + i);
+    const v2u32 c = __builtin_nontemporal_load(reinterpret_cast<const v2u32*>(LR) + i);
+    const int64_t lo = 2 * (int64_t)(int32_t)c.x, hi = 2 * (int64_t)(int32_t)c.y + 2;
+    ok = !failed && 0 <= l && l <= r && r < n && 0 <= lo && lo <= hi && hi < m;
+    if (ok) {
+      const int t = ilog2_u64((uint64_t)(hi - lo + 1));
+      if (t < levels) {
+        const uint64_t* lev = st + (size_t)t * (size_t)m;
+        best = umin64(lev[lo], lev[hi - (1ll << t) + 1]);
+      } else {
+        ok = false;  // never, for a table of ilog2(m) + 1 levels
+      }
+    }
+    __builtin_nontemporal_store(ok ? (int32_t)key_pos(best) : -1, out + i);
+  }
+  if (bad_count) {
+    const uint64_t bad = ballot(live && !ok);
+    if (bad && lane_id() == 0) atomicAdd(bad_count, (unsigned long long)__popcll(bad));
+  }
+}
+
 // Every query of a batch of tables (plain path): global query g belongs to
 // the table whose range of the concatenated query list holds it.
 // Queries of a batch: wave w does job w, 64 consecutive queries of one
@@ -936,6 +976,16 @@ hipError_t launch_query_contracted(const uint64_t* aq, int64_t m, int64_t n, int
                    (unsigned long long*)stats, lg, rec, rlev, fail));
   }
   return hipGetLastError();
+}
+
+hipError_t launch_query_st_elements(const uint64_t* st, int64_t m, int levels, const int32_t* L,
+                                    const int32_t* R, const int32_t* LR, int64_t q, int64_t n,
+                                    int32_t* out, int64_t* bad_count, hipStream_t stream,
+                                    const uint32_t* fail) {
+  if (q <= 0) return hipSuccess;
+  RMQ_TRY(launch(k_query_st_elements, dim3((unsigned)((q + WG - 1) / WG)), dim3(WG), 0, stream,
+                 st, m, levels, L, R, LR, q, n, out, (unsigned long long*)bad_count, fail));
+  return hipSuccess;
 }
 
 hipError_t launch_query_multi(const WaveJob* jobs, int64_t waves, hipStream_t stream) {

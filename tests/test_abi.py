@@ -239,3 +239,24 @@ def test_build_bytes_is_the_index_footprint():
                 assert with_rec == rmq.index_bytes(n, k)
         assert rmq.build_bytes(n, 65536, 1024) == rmq.index_bytes(n, 65536) + 8 * (-(-n // 1024))
     assert rmq.build_bytes(0) == 0 and rmq.build_bytes(10, 100) == 0
+
+
+def test_st_con_workspace_and_options():
+    """The comparison system ST-RMQ_CON (Section 2): its workspace holds the
+    element table over A_Q's 4q - 1 entries (floor(log2(4q - 1)) + 1 levels)
+    beside the sort's; block sizes, two levels, another arity or more than
+    2^29 queries are refused; the planner never picks it."""
+    n, q = 10 ** 8, 10 ** 6
+    m = 4 * q - 1
+    levels = m.bit_length()
+    w = rmq.workspace_bytes(n, q, "st_con")
+    con = rmq.workspace_bytes(n, q, "contracted", 512, records=False)
+    assert w >= 8 * m * levels
+    assert w <= 8 * m * levels + con + 16 * q + n // 256 + (1 << 20)
+    assert rmq.workspace_bytes(n, 1, "st_con") > 0
+    assert rmq.workspace_bytes(n, q, "st_con", 256) == 0
+    assert rmq.workspace_bytes(n, q, "st_con", sub_block_size=64) == 0
+    assert rmq.workspace_bytes(n, q, "st_con", arity_log2=2) == 0
+    assert rmq.workspace_bytes(n, (1 << 29) + 1, "st_con") == 0
+    for qq in (10, 10 ** 4, 10 ** 7):
+        assert rmq.plan_ex(n, qq)[1] in ("full", "contracted")
