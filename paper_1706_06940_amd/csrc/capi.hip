@@ -4,6 +4,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <atomic>
 #include <mutex>
 #include <new>
@@ -1182,7 +1183,12 @@ rmq_status rmq_batch_create(const rmq_batch_item* items, int32_t count, rmq_batc
   put(b->blockmin, jb_min);
   put(b->keys, jb_keys);
   for (int r = 0; r < ST_MAX_ROUNDS; ++r) put(b->round[r], jb_round[r]);
+  // waves over larger blocks first (longer partial scans, slower waves), so
+  // that the launch ends on short ones (fused batch of the benchmark:
+  // 0.296-0.314 ms against 0.303-0.315 in item order)
   jb_q2.insert(jb_q2.end(), jb_q1.begin(), jb_q1.end());
+  std::stable_sort(jb_q2.begin(), jb_q2.end(),
+                   [](const WaveJob& x, const WaveJob& y) { return x.d.kshift > y.d.kshift; });
   put(b->queries, jb_q2);
   e = hipMemcpy(dbase, img.data(), tbytes, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
