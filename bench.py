@@ -594,7 +594,7 @@ def bench_permutation(d, qs, reps=5):
 def bench_skewed(d, reps=5):
     """n = 1e9 uniform int32 (4 GB, drawn in HBM by the generator's torch
     form), q = 1e7: half short ranges (length uniform in [1, 1024]), half
-    uniform long ones.  The plain method with one block level and with two
+    uniform long ones.  The plain method with one, two and three block levels
     (Section 3.3), and the contracted method; whole offline jobs (mean of
     `reps` after a first run that also counts the entries read by partial-block
     scans)."""
@@ -610,14 +610,16 @@ def bench_skewed(d, reps=5):
     L, R = torch.from_numpy(L_h).to(d), torch.from_numpy(R_h).to(d)
     out = torch.empty(q, dtype=torch.int32, device=d)
     stream = torch.cuda.current_stream(d)
-    configs = [("full", 4096, 0), ("full", 16384, 0), ("full", 16384, 256), ("full", 65536, 256),
-               ("full", 65536, 1024), ("contracted", 0, 0)]
+    configs = [("full", 4096, 0, 0), ("full", 16384, 0, 0), ("full", 16384, 256, 0),
+               ("full", 65536, 256, 0), ("full", 65536, 1024, 0), ("full", 65536, 1024, 64),
+               ("full", 65536, 2048, 128), ("full", 262144, 4096, 128), ("contracted", 0, 0, 0)]
     res = {}
     ref = None
-    for path, k, k1 in configs:
+    for path, k, k1, k2 in configs:
         stats = torch.zeros(2, dtype=torch.int64, device=d)
         run = lambda st=None: rmq.query_batch(A, L, R, path=path, block_size=k,
-                                              sub_block_size=k1, out=out, stats=st)
+                                              sub_block_size=k1, sub_block_size2=k2, out=out,
+                                              stats=st)
         run(stats)
         torch.cuda.synchronize()
         got = out.clone()
@@ -625,7 +627,8 @@ def bench_skewed(d, reps=5):
             ref = got
         same = bool(torch.equal(got, ref))
         ms = time_runs(run, stream, warmup=0, reps=reps)
-        name = f"{path}/k={k or 'default'}" + (f"/k1={k1}" if k1 else "")
+        name = f"{path}/k={k or 'default'}" + (f"/k1={k1}" if k1 else "") + \
+            (f"/k2={k2}" if k2 else "")
         scans, reads = stats.tolist()
         res[name] = {"ms": round(ms, 4), "queries_per_s": round(q / (ms / 1e3), 1),
                      "partial_scans": scans, "entries_read_by_scans": reads,

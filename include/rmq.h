@@ -167,6 +167,16 @@ typedef struct rmq_options {
                                  reads each end block's key and the window
                                  beside it with one 16-byte load instead of
                                  two 8-byte ones.  Same answers either way. */
+    int32_t sub_block_size2; /* Section 3.3 with three block levels: k2, the
+                                size of still smaller blocks whose minima are
+                                kept under the k1-blocks (0 = none).  A power
+                                of two, 16 <= k2 < k1; needs sub_block_size and
+                                the plain method (path AUTO or FULL) in a
+                                single call (not the contracted method, the
+                                resident index, batches or the server).  A
+                                partial k1-block is then read as k2-block
+                                minima plus at most two partial k2-blocks.
+                                Same answers. */
 } rmq_options;
 
 /* A human-readable name for a status code (static storage). */

@@ -52,6 +52,7 @@ class _Options(ctypes.Structure):
         ("sub_block_size", ctypes.c_int32),
         ("table_arity_log2", ctypes.c_int32),
         ("no_query_records", ctypes.c_int32),
+        ("sub_block_size2", ctypes.c_int32),
     ]
 
 
@@ -175,11 +176,12 @@ class Timer:
 
 def _options(block_size=0, path="auto", bad_count=None, stats=None, workspace=None,
              timer: Optional[Timer] = None, sub_block_size: int = 0,
-             arity_log2: int = 0, records: bool = True) -> _Options:
+             arity_log2: int = 0, records: bool = True, sub_block_size2: int = 0) -> _Options:
     o = _Options()
     o.no_query_records = 0 if records else 1
     o.block_size = int(block_size)
     o.sub_block_size = int(sub_block_size)
+    o.sub_block_size2 = int(sub_block_size2)
     o.table_arity_log2 = int(arity_log2)
     o.path = PATHS[path] if isinstance(path, str) else int(path)
     o.bad_count = _dev_u64(bad_count, "bad_count") if bad_count is not None else None
@@ -275,9 +277,10 @@ def default_sub_block(n: int, q: int, path: str) -> int:
 
 
 def workspace_bytes(n: int, q: int, path="auto", block_size: int = 0,
-                    sub_block_size: int = 0, arity_log2: int = 0, records: bool = True) -> int:
+                    sub_block_size: int = 0, arity_log2: int = 0, records: bool = True,
+                    sub_block_size2: int = 0) -> int:
     o = _options(block_size, path, sub_block_size=sub_block_size, arity_log2=arity_log2,
-                 records=records)
+                 records=records, sub_block_size2=sub_block_size2)
     return int(lib().rmq_workspace_bytes(n, q, ctypes.byref(o)))
 
 
@@ -310,18 +313,19 @@ def table_levels(num_blocks: int, arity_log2: int = 0) -> int:
 def query_batch(A: torch.Tensor, L: torch.Tensor, R: torch.Tensor, *, path="auto",
                 block_size: int = 0, sub_block_size: int = 0, arity_log2: int = 0,
                 out: Optional[torch.Tensor] = None, bad_count=None, stats=None, workspace=None,
-                timer: Optional[Timer] = None, stream=None, records: bool = True) -> torch.Tensor:
+                timer: Optional[Timer] = None, stream=None, records: bool = True,
+                sub_block_size2: int = 0) -> torch.Tensor:
     """Answer all queries of one offline batch (Section 1); returns int32 out.
-    sub_block_size > 0 selects two block levels (Section 3.3) on the plain
-    method; arity_log2 in 2..5 builds the block table over powers of
-    l = 2^arity_log2 instead of 2 (Section 3.1)."""
+    sub_block_size > 0 selects two block levels (Section 3.3), and
+    sub_block_size2 > 0 a third (plain method); arity_log2 in 2..5 builds the
+    block table over powers of l = 2^arity_log2 instead of 2 (Section 3.1)."""
     n, q = A.numel(), L.numel()
     if R.numel() != q:
         raise ValueError("L and R differ in length")
     if out is None:
         out = torch.empty(q, dtype=torch.int32, device=A.device)
     o = _options(block_size, path, bad_count, stats, workspace, timer, sub_block_size,
-                 arity_log2, records)
+                 arity_log2, records, sub_block_size2)
     st = lib().rmq_query_batch_ex(_dev_i32(A, "A"), n, _dev_i32(L, "L") if q else None,
                                   _dev_i32(R, "R") if q else None, q,
                                   _dev_i32(out, "out") if q else None,

@@ -78,6 +78,7 @@ struct Plan {
   int k1shift;  // two block levels (Section 3.3): k1 = 2^k1shift; -1 = one level
   int lg;       // table over powers of l = 2^lg (Section 3.1); 1 = doubling
   bool records;  // query records allowed (opt->no_query_records == 0)
+  int k2shift = -1;  // three block levels (plain method): k2 = 2^k2shift; -1 = none
 };
 
 // Query records (see launch_records) for a doubling table of nb blocks and
@@ -151,14 +152,26 @@ constexpr int64_t BATCH_SUB_BLOCK = 1024;
 // list (4q entries) must index in 32 bits.
 constexpr int64_t ST_CON_MAX_Q = 1ll << 29;
 
+// single_call: the caller is rmq_query_batch_ex / rmq_workspace_bytes, which
+// alone take the comparison system ST-RMQ_CON and three block levels.
 rmq_status make_plan(int64_t n, int64_t q, const rmq_options* opt, Plan* p,
-                     bool allow_two_level = true, bool allow_st_con = false) {
+                     bool allow_two_level = true, bool single_call = false) {
   int32_t path = opt ? opt->path : RMQ_PATH_AUTO;
   int32_t k = opt ? opt->block_size : 0;
   int32_t k1 = opt ? opt->sub_block_size : 0;
+  const int32_t k2 = opt ? opt->sub_block_size2 : 0;
+  p->k2shift = -1;
+  if (k2 != 0) {
+    // three block levels (Section 3.3): the plain method, under a given k1
+    if (!single_call || k1 == 0 || !is_pow2_block(k2) || k2 >= k1 ||
+        (path != RMQ_PATH_AUTO && path != RMQ_PATH_FULL))
+      return RMQ_ERR_INVALID_ARG;
+    path = RMQ_PATH_FULL;
+    p->k2shift = ilog2_i64(k2);
+  }
   if (path == RMQ_PATH_ST_CON) {
     // the comparison system: no blocks, one element table (doubling)
-    if (!allow_st_con || k != 0 || k1 != 0 || arity_lg(opt) != 1 || q > ST_CON_MAX_Q)
+    if (!single_call || k != 0 || k1 != 0 || arity_lg(opt) != 1 || q > ST_CON_MAX_Q)
       return RMQ_ERR_INVALID_ARG;
     p->path = RMQ_PATH_ST_CON;
     p->k = 1;
@@ -217,14 +230,16 @@ rmq_status make_plan(int64_t n, int64_t q, const rmq_options* opt, Plan* p,
 
 // ---- workspace layouts ----
 struct FullLayout {
-  int64_t nb, nb1;
+  int64_t nb, nb1, nb2;
   int levels;
   bool rec;  // query records built
-  size_t off_st, off_sub, off_rec, bytes;
+  size_t off_st, off_sub, off_sub2, off_rec, bytes;
 };
 
-// The table, then (two block levels) the k1-block minima.
-FullLayout full_layout(int64_t n, int64_t k, int k1shift, int lg, bool records) {
+// The table, then (two block levels) the k1-block minima, then (three) the
+// k2-block minima.
+FullLayout full_layout(int64_t n, int64_t k, int k1shift, int lg, bool records,
+                       int k2shift = -1) {
   FullLayout f{};
   f.nb = num_blocks(n, k);
   f.levels = table_levels(f.nb, lg);
@@ -232,7 +247,9 @@ FullLayout full_layout(int64_t n, int64_t k, int k1shift, int lg, bool records) 
   f.off_st = 0;
   f.off_sub = align_up(sizeof(uint64_t) * (size_t)f.nb * (size_t)f.levels);
   f.nb1 = k1shift >= 0 ? num_blocks(n, 1ll << k1shift) : 0;
-  f.off_rec = f.off_sub + align_up(sizeof(uint64_t) * (size_t)f.nb1);
+  f.off_sub2 = f.off_sub + align_up(sizeof(uint64_t) * (size_t)f.nb1);
+  f.nb2 = k1shift >= 0 && k2shift >= 0 ? num_blocks(n, 1ll << k2shift) : 0;
+  f.off_rec = f.off_sub2 + (f.nb2 ? align_up(sizeof(uint64_t) * (size_t)f.nb2) : 0);
   f.bytes = f.off_rec + (f.rec ? align_up(records_bytes(f.nb, f.levels)) : 0);
   return f;
 }
@@ -309,7 +326,8 @@ StConLayout st_con_layout(int64_t n, int64_t q) {
 
 size_t plan_bytes(int64_t n, int64_t q, const Plan& p) {
   if (p.path == RMQ_PATH_ST_CON) return st_con_layout(n, q).bytes;
-  if (p.path == RMQ_PATH_FULL) return full_layout(n, p.k, p.k1shift, p.lg, p.records).bytes;
+  if (p.path == RMQ_PATH_FULL)
+    return full_layout(n, p.k, p.k1shift, p.lg, p.records, p.k2shift).bytes;
   return con_layout(n, q, p.k, p.k1shift, p.lg, p.records).bytes;
 }
 
@@ -405,17 +423,23 @@ rmq_status run_full(const int32_t* A, int64_t n, const int32_t* L, const int32_t
   rmq_timer* t = opt ? opt->timer : nullptr;
   ClockGuard guard;
   if (t) t->ran[0] = false;  // no sort stage on this path
-  const FullLayout f = full_layout(n, p.k, p.k1shift, p.lg, p.records);
+  const FullLayout f = full_layout(n, p.k, p.k1shift, p.lg, p.records, p.k2shift);
   uint64_t* st = reinterpret_cast<uint64_t*>(ws + f.off_st);
   uint64_t* sub = reinterpret_cast<uint64_t*>(ws + f.off_sub);
+  uint64_t* sub2 = reinterpret_cast<uint64_t*>(ws + f.off_sub2);
   uint64_t* rec = f.rec ? reinterpret_cast<uint64_t*>(ws + f.off_rec) : nullptr;
   const bool two = p.k1shift >= 0;
+  const bool three = two && p.k2shift >= 0;
   // stage 1 is the one pass over A; with two levels (Section 3.3) it takes
-  // the k1-block minima, and the k-block minima are taken from those in
-  // stage 2 with the table
+  // the k1-block minima (with three, the k2-block minima, and the k1-block
+  // minima from those), and the k-block minima are taken from the k1-block
+  // minima in stage 2 with the table
   stage_begin(t, 1);
-  hipError_t e = two ? launch_blockmin_i32(A, n, p.k1shift, sub, s)
-                     : launch_blockmin_i32(A, n, p.kshift, st, s);
+  hipError_t e = three ? launch_blockmin_i32(A, n, p.k2shift, sub2, s)
+                 : two ? launch_blockmin_i32(A, n, p.k1shift, sub, s)
+                       : launch_blockmin_i32(A, n, p.kshift, st, s);
+  if (e == hipSuccess && three)
+    e = launch_blockmin_keys(sub2, f.nb2, p.k1shift - p.k2shift, sub, s);
   if (e != hipSuccess) return from_hip(e);
   stage_end(t, 1, s);
   stage_begin(t, 2);
@@ -427,10 +451,12 @@ rmq_status run_full(const int32_t* A, int64_t n, const int32_t* L, const int32_t
   stage_begin(t, 3);
   int64_t* bad = opt ? opt->bad_count : nullptr;
   uint64_t* stats = opt ? opt->stats : nullptr;
-  e = two ? launch_query_full2(A, n, p.kshift, st, f.nb, sub, p.k1shift, L, R, q, out, bad, stats,
-                               s, p.lg, rec, f.levels)
-          : launch_query_full(A, n, p.kshift, st, f.nb, L, R, q, out, bad, stats, s, p.lg, rec,
-                              f.levels);
+  e = three ? launch_query_full3(A, n, p.kshift, st, f.nb, sub, p.k1shift, sub2, p.k2shift, L, R,
+                                 q, out, bad, stats, s, p.lg)
+      : two ? launch_query_full2(A, n, p.kshift, st, f.nb, sub, p.k1shift, L, R, q, out, bad,
+                                 stats, s, p.lg, rec, f.levels)
+            : launch_query_full(A, n, p.kshift, st, f.nb, L, R, q, out, bad, stats, s, p.lg, rec,
+                                f.levels);
   if (e != hipSuccess) return from_hip(e);
   stage_end(t, 3, s);
   return RMQ_OK;
@@ -708,6 +734,7 @@ rmq_status index_shape(int64_t n, const rmq_options* opt, IndexShape* sh) {
   const int32_t k1 = opt ? opt->sub_block_size : 0;
   const int lg = arity_lg(opt);
   if (lg < 0 || (k1 != 0 && !is_pow2_block(k1))) return RMQ_ERR_INVALID_ARG;
+  if (opt && opt->sub_block_size2 != 0) return RMQ_ERR_INVALID_ARG;  // single calls only
   if (k == 0 && k1 != 0) {
     k = default_block_two_level(n, k1);
   } else if (k == 0) {

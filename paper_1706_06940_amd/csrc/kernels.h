@@ -159,6 +159,14 @@ hipError_t launch_query_full2(const int32_t* A, int64_t n, int kshift, const uin
                               uint64_t* stats, hipStream_t stream, int lg = 1,
                               const uint64_t* rec = nullptr, int rlev = 0);
 
+// Three block levels (Section 3.3, h = 3): sub holds the k1-block minima,
+// sub2 the k2-block minima (k2 < k1 < k, powers of two).
+hipError_t launch_query_full3(const int32_t* A, int64_t n, int kshift, const uint64_t* st,
+                              int64_t nb, const uint64_t* sub, int k1shift, const uint64_t* sub2,
+                              int k2shift, const int32_t* L, const int32_t* R, int64_t q,
+                              int32_t* out, int64_t* bad_count, uint64_t* stats,
+                              hipStream_t stream, int lg = 1);
+
 // ---- contracted path (Section 3.1) ----
 // Device LSD radix sort of the 2q endpoints by (position, tag).  The sorted
 // list E holds (position << 32) | tag per slot.  With LR non-null the last

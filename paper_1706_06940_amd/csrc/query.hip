@@ -84,6 +84,7 @@ struct SrcA {
   // Queued pieces are read several at a time, each by a group of G lanes
   // (grouped_scans); an entry is 4 bytes.
   static constexpr bool kGroupScans = true;
+  static constexpr bool kNested = false;
   static constexpr int kEntryShift = 2;
   // This lane's share of the min key over A[lo..hi] when G lanes read it
   // together: four 16-byte loads per lane in flight, 16 G elements a pass
@@ -179,6 +180,7 @@ struct SrcKeys {
     return best;
   }
   static constexpr bool kGroupScans = true;  // as for the plain array; 8-byte entries
+  static constexpr bool kNested = false;
   static constexpr int kEntryShift = 3;
   // This lane's share of the min over S[lo..hi] when G lanes read it
   // together: four 16-byte loads per lane in flight, 8 G entries a pass
@@ -283,7 +285,7 @@ struct Src2 {
   // min over the entries lo..hi, which lie in one k1-block: its minimum if
   // that lies inside, nothing if it cannot beat `bound`, else a scan of the
   // entries
-  __device__ uint64_t part(int64_t lo, int64_t hi, int lane, uint64_t bound,
+  __device__ __forceinline__ uint64_t part(int64_t lo, int64_t hi, int lane, uint64_t bound,
                            int64_t& reads) const {
     const uint64_t kb = sub[lo >> s1];
     reads += 1;
@@ -297,15 +299,33 @@ struct Src2 {
   // 256: longer pieces read by one lane cost more than wave-wide scans).
   static constexpr bool kLaneScans = true;
   static constexpr bool kGroupScans = false;  // its pieces are read in two steps
+  // as an inner source itself (three block levels, Src2<Src2<SrcA>>): entry
+  // indices are its inner source's
+  static constexpr bool kIndexIsPos = Inner::kIndexIsPos;
+  // Entries one lane reads for a piece of `elems` entries inside one block
+  // of this level (as the inner source of a third level).
+  static constexpr bool kNested = true;
+  __device__ __forceinline__ int64_t piece_cost(int64_t elems) const {
+    const int64_t k1 = 1ll << s1;
+    const int64_t inner = elems < k1 ? elems : k1;
+    return (elems >> s1) + 2 + 2 * inner;
+  }
   __device__ __forceinline__ int64_t lane_cost(int64_t lo, int64_t hi) const {
+    const int64_t elems = hi - lo + 1, k1 = 1ll << s1;
+    if constexpr (Inner::kNested) {
+      // three levels: a partial k1-block costs its k2-block minima and two
+      // partial k2-blocks
+      const int64_t piece = a.piece_cost(elems < k1 ? elems : k1);
+      return (hi >> s1) - (lo >> s1) + 1 + 2 * piece;
+    }
     if (s1 > 8) return INT64_MAX;
-    const int64_t elems = hi - lo + 1, two = 2ll << s1;
+    const int64_t two = 2ll << s1;
     return (hi >> s1) - (lo >> s1) + 1 + (elems < two ? elems : two);
   }
   // the same decomposition by this lane alone (short ranges): k1-blocks
   // b_lo+1 .. b_hi-1 whole, then the pieces of b_lo and b_hi in the range
   // (a whole k1-block's minimum always lies inside, so it needs no scan)
-  __device__ uint64_t lane_scan(int64_t lo, int64_t hi, uint64_t bound, int64_t& reads) const {
+  __device__ __forceinline__ uint64_t lane_scan(int64_t lo, int64_t hi, uint64_t bound, int64_t& reads) const {
     const int64_t b_lo = lo >> s1, b_hi = hi >> s1;
     const int64_t k1 = 1ll << s1;
     const uint64_t kh = sub[b_lo], kt = sub[b_hi];  // both loads in flight
@@ -322,7 +342,7 @@ struct Src2 {
     if (b_hi != b_lo) piece(kt, b_hi * k1, hi);
     return best;
   }
-  __device__ uint64_t scan(int64_t lo, int64_t hi, int lane, uint64_t bound,
+  __device__ __forceinline__ uint64_t scan(int64_t lo, int64_t hi, int lane, uint64_t bound,
                            int64_t& reads) const {
     const int64_t b_lo = lo >> s1, b_hi = hi >> s1;
     if (b_lo == b_hi) return part(lo, hi, lane, bound, reads);
@@ -342,6 +362,9 @@ struct Src2 {
 };
 using SrcA2 = Src2<SrcA>;
 using SrcKeys2 = Src2<SrcKeys>;
+// Three block levels (Section 3.3 with h = 3): the k1-block minima over the
+// k2-block minima over A.
+using SrcA3 = Src2<SrcA2>;
 
 // --- the query step ----------------------------------------------------------
 // The queued partial-block pieces of a wave (pl: lanes with a left piece
@@ -919,6 +942,30 @@ hipError_t launch_query_full2(const int32_t* A, int64_t n, int kshift, const uin
                  SrcA2{SrcA{A, n}, sub, nsub, k1shift}, n, n, kshift, st, nb, L, R,
                  static_cast<const int32_t*>(nullptr), q, out, (unsigned long long*)bad_count,
                  (unsigned long long*)stats, lg, rec, rlev, static_cast<const uint32_t*>(nullptr)));
+  return hipGetLastError();
+}
+
+hipError_t launch_query_full3(const int32_t* A, int64_t n, int kshift, const uint64_t* st,
+                              int64_t nb, const uint64_t* sub, int k1shift, const uint64_t* sub2,
+                              int k2shift, const int32_t* L, const int32_t* R, int64_t q,
+                              int32_t* out, int64_t* bad_count, uint64_t* stats,
+                              hipStream_t stream, int lg) {
+  if (q <= 0) return hipSuccess;
+  const int64_t nsub = (n + (1ll << k1shift) - 1) >> k1shift;
+  const int64_t nsub2 = (n + (1ll << k2shift) - 1) >> k2shift;
+  const SrcA3 src{SrcA2{SrcA{A, n}, sub2, nsub2, k2shift}, sub, nsub, k1shift};
+  if (const int64_t words = lds_table_words(nb, lg, q)) {
+    RMQ_TRY(launch(k_query_lds<SrcA3>, dim3((unsigned)lds_grid(q)), dim3(LWG), 0, stream, src, n,
+                   n, kshift, st, nb, words, L, R, static_cast<const int32_t*>(nullptr), q, out,
+                   (unsigned long long*)bad_count, (unsigned long long*)stats,
+                   static_cast<const uint32_t*>(nullptr)));
+    return hipGetLastError();
+  }
+  const int64_t grid = (q + WG - 1) / WG;
+  RMQ_TRY(launch(k_query<SrcA3>, dim3((unsigned)grid), dim3(WG), 0, stream, src, n, n, kshift, st,
+                 nb, L, R, static_cast<const int32_t*>(nullptr), q, out,
+                 (unsigned long long*)bad_count, (unsigned long long*)stats, lg,
+                 static_cast<const uint64_t*>(nullptr), 0, static_cast<const uint32_t*>(nullptr)));
   return hipGetLastError();
 }
 

@@ -260,3 +260,25 @@ def test_st_con_workspace_and_options():
     assert rmq.workspace_bytes(n, (1 << 29) + 1, "st_con") == 0
     for qq in (10, 10 ** 4, 10 ** 7):
         assert rmq.plan_ex(n, qq)[1] in ("full", "contracted")
+
+
+def test_three_block_levels_workspace_and_options():
+    """Three block levels (Section 3.3, h = 3): the workspace adds the
+    k2-block minima to the two-level one; k2 needs k1 > k2, the plain method
+    and a single call (the resident index refuses it)."""
+    n, q = 10 ** 8, 10 ** 6
+    two = rmq.workspace_bytes(n, q, "full", 65536, sub_block_size=1024)
+    three = rmq.workspace_bytes(n, q, "full", 65536, sub_block_size=1024, sub_block_size2=64)
+    nb2 = -(-n // 64)
+    assert 8 * nb2 <= three - two <= 8 * nb2 + 512
+    assert rmq.workspace_bytes(n, q, "auto", 65536, sub_block_size=1024, sub_block_size2=64) == three
+    assert rmq.workspace_bytes(n, q, "full", 65536, sub_block_size2=64) == 0            # no k1
+    assert rmq.workspace_bytes(n, q, "full", 65536, sub_block_size=1024,
+                               sub_block_size2=1024) == 0                              # k2 >= k1
+    assert rmq.workspace_bytes(n, q, "full", 65536, sub_block_size=1024,
+                               sub_block_size2=100) == 0                               # not a power of 2
+    assert rmq.workspace_bytes(n, q, "contracted", 4096, sub_block_size=256,
+                               sub_block_size2=64) == 0                                # plain only
+    assert rmq.workspace_bytes(n, q, "st_con", sub_block_size2=64) == 0
+    o = rmq._options(65536, "full", sub_block_size=1024, sub_block_size2=64)
+    assert rmq.lib().rmq_build_bytes(n, ctypes.byref(o)) == 0
