@@ -182,7 +182,9 @@ typedef struct rmq_options {
 /* A human-readable name for a status code (static storage). */
 const char *rmq_status_string(rmq_status s);
 
-/* Library version string (static storage). */
+/* Library version string (static storage).  "rmq-gfx950 1.1": rmq_options
+ * ends with sub_block_size2 and rmq_path has RMQ_PATH_ST_CON; a caller built
+ * against 1.0's shorter rmq_options must be rebuilt. */
 const char *rmq_version(void);
 
 /* ----------------------------------------------------------------------------

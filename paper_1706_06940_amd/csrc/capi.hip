@@ -568,7 +568,7 @@ const char* rmq_status_string(rmq_status s) {
   return "unknown status";
 }
 
-const char* rmq_version(void) { return "rmq-gfx950 1.0"; }
+const char* rmq_version(void) { return "rmq-gfx950 1.1"; }
 
 int32_t rmq_table_levels(int64_t nb) {
   if (nb <= 3) return 1;
