@@ -59,6 +59,10 @@ __device__ __forceinline__ void st_tile(uint64_t* __restrict__ st, int64_t nb, i
   const int64_t tile_c = tile_idx % col_tiles;
   const int64_t tile_r = tile_idx / col_tiles;
   const int64_t r0 = tile_c * R;
+  // R is a power of two (min(stride, 16)): rows and columns of an LDS index
+  // by shift and mask (a run-time division per entry and level was most of
+  // a small table's build time)
+  const int rs = __builtin_ctz((unsigned)R);
   const int64_t i0 = tile_r * TI;
   const uint64_t* src = st + (size_t)j0 * nb;
 
@@ -69,9 +73,9 @@ __device__ __forceinline__ void st_tile(uint64_t* __restrict__ st, int64_t nb, i
 #pragma unroll
   for (int u = 0; u < LOADS; ++u) {
     const int idx = threadIdx.x + u * WG;
-    const int row = idx / R, c = idx % R;
+    const int row = idx >> rs, c = idx & (R - 1);
     const int64_t r = r0 + c;
-    const int64_t b = (i0 + row) * s + r;
+    const int64_t b = ((i0 + row) << j0) + r;
     const bool ok = idx < rows * R && r < s && b < nb;
     v[u] = src[ok ? b : 0];
     if (!ok) v[u] = KEY_NONE;
@@ -101,10 +105,10 @@ __device__ __forceinline__ void st_tile(uint64_t* __restrict__ st, int64_t nb, i
       const int idx = threadIdx.x + u * WG;
       if (idx < rows_m * R) {
         nxt[idx] = w[u];
-        const int row = idx / R, c = idx % R;
+        const int row = idx >> rs, c = idx & (R - 1);
         if (row < TI) {
           const int64_t r = r0 + c;
-          const int64_t b = (i0 + row) * s + r;
+          const int64_t b = ((i0 + row) << j0) + r;
           if (r < s && b < nb) dst[b] = w[u];
         }
       }
@@ -227,12 +231,16 @@ __global__ __launch_bounds__(WG) void k_st_lary(const uint64_t* __restrict__ pre
 
 // Query records: one thread per key, in record order (coalesced writes);
 // the table reads are gathers from a table small enough for L2.
+// (Records are built only while they take at most 8 MiB, so pair indices
+// stay below 2^31 and divide by the level count through a Divisor.)
 __global__ __launch_bounds__(WG) void k_records(const uint64_t* __restrict__ st, int64_t nb,
-                                                int levels, uint64_t* __restrict__ rec) {
+                                                int levels, Divisor lv,
+                                                uint64_t* __restrict__ rec) {
   const int64_t e = (int64_t)blockIdx.x * WG + threadIdx.x;
   if (e >= 4 * nb * levels) return;
   const int64_t pair = e >> 1;
-  const int64_t rb = pair / levels;  // record: forward 0 .. nb-1, backward nb .. 2nb-1
+  // record: forward 0 .. nb-1, backward nb .. 2nb-1
+  const int64_t rb = div_by((uint32_t)pair, lv);
   const int t = (int)(pair - rb * levels);
   const bool fwd = rb < nb;
   const int64_t b = fwd ? rb : rb - nb;
@@ -251,8 +259,9 @@ __global__ __launch_bounds__(WG) void k_records(const uint64_t* __restrict__ st,
 hipError_t launch_records(const uint64_t* st, int64_t nb, int levels, uint64_t* rec,
                           hipStream_t stream) {
   const int64_t total = 4 * nb * levels;
+  if (total / 2 >= (1ll << 31)) return hipErrorInvalidValue;  // never: records are at most 8 MiB
   RMQ_TRY(launch(k_records, dim3((unsigned)((total + WG - 1) / WG)), dim3(WG), 0, stream, st, nb,
-                 levels, rec));
+                 levels, make_divisor((uint32_t)levels), rec));
   return hipSuccess;
 }
 
