@@ -457,7 +457,11 @@ __device__ __forceinline__ void query_core(const Src& src, int64_t src_len, int6
       pl = *reinterpret_cast<const v2u64*>(rec + 2 * (bl * rlev + t));
       if (bl != br) pr = *reinterpret_cast<const v2u64*>(rec + 2 * ((nb + br) * rlev + t));
     }
+    // both end blocks' keys are read before the inner windows, so that all
+    // of the query's table reads are in flight together (bl == br: the
+    // same key twice)
     const uint64_t kl = rec ? pl.x : st[bl];
+    const uint64_t kr_end = rec ? pr.x : st[br];
     if (bl == br) {
       const int64_t p = src.pos_of(kl);
       if (l <= p && p <= r) {
@@ -487,7 +491,7 @@ __device__ __forceinline__ void query_core(const Src& src, int64_t src_len, int6
             best = umin64(best, lev[lary_addr(br - (1ll << sh), nb, sh)]);
         }
       }
-      kr = rec ? pr.x : st[br];
+      kr = kr_end;
       if ((int64_t)src.pos_of(kl) >= l) {
         best = umin64(best, kl);
       } else if (kl < best) {
