@@ -425,21 +425,21 @@ __device__ __forceinline__ void grouped_scans(const Src& src, uint64_t pl, uint6
   }
 }
 
-// One lane's query [l, r] (positions in A, validated here) over source
-// entries [li, ri] of its table (st: level-major, nb blocks of 2^kshift
-// entries).  All 64 lanes of the wave must call this together: the partial
-// scans are done by the whole wave.  Lanes may belong to different tables
-// (batched launches); `live` is false for padding lanes.
+// The end-block step of one lane's query: validity, the inner windows'
+// minimum, both end blocks' keys with the speculation of Section 3.1 step 4,
+// and the partial pieces still to read (queued below).
+struct EndState {
+  uint64_t best, kr;
+  int64_t loL, hiL, loR, hiR;
+  bool ok, needL, needR;
+};
 template <class Src, class TablePtr = const uint64_t*>
-__device__ __forceinline__ void query_core(const Src& src, int64_t src_len, int64_t n,
-                                           int kshift, TablePtr __restrict__ st,
-                                           int64_t nb, int64_t l, int64_t r, int64_t li,
-                                           int64_t ri, bool live, int32_t* outp,
-                                           unsigned long long* __restrict__ bad_count,
-                                           unsigned long long* __restrict__ stats,
-                                           int lg = 1, const uint64_t* __restrict__ rec = nullptr,
-                                           int rlev = 0) {
-  const int lane = lane_id();
+__device__ __forceinline__ EndState query_ends(const Src& src, int64_t src_len, int64_t n,
+                                               int kshift, TablePtr __restrict__ st, int64_t nb,
+                                               int64_t l, int64_t r, int64_t li, int64_t ri,
+                                               bool live, int lg = 1,
+                                               const uint64_t* __restrict__ rec = nullptr,
+                                               int rlev = 0) {
   const bool ok = live && 0 <= l && l <= r && r < n && 0 <= li && li <= ri && ri < src_len;
 
   uint64_t best = KEY_NONE, kr = KEY_NONE;
@@ -509,6 +509,64 @@ __device__ __forceinline__ void query_core(const Src& src, int64_t src_len, int6
     }
   }
 
+  return EndState{best, kr, loL, hiL, loR, hiR, ok, needL, needR};
+}
+
+// The same end-block step from a doubling table in LDS without query records
+// (at most 18432 words: 32-bit indices), with no branches: every table read
+// is made, at clamped indices, and the cases are selected afterwards.
+template <class Src, class TablePtr>
+__device__ __forceinline__ EndState query_ends_lds(const Src& src, int64_t src_len, int64_t n,
+                                                   int kshift, TablePtr __restrict__ st,
+                                                   int64_t nb, int64_t l, int64_t r, int64_t li,
+                                                   int64_t ri, bool live) {
+  const bool ok = live && 0 <= l && l <= r && r < n && 0 <= li && li <= ri && ri < src_len;
+  const uint32_t bl = ok ? (uint32_t)(li >> kshift) : 0u;
+  const uint32_t br = ok ? (uint32_t)(ri >> kshift) : 0u;
+  const bool has_inner = br > bl + 1u;
+  const uint32_t inner = has_inner ? br - bl - 1u : 1u;
+  const int t = 31 - __clz(inner);
+  const uint32_t base = (uint32_t)t * (uint32_t)nb;
+  const uint32_t w1 = base + (has_inner ? bl + 1u : bl);
+  const uint32_t w2 = base + (has_inner ? br - (1u << t) : bl);
+  const uint64_t kl = st[bl], kre = st[br], x1 = st[w1], x2 = st[w2];
+  const uint64_t b1 = has_inner ? umin64(x1, x2) : KEY_NONE;  // the inner windows
+  const int64_t pl = (int64_t)src.pos_of(kl), pr = (int64_t)src.pos_of(kre);
+  const bool same = bl == br;
+  // one block: its minimum, or the whole range is a piece
+  const bool in_one = l <= pl && pl <= r;
+  // two end blocks: each end block's minimum if it lies in the range, else
+  // a piece of it while that minimum could still win
+  const bool l_in = pl >= l;
+  const uint64_t b2 = l_in ? umin64(b1, kl) : b1;
+  const bool r_in = pr <= r;
+  const uint64_t b3 = r_in ? umin64(b2, kre) : b2;
+  EndState e;
+  e.ok = ok;
+  e.best = !ok ? KEY_NONE : same ? (in_one ? kl : KEY_NONE) : b3;
+  e.kr = ok && !same ? kre : KEY_NONE;
+  e.needL = ok && (same ? !in_one : (!l_in && kl < b1));
+  e.needR = ok && !same && !r_in && kre < b2;
+  e.loL = ok ? li : 0;
+  e.hiL = !ok ? -1 : same ? ri : (((int64_t)bl + 1) << kshift) - 1;
+  e.loR = ok ? ((int64_t)br << kshift) : 0;
+  e.hiR = ok ? ri : -1;
+  return e;
+}
+
+// The partial-block step of one lane's query (all 64 lanes together) and its
+// answer: the pieces the end-block step left are read, then out is written.
+template <class Src>
+__device__ __forceinline__ void query_scans(const Src& src, const EndState& e, int64_t l,
+                                            int64_t r, bool live, int32_t* outp,
+                                            unsigned long long* __restrict__ bad_count,
+                                            unsigned long long* __restrict__ stats) {
+  const int lane = lane_id();
+  const bool ok = e.ok;
+  uint64_t best = e.best;
+  const uint64_t kr = e.kr;
+  bool needL = e.needL, needR = e.needR;
+  const int64_t loL = e.loL, hiL = e.hiL, loR = e.loR, hiR = e.hiR;
   // ---- partial-block scans: a short range is read by its own lane (many
   // of them at once); a long one is queued and read by the whole wave ----
   uint64_t n_scans = 0, n_elems = 0;  // wave-uniform counts of queued scans
@@ -597,6 +655,24 @@ __device__ __forceinline__ void query_core(const Src& src, int64_t src_len, int6
       atomicAdd(stats + 1, (unsigned long long)n_elems);
     }
   }
+}
+
+// One lane's query [l, r] (positions in A, validated here) over source
+// entries [li, ri] of its table (st: level-major, nb blocks of 2^kshift
+// entries).  All 64 lanes of the wave must call this together: the partial
+// scans are done by the whole wave.  Lanes may belong to different tables
+// (batched launches); `live` is false for padding lanes.
+template <class Src, class TablePtr = const uint64_t*>
+__device__ __forceinline__ void query_core(const Src& src, int64_t src_len, int64_t n,
+                                           int kshift, TablePtr __restrict__ st,
+                                           int64_t nb, int64_t l, int64_t r, int64_t li,
+                                           int64_t ri, bool live, int32_t* outp,
+                                           unsigned long long* __restrict__ bad_count,
+                                           unsigned long long* __restrict__ stats,
+                                           int lg = 1, const uint64_t* __restrict__ rec = nullptr,
+                                           int rlev = 0) {
+  const EndState e = query_ends(src, src_len, n, kshift, st, nb, l, r, li, ri, live, lg, rec, rlev);
+  query_scans(src, e, l, r, live, outp, bad_count, stats);
 }
 
 // One table.  L, R: the queries' positions in A.  For the contracted path, LR
@@ -717,8 +793,8 @@ __global__ __launch_bounds__(LWG) void k_query_lds(Src src, int64_t src_len, int
     const int64_t ri = LR ? (int64_t)(int32_t)(uint32_t)(q1.c >> 32) : r;
     q1 = q2;
     fetch(w + 2 * stride, q2);
-    query_core(src, src_len, n, kshift, lds_table, nb, l, r, li, ri, live,
-               out + (live ? i : 0), bad_count, stats);
+    const EndState e = query_ends_lds(src, src_len, n, kshift, lds_table, nb, l, r, li, ri, live);
+    query_scans(src, e, l, r, live, out + (live ? i : 0), bad_count, stats);
   }
 }
 
