@@ -13,7 +13,7 @@
 //   streaming the list for dense ones); and A_Q[j - 1] = +inf for every slot
 //   j that is the first in its tile -- that area reaches into the tile from
 //   an earlier one, so it may be finished by atomicMin from several waves.
-// k_contract (one streaming pass over A): each wave walks TPW consecutive
+// k_contract (one streaming pass over A): each wave walks tpw consecutive
 //   tiles, the next tile's values and first endpoints in flight while it
 //   works on the current one, and carries the area that is still open at a
 //   tile's end into the next tile (no barrier: waves share nothing).
@@ -138,7 +138,10 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-constexpr int TPW = 8;   // tiles per wave (2 or 4 were slower at every density)
+// Tiles per wave: enough that one round of waves (5 per SIMD) covers A,
+// at least 8 (2 or 4 were slower at every density) and at most 63 (a lane
+// per tile of the wave holds its table entry).
+constexpr int TPW_MIN = 8, TPW_MAX = 63, WAVES_PER_SIMD = 5;
 constexpr int KREG = 4;  // endpoint slots per lane of a tile held in registers (256 a tile)
 
 // The tile's values, coalesced: lane l holds elements 256 c + 4 l + (0..3);
@@ -179,20 +182,20 @@ __device__ __forceinline__ void load_ends(const int32_t* __restrict__ E, uint32_
   }
 }
 
-__global__ __launch_bounds__(WG) void k_contract(const int32_t* __restrict__ A, int64_t n,
-                                                 const int32_t* __restrict__ E, int64_t M,
-                                                 const int32_t* __restrict__ tile_start,
-                                                 int64_t num_tiles, uint64_t* __restrict__ aq,
-                                                 const uint32_t* __restrict__ fail) {
+// (at most 96 VGPRs: 5 waves per SIMD; the LDS of 5 workgroups fits a CU)
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(WAVES_PER_SIMD))) void
+k_contract(const int32_t* __restrict__ A, int64_t n, const int32_t* __restrict__ E, int64_t M,
+           const int32_t* __restrict__ tile_start, int64_t num_tiles, int tpw,
+           uint64_t* __restrict__ aq, const uint32_t* __restrict__ fail) {
   __shared__ __align__(16) int32_t s_x[WAVES][XWORDS];  // the tile, lane-consecutive
   __shared__ uint32_t s_off[WAVES][EPL / 2][64];         // run-min offsets, 2 x 16 bits
   __shared__ uint32_t s_head[WAVES][T / 32];             // endpoint bits
   __shared__ uint64_t s_carry[WAVES][64];                // run entering each lane
   const int lane = lane_id();
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int64_t tb = ((int64_t)blockIdx.x * WAVES + wave) * TPW;
+  const int64_t tb = ((int64_t)blockIdx.x * WAVES + wave) * tpw;
   if (tb >= num_tiles) return;  // the whole wave
-  const int cnt = (int)(num_tiles - tb < TPW ? num_tiles - tb : TPW);
+  const int cnt = (int)(num_tiles - tb < tpw ? num_tiles - tb : tpw);
   const bool aligned = ((uintptr_t)A & 15) == 0;
   // the first tile's values go out before anything else is read: they are
   // in flight while the wave reads the abort word and its table entries
@@ -208,7 +211,7 @@ __global__ __launch_bounds__(WG) void k_contract(const int32_t* __restrict__ A, 
   uint32_t ts_lane = lane <= cnt ? (uint32_t)tile_start[tb + lane] : 0u;
   ts_lane = ts_lane < Mu ? ts_lane : Mu;
 #pragma unroll
-  for (int dlt = 1; dlt < 16; dlt <<= 1) {  // running max over lanes 0 .. cnt (<= 8)
+  for (int dlt = 1; dlt < 64; dlt <<= 1) {  // running max over lanes 0 .. cnt (<= 63)
     const uint32_t up = (uint32_t)__shfl_up((int)ts_lane, dlt);
     if (lane >= dlt && up > ts_lane) ts_lane = up;
   }
@@ -415,10 +418,13 @@ hipError_t launch_contract(const int32_t* A, int64_t n, const int32_t* E, int64_
   else
     RMQ_TRY(launch(k_tiles_search, dim3((unsigned)((num_tiles + 1 + WG - 1) / WG)), dim3(WG), 0,
                    stream, E, M, aq, tile_start, num_tiles, fail));
-  const int64_t waves = (num_tiles + TPW - 1) / TPW;
+  const int64_t slots = (int64_t)device_cu_count() * 4 * WAVES_PER_SIMD;
+  int64_t tpw = (num_tiles + slots - 1) / slots;
+  tpw = tpw < TPW_MIN ? TPW_MIN : (tpw > TPW_MAX ? TPW_MAX : tpw);
+  const int64_t waves = (num_tiles + tpw - 1) / tpw;
   const int64_t grid = (waves + WAVES - 1) / WAVES;
   RMQ_TRY(launch(k_contract, dim3((unsigned)grid), dim3(WG), 0, stream, A, n, E, M, tile_start,
-                 num_tiles, aq, fail));
+                 num_tiles, (int)tpw, aq, fail));
   return hipSuccess;
 }
 

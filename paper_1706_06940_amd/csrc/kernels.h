@@ -167,6 +167,9 @@ hipError_t launch_query_full3(const int32_t* A, int64_t n, int kshift, const uin
                               int32_t* out, int64_t* bad_count, uint64_t* stats,
                               hipStream_t stream, int lg = 1);
 
+// Compute units of the current device (cached per device).
+int device_cu_count();
+
 // ---- contracted path (Section 3.1) ----
 // Device LSD radix sort of the 2q endpoints by (position, tag).  The sorted
 // list E holds (position << 32) | tag per slot.  With LR non-null the last

@@ -968,19 +968,10 @@ int64_t lds_table_words(int64_t nb, int lg, int64_t q) {
 }
 
 int lds_grid(int64_t q) {
-  static int cus[64] = {};
-  int dev = 0;
-  (void)hipGetDevice(&dev);
-  if (dev < 0 || dev >= 64) dev = 0;
-  if (!cus[dev]) {
-    int c = 0;
-    if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c < 1)
-      c = 256;
-    cus[dev] = c;
-  }
+  const int cus = device_cu_count();
   const int64_t waves = (q + 63) / 64;
   const int64_t need = (waves + LWG / 64 - 1) / (LWG / 64);
-  return (int)(need < cus[dev] ? need : cus[dev]);
+  return (int)(need < cus ? need : cus);
 }
 
 hipError_t launch_query_full(const int32_t* A, int64_t n, int kshift, const uint64_t* st,
@@ -1120,6 +1111,22 @@ hipError_t launch_query_multi(const WaveJob* jobs, int64_t waves, hipStream_t st
   const int64_t grid = (waves + WG / 64 - 1) / (WG / 64);
   RMQ_TRY(launch(k_query_multi, dim3((unsigned)grid), dim3(WG), 0, stream, jobs, waves));
   return hipSuccess;
+}
+
+// Compute units of the current device (cached per device; 256 if the
+// runtime cannot say).
+int device_cu_count() {
+  static int cus[64] = {};
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  if (dev < 0 || dev >= 64) dev = 0;
+  if (!cus[dev]) {
+    int c = 0;
+    if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c < 1)
+      c = 256;
+    cus[dev] = c;
+  }
+  return cus[dev];
 }
 
 }  // namespace rmq
