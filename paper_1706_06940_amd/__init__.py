@@ -341,7 +341,7 @@ NOALLOC_SCRATCH_BYTES = 128 << 20
 def query_batch_noalloc(A: torch.Tensor, L: torch.Tensor, R: torch.Tensor, out: torch.Tensor,
                         *, path="auto", block_size: int = 0, sub_block_size: int = 0,
                         arity_log2: int = 0, bad_count=None, stats=None, stream=None,
-                        records: bool = True) -> torch.Tensor:
+                        records: bool = True, sub_block_size2: int = 0) -> torch.Tensor:
     """query_batch through rmq_query_batch_noalloc: the scratch is the
     library's fixed device array, so the call allocates nothing (out must be
     given).  Raises RMQError (status 6) when the batch needs more scratch
@@ -350,7 +350,7 @@ def query_batch_noalloc(A: torch.Tensor, L: torch.Tensor, R: torch.Tensor, out: 
     if R.numel() != q or out.numel() != q:
         raise ValueError("L, R and out differ in length")
     o = _options(block_size, path, bad_count, stats, None, None, sub_block_size, arity_log2,
-                 records)
+                 records, sub_block_size2)
     st = lib().rmq_query_batch_noalloc(_dev_i32(A, "A"), n, _dev_i32(L, "L") if q else None,
                                        _dev_i32(R, "R") if q else None, q,
                                        _dev_i32(out, "out") if q else None,
