@@ -353,7 +353,7 @@ typedef struct rmq_lca_s *rmq_lca;
  * for the device (it checks the input and the tour) and returns
  * RMQ_ERR_INVALID_ARG for a forest, a parent out of range or a cycle, and
  * RMQ_ERR_DEVICE if the sort of the children gave up (see "Sort failure").
- * Temporary device memory: about 60 bytes per node, freed before return. */
+ * Temporary device memory: about 75 bytes per node, freed before return. */
 rmq_status rmq_lca_build(const int32_t *parent, int64_t num_nodes, const rmq_options *opt,
                          void *stream, rmq_lca *out);
 

@@ -48,6 +48,7 @@ struct rmq_lca_s {
 namespace rmq {
 
 namespace {
+typedef int32_t v2i32 __attribute__((ext_vector_type(2)));  // (count, depth sum)
 
 constexpr int WG = 256;
 constexpr int32_t END = -1;      // successor of the last arc
@@ -131,21 +132,17 @@ __device__ __forceinline__ int64_t sample_id(int64_t a, int64_t head, int64_t S)
 __global__ __launch_bounds__(WG) void k_lca_walk(const int32_t* __restrict__ nxt, int64_t NA,
                                                  const int32_t* __restrict__ first_child,
                                                  int32_t root, int64_t S,
-                                                 int32_t* __restrict__ owner,
-                                                 int32_t* __restrict__ lrank,
-                                                 int32_t* __restrict__ lw,
+                                                 v4i32* __restrict__ arc,
                                                  int32_t* __restrict__ s_next,
-                                                 int32_t* __restrict__ s_len,
-                                                 int32_t* __restrict__ s_w,
+                                                 v2i32* __restrict__ s_lw,
                                                  unsigned long long* __restrict__ stat) {
   const int64_t sid = (int64_t)blockIdx.x * WG + threadIdx.x;
   if (sid > S) return;
   const int64_t head = 2 * (int64_t)first_child[root];  // negative: no list (rejected)
   const int64_t a0 = sid == S ? head : sid * SPLIT;
   if (a0 < 0 || a0 >= NA || nxt[a0] == NOT_ARC || (sid < S && a0 == head)) {
-    s_len[sid] = -1;  // no walk starts here
+    s_lw[sid] = v2i32{-1, 0};  // no walk starts here
     s_next[sid] = END;
-    s_w[sid] = 0;
     return;
   }
   int64_t a = a0;
@@ -153,9 +150,9 @@ __global__ __launch_bounds__(WG) void k_lca_walk(const int32_t* __restrict__ nxt
   int32_t nx = END;
   bool ended = false;
   for (int64_t guard = 0; guard <= NA; ++guard) {
-    owner[a] = (int32_t)sid;
-    lrank[a] = cnt;
-    lw[a] = w;
+    // the arc's sample, count and depth sum: one 16-byte store (three 4-byte
+    // stores to as many arrays made three scattered writes per arc)
+    arc[a] = v4i32{(int32_t)sid, cnt, w, 0};
     cnt += 1;
     w += (a & 1) ? -1 : 1;
     nx = nxt[a];
@@ -166,8 +163,7 @@ __global__ __launch_bounds__(WG) void k_lca_walk(const int32_t* __restrict__ nxt
     a = nx;
   }
   if (!ended) atomicExch(&stat[1], 1ull);  // longer than the whole list: a cycle
-  s_len[sid] = cnt;
-  s_w[sid] = w;
+  s_lw[sid] = v2i32{cnt, w};
   s_next[sid] = (nx >= 0 && nx < NA) ? (int32_t)sample_id(nx, head, S) : END;
   atomicAdd(&stat[0], (unsigned long long)cnt);
 }
@@ -175,34 +171,31 @@ __global__ __launch_bounds__(WG) void k_lca_walk(const int32_t* __restrict__ nxt
 // One round of pointer jumping over the samples: sums (count, depth step)
 // from each sample to the end of the list.
 __global__ __launch_bounds__(WG) void k_lca_jump(const int32_t* __restrict__ in_next,
-                                                 const int32_t* __restrict__ in_len,
-                                                 const int32_t* __restrict__ in_w,
+                                                 const v2i32* __restrict__ in_lw,
                                                  int32_t* __restrict__ out_next,
-                                                 int32_t* __restrict__ out_len,
-                                                 int32_t* __restrict__ out_w, int64_t S1) {
+                                                 v2i32* __restrict__ out_lw, int64_t S1) {
   const int64_t j = (int64_t)blockIdx.x * WG + threadIdx.x;
   if (j >= S1) return;
   const int32_t nx = in_next[j];
-  int32_t len = in_len[j], w = in_w[j], nn = nx;
+  // (count, depth sum) of a sample as one 8-byte word: one gather per jump
+  const v2i32 lw = in_lw[j];
+  int32_t len = lw.x, w = lw.y, nn = nx;
   if (len >= 0 && nx >= 0 && nx < S1) {
-    len += in_len[nx];
-    w += in_w[nx];
+    const v2i32 o = in_lw[nx];
+    len += o.x;
+    w += o.y;
     nn = in_next[nx];
   }
   out_next[j] = nn;
-  out_len[j] = len;
-  out_w[j] = w;
+  out_lw[j] = v2i32{len, w};
 }
 
 // Tour position and depth of every arc; the tour's node and depth arrays,
-// first occurrences.  suf_len / suf_w: sums from each sample to the end.
+// first occurrences.  suf: (count, depth sum) from each sample to the end.
 __global__ __launch_bounds__(WG) void k_lca_place(const int32_t* __restrict__ parent, int64_t NA,
                                                   int32_t root, int64_t S,
-                                                  const int32_t* __restrict__ owner,
-                                                  const int32_t* __restrict__ lrank,
-                                                  const int32_t* __restrict__ lw,
-                                                  const int32_t* __restrict__ suf_len,
-                                                  const int32_t* __restrict__ suf_w,
+                                                  const v4i32* __restrict__ arc,
+                                                  const v2i32* __restrict__ suf,
                                                   const int32_t* __restrict__ nxt,
                                                   int32_t* __restrict__ depth,
                                                   int32_t* __restrict__ node,
@@ -214,11 +207,14 @@ __global__ __launch_bounds__(WG) void k_lca_place(const int32_t* __restrict__ pa
     first[root] = 0;
   }
   if (a >= NA || nxt[a] == NOT_ARC) return;
-  const int32_t sid = owner[a];
-  if (sid < 0 || sid > S) return;  // not reached: the host rejects the tour
-  const int64_t total = suf_len[S], total_w = suf_w[S];
-  const int64_t pos = total - suf_len[sid] + lrank[a] + 1;
-  const int64_t d = (total_w - suf_w[sid]) + lw[a] + ((a & 1) ? -1 : 1);
+  // every arc of the list was walked: the host checked the count before
+  // this launch (the sample is still range-checked)
+  const v4i32 x = arc[a];
+  const int32_t sid = x.x;
+  if (sid < 0 || sid > S) return;
+  const v2i32 all = suf[S], mine = suf[sid];
+  const int64_t pos = (int64_t)all.x - mine.x + x.y + 1;
+  const int64_t d = ((int64_t)all.y - mine.y) + x.z + ((a & 1) ? -1 : 1);
   if (pos < 1 || pos > NA - 2) return;
   const int32_t c = (int32_t)(a >> 1);
   depth[pos] = (int32_t)d;
@@ -256,9 +252,9 @@ rmq_status build_tour(const int32_t* parent, int64_t N, int32_t root, rmq_lca_s*
   };
   const size_t o_items = take(8 * (size_t)N), o_sorted = take(8 * (size_t)N),
                o_sort = take(sort_ws), o_fc = take(4 * (size_t)N), o_ns = take(4 * (size_t)N),
-               o_nxt = take(4 * (size_t)NA), o_owner = take(4 * (size_t)NA),
-               o_lrank = take(4 * (size_t)NA), o_lw = take(4 * (size_t)NA),
-               o_s = take(6 * 4 * (size_t)S1), o_stat = take(4 * 8);
+               o_nxt = take(4 * (size_t)NA), o_arc = take(16 * (size_t)NA),
+               o_sa = take(12 * (size_t)S1), o_sb = take(12 * (size_t)S1),
+               o_stat = take(4 * 8);
   void* tmp = nullptr;
   hipError_t e = hipMalloc(&tmp, off);
   if (e != hipSuccess) return status_of(e);
@@ -268,11 +264,16 @@ rmq_status build_tour(const int32_t* parent, int64_t N, int32_t root, rmq_lca_s*
   int32_t* fc = reinterpret_cast<int32_t*>(t + o_fc);
   int32_t* ns = reinterpret_cast<int32_t*>(t + o_ns);
   int32_t* nxt = reinterpret_cast<int32_t*>(t + o_nxt);
-  int32_t* owner = reinterpret_cast<int32_t*>(t + o_owner);
-  int32_t* lrank = reinterpret_cast<int32_t*>(t + o_lrank);
-  int32_t* lw = reinterpret_cast<int32_t*>(t + o_lw);
-  int32_t* sa = reinterpret_cast<int32_t*>(t + o_s);  // next, len, w  x  ping, pong
-  int32_t* sb = sa + 3 * S1;
+  v4i32* arc = reinterpret_cast<v4i32*>(t + o_arc);  // per arc: sample, count, depth sum
+  // per sample, ping and pong: (count, depth sum) pairs, then next samples
+  struct Samples {
+    v2i32* lw;
+    int32_t* next;
+  };
+  const Samples sa{reinterpret_cast<v2i32*>(t + o_sa),
+                   reinterpret_cast<int32_t*>(t + o_sa + 8 * (size_t)S1)};
+  const Samples sb{reinterpret_cast<v2i32*>(t + o_sb),
+                   reinterpret_cast<int32_t*>(t + o_sb + 8 * (size_t)S1)};
   unsigned long long* stat = reinterpret_cast<unsigned long long*>(t + o_stat);
 
   rmq_status st = RMQ_OK;
@@ -294,19 +295,18 @@ rmq_status build_tour(const int32_t* parent, int64_t N, int32_t root, rmq_lca_s*
     }
     RMQ_TRY(launch(k_fill_i32, dim3((unsigned)blocks(N)), dim3(WG), 0, s, fc, N, -1));
     RMQ_TRY(launch(k_fill_i32, dim3((unsigned)blocks(N)), dim3(WG), 0, s, ns, N, -1));
-    RMQ_TRY(launch(k_fill_i32, dim3((unsigned)blocks(NA)), dim3(WG), 0, s, owner, NA, -1));
     RMQ_TRY(launch(k_lca_links, dim3((unsigned)blocks(N)), dim3(WG), 0, s, sorted, N, fc, ns));
     RMQ_TRY(launch(k_lca_next, dim3((unsigned)blocks(N)), dim3(WG), 0, s, parent, N, root, fc, ns,
                    nxt));
     RMQ_TRY(launch(k_lca_walk, dim3((unsigned)blocks(S1)), dim3(WG), 0, s, nxt, NA, fc, root, S,
-                   owner, lrank, lw, sa, sa + S1, sa + 2 * S1, stat));
+                   arc, sa.next, sa.lw, stat));
     int rounds = 1;
     while ((1ll << rounds) < S1) ++rounds;
-    int32_t *in = sa, *outb = sb;
+    Samples in = sa, outb = sb;
     for (int r = 0; r <= rounds; ++r) {
-      RMQ_TRY(launch(k_lca_jump, dim3((unsigned)blocks(S1)), dim3(WG), 0, s, in, in + S1,
-                     in + 2 * S1, outb, outb + S1, outb + 2 * S1, S1));
-      int32_t* x = in;
+      RMQ_TRY(launch(k_lca_jump, dim3((unsigned)blocks(S1)), dim3(WG), 0, s, in.next,
+                     static_cast<const v2i32*>(in.lw), outb.next, outb.lw, S1));
+      const Samples x = in;
       in = outb;
       outb = x;
     }
@@ -314,8 +314,8 @@ rmq_status build_tour(const int32_t* parent, int64_t N, int32_t root, rmq_lca_s*
     // end, the walks cover 2(N - 1) arcs and the head's sum is 2(N - 1)
     int32_t head_next = 0, head_len = 0;
     unsigned long long h_stat[2] = {0, 0};
-    RMQ_TRY(hipMemcpyAsync(&head_next, in + S, 4, hipMemcpyDeviceToHost, s));
-    RMQ_TRY(hipMemcpyAsync(&head_len, in + S1 + S, 4, hipMemcpyDeviceToHost, s));
+    RMQ_TRY(hipMemcpyAsync(&head_next, in.next + S, 4, hipMemcpyDeviceToHost, s));
+    RMQ_TRY(hipMemcpyAsync(&head_len, in.lw + S, 4, hipMemcpyDeviceToHost, s));  // its count
     RMQ_TRY(hipMemcpyAsync(h_stat, stat, 16, hipMemcpyDeviceToHost, s));
     RMQ_TRY(hipStreamSynchronize(s));
     if (head_next != END || h_stat[1] != 0 || (int64_t)h_stat[0] != NA - 2 ||
@@ -324,7 +324,7 @@ rmq_status build_tour(const int32_t* parent, int64_t N, int32_t root, rmq_lca_s*
       return hipSuccess;
     }
     RMQ_TRY(launch(k_lca_place, dim3((unsigned)blocks(NA)), dim3(WG), 0, s, parent, NA, root, S,
-                   owner, lrank, lw, in + S1, in + 2 * S1, nxt, h->depth, h->node, h->first));
+                   arc, static_cast<const v2i32*>(in.lw), nxt, h->depth, h->node, h->first));
     return hipStreamSynchronize(s);
   };
   e = run();
