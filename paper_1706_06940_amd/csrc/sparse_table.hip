@@ -21,6 +21,9 @@ namespace rmq {
 namespace {
 
 constexpr int WG = 256;
+// The doubling rounds' workgroups: 8 waves, so that a small table's one or
+// two tiles still spread their per-level LDS work over every SIMD of a CU.
+constexpr int STWG = 512;
 constexpr int TILE = 1024;  // outputs per workgroup per level (R * TI)
 
 struct RoundShape {
@@ -68,11 +71,11 @@ __device__ __forceinline__ void st_tile(uint64_t* __restrict__ st, int64_t nb, i
 
   // all loads first (rows * R <= 2 * TILE entries, at most LOADS per
   // thread), so that they are in flight together
-  constexpr int LOADS = 2 * TILE / WG;
+  constexpr int LOADS = 2 * TILE / STWG;
   uint64_t v[LOADS];
 #pragma unroll
   for (int u = 0; u < LOADS; ++u) {
-    const int idx = threadIdx.x + u * WG;
+    const int idx = threadIdx.x + u * STWG;
     const int row = idx >> rs, c = idx & (R - 1);
     const int64_t r = r0 + c;
     const int64_t b = ((i0 + row) << j0) + r;
@@ -82,7 +85,7 @@ __device__ __forceinline__ void st_tile(uint64_t* __restrict__ st, int64_t nb, i
   }
 #pragma unroll
   for (int u = 0; u < LOADS; ++u) {
-    const int idx = threadIdx.x + u * WG;
+    const int idx = threadIdx.x + u * STWG;
     if (idx < rows * R) buf0[idx] = v[u];
   }
   __syncthreads();
@@ -97,12 +100,12 @@ __device__ __forceinline__ void st_tile(uint64_t* __restrict__ st, int64_t nb, i
     uint64_t w[LOADS];
 #pragma unroll
     for (int u = 0; u < LOADS; ++u) {
-      const int idx = threadIdx.x + u * WG;
+      const int idx = threadIdx.x + u * STWG;
       if (idx < rows_m * R) w[u] = umin64(cur[idx], cur[idx + half * R]);
     }
 #pragma unroll
     for (int u = 0; u < LOADS; ++u) {
-      const int idx = threadIdx.x + u * WG;
+      const int idx = threadIdx.x + u * STWG;
       if (idx < rows_m * R) {
         nxt[idx] = w[u];
         const int row = idx >> rs, c = idx & (R - 1);
@@ -120,7 +123,7 @@ __device__ __forceinline__ void st_tile(uint64_t* __restrict__ st, int64_t nb, i
   }
 }
 
-__global__ __launch_bounds__(WG) void k_st_levels(uint64_t* __restrict__ st, int64_t nb, int j0,
+__global__ __launch_bounds__(STWG) void k_st_levels(uint64_t* __restrict__ st, int64_t nb, int j0,
                                                   int t, int R, int64_t col_tiles) {
   extern __shared__ uint64_t lds[];
   st_tile(st, nb, j0, t, R, col_tiles, blockIdx.x, lds);
@@ -128,7 +131,7 @@ __global__ __launch_bounds__(WG) void k_st_levels(uint64_t* __restrict__ st, int
 
 // Round `round` of every table of a batch: workgroup w does job w, one
 // tile of one table.
-__global__ __launch_bounds__(WG) void k_st_multi(const TileJob* __restrict__ jobs, int j0, int R,
+__global__ __launch_bounds__(STWG) void k_st_multi(const TileJob* __restrict__ jobs, int j0, int R,
                                                  int tmax) {
   extern __shared__ uint64_t lds[];
   const TileJob jb = jobs[blockIdx.x];
@@ -317,7 +320,7 @@ hipError_t launch_sparse_table(uint64_t* st, int64_t nb, int levels, hipStream_t
     const int64_t col_tiles = (s + sh.R - 1) / sh.R;
     const int64_t grid = st_round_tiles(nb, levels, r);
     const size_t lds = 2ull * (size_t)(sh.TI + (1 << t) - 1) * sh.R * sizeof(uint64_t);
-    RMQ_TRY(launch(k_st_levels, dim3((unsigned)grid), dim3(WG), (uint32_t)lds, stream, st, nb,
+    RMQ_TRY(launch(k_st_levels, dim3((unsigned)grid), dim3(STWG), (uint32_t)lds, stream, st, nb,
                    sh.j0, t, sh.R, col_tiles));
   }
   return hipSuccess;
@@ -327,7 +330,7 @@ hipError_t launch_sparse_table_multi(const TileJob* jobs, int round, int64_t cou
                                      hipStream_t stream) {
   if (count <= 0) return hipSuccess;
   const RoundShape sh = round_shape(round);
-  RMQ_TRY(launch(k_st_multi, dim3((unsigned)count), dim3(WG), (uint32_t)st_round_lds(round),
+  RMQ_TRY(launch(k_st_multi, dim3((unsigned)count), dim3(STWG), (uint32_t)st_round_lds(round),
                  stream, jobs, sh.j0, sh.R, sh.tmax));
   return hipSuccess;
 }
