@@ -21,9 +21,9 @@ namespace rmq {
 namespace {
 
 constexpr int WG = 256;
-// The doubling rounds' workgroups: 8 waves, so that a small table's one or
+// The doubling rounds' workgroups: 16 waves, so that a small table's one or
 // two tiles still spread their per-level LDS work over every SIMD of a CU.
-constexpr int STWG = 512;
+constexpr int STWG = 1024;
 constexpr int TILE = 1024;  // outputs per workgroup per level (R * TI)
 
 struct RoundShape {
