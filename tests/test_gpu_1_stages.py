@@ -114,8 +114,12 @@ def test_sort_endpoints_invalid_queries_sort_as_zero(orc):
     assert np.array_equal(host(pos), ep) and np.array_equal(host(tag), et)
 
 
+# the last rows leave most waves of the contraction without endpoints, the
+# first of them with a last wave shorter than the others and the second with
+# a partial last tile
 @pytest.mark.parametrize("n,q", [(1, 1), (10, 7), (1000, 3), (5000, 300), (1 << 20, 1024),
-                                 (1_000_003, 40_000), (3000, 20_000)])
+                                 (1_000_003, 40_000), (3000, 20_000), (1021 * 1024, 5),
+                                 (3_000_017, 6), (1 << 22, 2)])
 def test_contract(orc, n, q):
     d = need_gpu()
     say("contract", n, q)
