@@ -14,9 +14,9 @@
 //   j that is the first in its tile -- that area reaches into the tile from
 //   an earlier one, so it may be finished by atomicMin from several waves.
 // k_contract (one streaming pass over A): each wave walks a run of up to 63
-//   consecutive tiles, the next tile's values and first endpoints in flight while it
-//   works on the current one, and carries the area that is still open at a
-//   tile's end into the next tile (no barrier: waves share nothing).
+//   consecutive tiles, the next tile's values and first endpoints in flight
+//   while it works on the current one, and carries the area that is still
+//   open at a tile's end into the next tile (no barrier: waves share nothing).
 //   * a tile without endpoints lies inside the open area: each lane keeps
 //     its min over a run of such tiles (32-bit compares, leftmost on ties),
 //     and the wave's min over the run joins the carried value when the run
@@ -138,9 +138,10 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Tiles per wave: at least 8 (2 or 4 were slower at every density) and at
-// most 63 (a lane per tile of the wave holds its table entry).  Between the
-// two, whole rounds of waves share the tiles evenly.
+// Tiles per wave: about 8 where less than one round of waves covers A (2 or
+// 4 were slower at every density), at most 63 (a lane per tile of the wave
+// holds its table entry); in between, whole rounds of waves share the tiles
+// evenly.
 constexpr int TPW_MIN = 8, TPW_MAX = 63, WAVES_PER_SIMD = 5;
 constexpr int KREG = 4;  // endpoint slots per lane of a tile held in registers (256 a tile)
 
@@ -422,12 +423,12 @@ hipError_t launch_contract(const int32_t* A, int64_t n, const int32_t* E, int64_
   else
     RMQ_TRY(launch(k_tiles_search, dim3((unsigned)((num_tiles + 1 + WG - 1) / WG)), dim3(WG), 0,
                    stream, E, M, aq, tile_start, num_tiles, fail));
-  // 8 tiles per wave while that takes less than one round of waves, else
-  // the fewest whole rounds with at most 63 tiles per wave; the tiles are
-  // shared evenly, so that every SIMD of a round has the same load.  A round
-  // is 5 waves per SIMD, or 4 where the list has at most one endpoint per
-  // tile (n = 1e8: 64.3 against 66.8 us at 2e3 endpoints, while 4e7
-  // endpoints took 224 against 204 us)
+  // 8 tiles per wave (7 or 8, shared evenly) while that takes less than one
+  // round of waves, else the fewest whole rounds with at most 63 tiles per
+  // wave, the tiles shared evenly so that every SIMD of a round has the same
+  // load.  A round is 5 waves per SIMD, or 4 where the list has at most one
+  // endpoint per tile (n = 1e8: 64.3 against 66.8 us at 2e3 endpoints, while
+  // 4e7 endpoints took 224 against 204 us)
   const int round_waves = M <= num_tiles ? 4 : WAVES_PER_SIMD;
   const int64_t slots = (int64_t)device_cu_count() * 4 * round_waves;
   const int64_t waves = num_tiles <= slots * TPW_MIN
